@@ -1,0 +1,162 @@
+"""FP64 CPU oracle for the batched small dense linear algebra path.
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU
+baseline leg of the benchmark are the only callers.  The product library never
+imports, links or calls anything in this directory, and this directory uses
+nothing from the product library.
+
+Each function takes numpy arrays (any float dtype; promoted exactly to float64)
+in the row-major batch-contiguous layout X[batch][rows][cols] and returns new
+float64 arrays; inputs are never modified.  The arithmetic lives in
+``glass_oracle.c`` (plain loops, FP64, no BLAS/LAPACK) and is reached through
+ctypes.  What each function computes is stated beside it in the C source,
+with the paper section it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "glass_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_CFLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11"]
+
+
+def build(force: bool = True) -> str:
+    """Compile glass_oracle.c into liboracle.so with gcc; returns the path."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *_CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        d = ctypes.c_double
+        i = ctypes.c_int
+        p = ctypes.c_void_p
+        sig = {
+            "oracle_gemm": [i, i, i, i, d, p, p, d, p],
+            "oracle_gemv": [i, i, i, d, p, p, d, p],
+            "oracle_potrf": [i, i, p, p],
+            "oracle_potrs": [i, i, i, p, p],
+            "oracle_posv": [i, i, i, p, p, p],
+            "oracle_trsv": [i, i, i, p, p],
+            "oracle_se3_compose": [i, p, p, p],
+            "oracle_se3_inverse": [i, p, p],
+            "oracle_num_threads": [],
+            "oracle_set_num_threads": [i],
+        }
+        for name, args in sig.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int if name == "oracle_num_threads" else None
+        _lib = lib
+    return _lib
+
+
+def _f64(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def num_threads() -> int:
+    return _load().oracle_num_threads()
+
+
+def set_num_threads(t: int) -> None:
+    _load().oracle_set_num_threads(int(t))
+
+
+def gemm(A, B, C=None, alpha: float = 1.0, beta: float = 0.0) -> np.ndarray:
+    """C = alpha A B + beta C for A [b,m,k], B [b,k,n] (C [b,m,n] read iff beta != 0)."""
+    A = _f64(A)
+    B = _f64(B)
+    b, m, k = A.shape
+    n = B.shape[2]
+    assert B.shape == (b, k, n)
+    out = np.zeros((b, m, n)) if C is None else _f64(C).copy()
+    _load().oracle_gemm(m, n, k, b, float(alpha), _ptr(A), _ptr(B), float(beta), _ptr(out))
+    return out
+
+
+def gemv(A, x, y=None, alpha: float = 1.0, beta: float = 0.0) -> np.ndarray:
+    """y = alpha A x + beta y for A [b,m,n], x [b,n] (y [b,m] read iff beta != 0)."""
+    A = _f64(A)
+    x = _f64(x)
+    b, m, n = A.shape
+    out = np.zeros((b, m)) if y is None else _f64(y).reshape(b, m).copy()
+    _load().oracle_gemv(m, n, b, float(alpha), _ptr(A), _ptr(x.reshape(b, n)), float(beta), _ptr(out))
+    return out
+
+
+def potrf(A):
+    """Lower Cholesky of SPD A [b,n,n]; returns (L with +0 strict upper, info int32 [b])."""
+    L = _f64(A).copy()
+    b, n, _ = L.shape
+    info = np.zeros(b, dtype=np.int32)
+    _load().oracle_potrf(n, b, _ptr(L), _ptr(info))
+    return L, info
+
+
+def potrs(L, B):
+    """X = (L L^T)^{-1} B for L [b,n,n] (lower read), B [b,n,r]."""
+    L = _f64(L)
+    X = _f64(B).copy()
+    b, n, r = X.shape
+    _load().oracle_potrs(n, r, b, _ptr(L), _ptr(X))
+    return X
+
+
+def posv(A, B):
+    """Factor-and-solve; returns (L, X, info).  X unspecified where info != 0."""
+    L = _f64(A).copy()
+    X = _f64(B).copy()
+    b, n, r = X.shape
+    info = np.zeros(b, dtype=np.int32)
+    _load().oracle_posv(n, r, b, _ptr(L), _ptr(X), _ptr(info))
+    return L, X, info
+
+
+def trsv(L, x, trans: int = 0):
+    """Solve L x = b (trans=0) or L^T x = b (trans=1); L [b,n,n] lower, x [b,n]."""
+    L = _f64(L)
+    b, n, _ = L.shape
+    X = _f64(x).reshape(b, n).copy()
+    _load().oracle_trsv(n, b, int(trans), _ptr(L), _ptr(X))
+    return X
+
+
+def se3_compose(Ta, Tb):
+    """T = Ta Tb for homogeneous transforms [b,4,4] (row 3 written as 0 0 0 1)."""
+    Ta = _f64(Ta)
+    Tb = _f64(Tb)
+    b = Ta.shape[0]
+    out = np.empty((b, 4, 4))
+    _load().oracle_se3_compose(b, _ptr(Ta), _ptr(Tb), _ptr(out))
+    return out
+
+
+def se3_inverse(Ta):
+    """Closed-form rigid-motion inverse [R^T, -R^T t; 0 0 0 1] of Ta [b,4,4]."""
+    Ta = _f64(Ta)
+    b = Ta.shape[0]
+    out = np.empty((b, 4, 4))
+    _load().oracle_se3_inverse(b, _ptr(Ta), _ptr(out))
+    return out

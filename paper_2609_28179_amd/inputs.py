@@ -1,0 +1,180 @@
+"""Seeded synthetic inputs shaped like the paper's robotics-scale workloads.
+
+This module only draws random numbers and assembles well-posed problem
+instances (SPD matrices, well-conditioned triangles, rigid transforms).  It
+holds none of the batched operations themselves and is shared, unchanged, by
+the tests, the benchmark and the tuner; nothing here calls the GPU library or
+the oracle.
+
+Recipes (the paper states no input distribution, Sec. IV-A only asks for a
+fresh valid input per launch of a destructive op):
+  general matrices / vectors : iid uniform[-1, 1]
+  SPD matrices               : A = M M^T + n I, M iid uniform[-1, 1], formed in
+                               float64, lower triangle mirrored into the upper
+                               (exact symmetry), rounded to float32
+  triangular factors          : the float64 Cholesky factor of such an A
+                               (LAPACK, through numpy), rounded to float32; a
+                               random uniform triangle would have condition
+                               numbers near 1e19 at n = 64
+  SE(3) transforms            : R from a Hamilton unit quaternion (w, x, y, z)
+                               q = normalize(N(0, 1)^4) (uniform on S^3),
+                               t iid uniform[-1, 1]^3, last row (0, 0, 0, 1)
+
+Seeding: ``numpy.random.default_rng(SeedSequence([cfg, op_id, n, batch]))``
+for the host generators; the ``*_torch`` variants draw the same recipes from a
+seeded ``torch.Generator`` on the target device (used for the multi-GB
+benchmark inputs, which are too large to draw on the host).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+OP_IDS = {
+    "gemm": 0, "gemv": 1, "potrf": 2, "potrs": 3, "posv": 4, "trsv": 5,
+    "se3_compose": 6, "se3_inverse": 7, "adjoint": 8, "ragged": 9, "riccati": 10,
+}
+
+
+def rng_for(cfg: int, op: str, n: int, batch: int, extra: int = 0) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([cfg, OP_IDS[op], n, batch, extra]))
+
+
+def uniform(rng: np.random.Generator, shape) -> np.ndarray:
+    return rng.uniform(-1.0, 1.0, size=shape).astype(np.float32)
+
+
+def spd64(rng: np.random.Generator, batch: int, n: int) -> np.ndarray:
+    """float64 A = M M^T + n I (exactly symmetric), before rounding."""
+    M = rng.uniform(-1.0, 1.0, size=(batch, n, n))
+    A = np.matmul(M, np.swapaxes(M, 1, 2))
+    A += n * np.eye(n)[None]
+    il = np.tril_indices(n, -1)
+    A[:, il[1], il[0]] = A[:, il[0], il[1]]
+    return A
+
+
+def spd(rng: np.random.Generator, batch: int, n: int) -> np.ndarray:
+    return spd64(rng, batch, n).astype(np.float32)
+
+
+def lower_factor(rng: np.random.Generator, batch: int, n: int) -> np.ndarray:
+    """Well-conditioned lower triangle with zero strict upper part (float32)."""
+    A = spd64(rng, batch, n)
+    L = np.linalg.cholesky(A)
+    return np.tril(L).astype(np.float32)
+
+
+def rotations64(rng: np.random.Generator, batch: int) -> np.ndarray:
+    q = rng.standard_normal(size=(batch, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
+    R = np.empty((batch, 3, 3))
+    R[:, 0, 0] = 1 - 2 * (y * y + z * z)
+    R[:, 0, 1] = 2 * (x * y - w * z)
+    R[:, 0, 2] = 2 * (x * z + w * y)
+    R[:, 1, 0] = 2 * (x * y + w * z)
+    R[:, 1, 1] = 1 - 2 * (x * x + z * z)
+    R[:, 1, 2] = 2 * (y * z - w * x)
+    R[:, 2, 0] = 2 * (x * z - w * y)
+    R[:, 2, 1] = 2 * (y * z + w * x)
+    R[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return R
+
+
+def se3(rng: np.random.Generator, batch: int) -> np.ndarray:
+    T = np.zeros((batch, 4, 4))
+    T[:, :3, :3] = rotations64(rng, batch)
+    T[:, :3, 3] = rng.uniform(-1.0, 1.0, size=(batch, 3))
+    T[:, 3, 3] = 1.0
+    return T.astype(np.float32)
+
+
+# ---------------------------------------------------------------- problem sets
+def make_case(op: str, n: int, batch: int, cfg: int = 1, nrhs: int = 1, extra: int = 0) -> dict:
+    """Inputs of one (op, n, batch) cell as float32 numpy arrays."""
+    rng = rng_for(cfg, op, n, batch, extra)
+    if op == "gemm":
+        return {"A": uniform(rng, (batch, n, n)), "B": uniform(rng, (batch, n, n))}
+    if op == "gemv":
+        return {"A": uniform(rng, (batch, n, n)), "x": uniform(rng, (batch, n))}
+    if op == "potrf":
+        return {"A": spd(rng, batch, n)}
+    if op == "posv":
+        A = spd(rng, batch, n)
+        return {"A": A, "B": uniform(rng, (batch, n, nrhs))}
+    if op == "potrs":
+        L = lower_factor(rng, batch, n)
+        return {"L": L, "B": uniform(rng, (batch, n, nrhs))}
+    if op == "trsv":
+        L = lower_factor(rng, batch, n)
+        return {"L": L, "x": uniform(rng, (batch, n))}
+    if op == "se3_compose":
+        return {"Ta": se3(rng, batch), "Tb": se3(rng, batch)}
+    if op == "se3_inverse":
+        return {"Ta": se3(rng, batch)}
+    raise ValueError(op)
+
+
+# ------------------------------------------------------- device-side variants
+def _torch():
+    import torch
+    return torch
+
+
+def torch_generator(device, seed: int):
+    torch = _torch()
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    return g
+
+
+def uniform_torch(g, shape, device):
+    torch = _torch()
+    return torch.rand(shape, generator=g, device=device, dtype=torch.float32) * 2.0 - 1.0
+
+
+def spd_torch(g, batch: int, n: int, device, chunk: int = 16384):
+    """Same recipe as ``spd`` drawn on ``device``: float64 M M^T + n I, mirrored, float32."""
+    torch = _torch()
+    out = torch.empty((batch, n, n), dtype=torch.float32, device=device)
+    eye = torch.eye(n, dtype=torch.float64, device=device)
+    for s in range(0, batch, chunk):
+        e = min(batch, s + chunk)
+        M = torch.rand((e - s, n, n), generator=g, device=device, dtype=torch.float64) * 2.0 - 1.0
+        A = torch.matmul(M, M.transpose(1, 2).contiguous()) + n * eye
+        A = torch.tril(A) + torch.tril(A, -1).transpose(1, 2)
+        out[s:e] = A.to(torch.float32)
+    return out
+
+
+def lower_factor_torch(g, batch: int, n: int, device, chunk: int = 16384):
+    torch = _torch()
+    out = torch.empty((batch, n, n), dtype=torch.float32, device=device)
+    eye = torch.eye(n, dtype=torch.float64, device=device)
+    for s in range(0, batch, chunk):
+        e = min(batch, s + chunk)
+        M = torch.rand((e - s, n, n), generator=g, device=device, dtype=torch.float64) * 2.0 - 1.0
+        A = torch.matmul(M, M.transpose(1, 2).contiguous()) + n * eye
+        A = torch.tril(A) + torch.tril(A, -1).transpose(1, 2)
+        out[s:e] = torch.tril(torch.linalg.cholesky(A)).to(torch.float32)
+    return out
+
+
+def se3_torch(g, batch: int, device):
+    torch = _torch()
+    q = torch.randn((batch, 4), generator=g, device=device, dtype=torch.float64)
+    q = q / q.norm(dim=1, keepdim=True)
+    w, x, y, z = q.unbind(1)
+    T = torch.zeros((batch, 4, 4), dtype=torch.float64, device=device)
+    T[:, 0, 0] = 1 - 2 * (y * y + z * z)
+    T[:, 0, 1] = 2 * (x * y - w * z)
+    T[:, 0, 2] = 2 * (x * z + w * y)
+    T[:, 1, 0] = 2 * (x * y + w * z)
+    T[:, 1, 1] = 1 - 2 * (x * x + z * z)
+    T[:, 1, 2] = 2 * (y * z - w * x)
+    T[:, 2, 0] = 2 * (x * z - w * y)
+    T[:, 2, 1] = 2 * (y * z + w * x)
+    T[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    T[:, :3, 3] = torch.rand((batch, 3), generator=g, device=device, dtype=torch.float64) * 2.0 - 1.0
+    T[:, 3, 3] = 1.0
+    return T.to(torch.float32)
