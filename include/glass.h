@@ -1,0 +1,179 @@
+/*
+ * glass.h -- C-ABI of the MI355X (gfx950) batched small dense linear algebra
+ * library: GEMM, GEMV, Cholesky factor / solve, triangular solve and SE(3)
+ * compose / inverse at robotics sizes (n <= 64), each with thread-,
+ * wavefront- and workgroup-scoped kernels and a measured placement table.
+ *
+ * Method: GLASS (Sec. III).  Sec. III-A defines the three execution scopes
+ * (one problem per thread, per wave -- a 32-lane warp in the paper, a 64-lane
+ * wavefront here -- or per block/workgroup), the offline-measured placement
+ * table, the bare call that consults it and the advisor that reports it;
+ * Sec. III-B lists the operations; Sec. IV-C calls launch packing (problems
+ * per workgroup) part of a placement.
+ *
+ * Common contract of every batched call
+ *   - Data: FP32, row-major, batch-contiguous: X[batch][rows][cols], no
+ *     leading-dimension argument, no padding between problems.
+ *   - Pointers: DEVICE pointers, 4-byte aligned, owned by the caller; the
+ *     library allocates nothing and keeps no per-call state.  16-byte aligned
+ *     pointers enable wider loads but are not required.
+ *   - Sizes: 1 <= n, m, k, nrhs <= 64 (else GLASS_ERR_UNSUPPORTED);
+ *     batch == 0 is a no-op returning GLASS_OK; batch < 0 or a required
+ *     pointer that is NULL while batch > 0 -> GLASS_ERR_INVALID_VALUE.
+ *   - All argument errors are detected on the host before anything is
+ *     enqueued: on error nothing runs.
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = the default
+ *     stream).  A failed launch returns GLASS_ERR_LAUNCH.
+ *   - Numerical failure is never a return code: factorizations report it per
+ *     problem in info[] (LAPACK convention, see glass_potrf_batched).
+ *   - Placement: `force == NULL` looks the call up in the built-in gfx950
+ *     table (the paper's bare call); if the tabulated placement is infeasible
+ *     for this exact call (e.g. nrhs or a rectangular GEMM exceeds what that
+ *     scope supports) the call falls back to wavefront scope, pack 1, which is
+ *     feasible for every supported shape.  `force != NULL` runs exactly that
+ *     placement (only its `scope` and `pack` fields are read) or returns
+ *     GLASS_ERR_INFEASIBLE_PLACEMENT without enqueuing anything.
+ *   - Thread safety: stateless apart from a per-process, read-only device
+ *     property cache; calls may be made concurrently from several threads.
+ */
+#ifndef GLASS_H_
+#define GLASS_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GLASS_OK = 0,
+    GLASS_ERR_INVALID_VALUE = -1,        /* bad pointer / negative batch / bad enum  */
+    GLASS_ERR_UNSUPPORTED = -2,          /* size outside 1..64                       */
+    GLASS_ERR_INFEASIBLE_PLACEMENT = -3, /* forced placement cannot run this shape   */
+    GLASS_ERR_LAUNCH = -4                /* the HIP runtime rejected the launch      */
+} glass_status_t;
+
+typedef enum {
+    GLASS_OP_GEMM = 0,
+    GLASS_OP_GEMV = 1,
+    GLASS_OP_POTRF = 2,
+    GLASS_OP_POTRS = 3,
+    GLASS_OP_POSV = 4,
+    GLASS_OP_TRSV = 5,
+    GLASS_OP_SE3_COMPOSE = 6,
+    GLASS_OP_SE3_INVERSE = 7
+} glass_op_t;
+
+/* Execution scope (Sec. III-A). */
+typedef enum {
+    GLASS_SCOPE_THREAD = 0,    /* one problem per lane                       */
+    GLASS_SCOPE_WAVE = 1,      /* one problem per 64-lane wavefront          */
+    GLASS_SCOPE_WORKGROUP = 2  /* one problem per workgroup at a time        */
+} glass_scope_t;
+
+/* A placement (Sec. III-A, Sec. IV-C).  `pack` P in {1,2,4,8} counts the
+ * scope's unit per workgroup:
+ *   thread    : workgroup of 64P lanes, 64P problems per workgroup;
+ *   wave      : workgroup of P wavefronts, P problems (one per wavefront);
+ *   workgroup : workgroup of T(n) = 64*min(4, ceil(n/16)) lanes that solves
+ *               P problems one after the other.
+ * wg_threads and problems_per_wg are outputs (what a launch uses); as input
+ * only scope and pack are read. */
+typedef struct {
+    int32_t scope;
+    int32_t pack;
+    int32_t wg_threads;
+    int32_t problems_per_wg;
+} glass_placement_t;
+
+/* C = alpha * A B + beta * C  (Sec. III-B, BLAS L3).
+ * A [batch][m][k], B [batch][k][n], C [batch][m][n].  beta == 0: C is not
+ * read (NaN in C does not propagate).  C must not overlap A or B.
+ * Thread scope requires m == n == k <= 12; wave and workgroup scope use FP32
+ * MFMA (v_mfma_f32_16x16x4_f32) when max(m, n, k) >= 16. */
+glass_status_t glass_gemm_batched(int m, int n, int k, int batch, float alpha,
+                                  const float* A, const float* B, float beta,
+                                  float* C, const glass_placement_t* force,
+                                  void* stream);
+
+/* y = alpha * A x + beta * y  (Sec. III-B, BLAS L2).
+ * A [batch][m][n], x [batch][n], y [batch][m]; beta == 0: y is not read.
+ * y must not overlap A or x.  Thread scope requires m == n <= 16. */
+glass_status_t glass_gemv_batched(int m, int n, int batch, float alpha,
+                                  const float* A, const float* x, float beta,
+                                  float* y, const glass_placement_t* force,
+                                  void* stream);
+
+/* Lower Cholesky factorization A = L L^T, in place  (Sec. III-B).
+ * A [batch][n][n]: only the lower triangle (i >= j) is read; on return it
+ * holds L and the strict upper triangle holds +0.0.
+ * info [batch] (device int32, may be NULL): 0 on success, otherwise j+1 for
+ * the first column j whose pivot A_jj - sum_k L_jk^2 is not > 0 (zero,
+ * negative or NaN); columns >= j of that problem are then unspecified. */
+glass_status_t glass_potrf_batched(int n, int batch, float* A, int32_t* info,
+                                   const glass_placement_t* force, void* stream);
+
+/* Solve A X = B with a given Cholesky factor, in place  (Sec. III-B).
+ * L [batch][n][n] (lower triangle read, non-unit diagonal),
+ * B [batch][n][nrhs]: right-hand sides on entry, X = (L L^T)^{-1} B on exit.
+ * B must not overlap L. */
+glass_status_t glass_potrs_batched(int n, int nrhs, int batch, const float* L,
+                                   float* B, const glass_placement_t* force,
+                                   void* stream);
+
+/* Factor and solve in one kernel (POSV; Sec. III-A's example call).
+ * A is overwritten by L exactly as glass_potrf_batched does, B by the
+ * solution; info as for glass_potrf_batched (may be NULL).  Where
+ * info[b] != 0 the contents of B[b] are unspecified. */
+glass_status_t glass_posv_batched(int n, int nrhs, int batch, float* A,
+                                  float* B, int32_t* info,
+                                  const glass_placement_t* force, void* stream);
+
+/* Triangular solve, in place  (Sec. III-B).
+ * L [batch][n][n] lower triangle read, non-unit diagonal; x [batch][n] holds
+ * b on entry and the solution on exit.  trans = 0: L x = b; trans = 1:
+ * L^T x = b; any other value -> GLASS_ERR_INVALID_VALUE. */
+glass_status_t glass_trsv_batched(int n, int batch, int trans, const float* L,
+                                  float* x, const glass_placement_t* force,
+                                  void* stream);
+
+/* SE(3) homogeneous transforms  (Sec. III-B).  Each problem is a 4x4
+ * row-major [R t; 0 0 0 1]; row 3 of an input is never read and row 3 of
+ * the output is written as exactly (0, 0, 0, 1).
+ * op = GLASS_OP_SE3_COMPOSE: Tout = Ta Tb (R = Ra Rb, t = Ra tb + ta);
+ * op = GLASS_OP_SE3_INVERSE: Tout = [Ra^T, -Ra^T ta] (closed form for a
+ * rigid motion; Tb is ignored and may be NULL).  Tout may be exactly Ta or
+ * Tb (every problem is fully read before it is written); partial overlap is
+ * undefined. */
+glass_status_t glass_se3_batched(glass_op_t op, int batch, const float* Ta,
+                                 const float* Tb, float* Tout,
+                                 const glass_placement_t* force, void* stream);
+
+/* The advisor (Sec. III-A): the placement the built-in table gives for
+ * (op, n, batch), written to *out (HOST pointer).  Lookup rule: n_key = the
+ * smallest tabulated n >= n (n <= 2 maps to the smallest key); batch_key =
+ * the tabulated batch nearest in |log2| distance, ties to the smaller; the
+ * SE(3) ops ignore n.  n outside 1..64 -> GLASS_ERR_UNSUPPORTED; batch < 1
+ * or out == NULL -> GLASS_ERR_INVALID_VALUE.  For GEMM pass n = max(m,n,k). */
+glass_status_t glass_query_placement(glass_op_t op, int n, int batch,
+                                     glass_placement_t* out);
+
+/* Whether placement (scope, pack) can run a square problem of order n with
+ * nrhs right-hand sides (POTRS/POSV; ignored elsewhere).  Returns 1 if
+ * feasible, 0 if not, GLASS_ERR_* for bad arguments.  The rule is
+ * deterministic and device-independent (a fixed 64 KiB LDS budget per
+ * workgroup and per-scope register limits), mirroring Sec. III-A's rule that
+ * a body is instantiated only where its size and resources fit. */
+int glass_placement_feasible(glass_op_t op, int n, int nrhs, int scope, int pack);
+
+/* Provenance string of the built-in table ("gfx950 / ... / sweep ..."). */
+const char* glass_table_provenance(void);
+
+/* Human-readable name of a status code (static storage). */
+const char* glass_status_string(glass_status_t s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GLASS_H_ */

@@ -1,0 +1,222 @@
+// api.cpp -- the C-ABI of include/glass.h: host-side argument validation,
+// placement resolution (static table, advisor, forced placement) and dispatch
+// to the kernel launchers.  Everything before the launch is plain host code
+// that touches no HIP API, so every error path runs without a device.
+#include <math.h>
+
+#include "glass_internal.hpp"
+
+namespace glass {
+namespace {
+
+#include "glass_table_gfx950.inc"
+
+constexpr int kNumN = sizeof(kTableN) / sizeof(kTableN[0]);
+constexpr int kNumB = sizeof(kTableB) / sizeof(kTableB[0]);
+
+inline bool is_se3(glass_op_t op) { return op == GLASS_OP_SE3_COMPOSE || op == GLASS_OP_SE3_INVERSE; }
+inline bool size_ok(int v) { return v >= 1 && v <= kMaxN; }
+
+// Smallest tabulated n >= n (n below the first key maps to the first key).
+int n_index(int n) {
+    for (int i = 0; i < kNumN; ++i)
+        if (kTableN[i] >= n) return i;
+    return kNumN - 1;
+}
+
+// Tabulated batch nearest to `batch` in |log2| distance, ties to the smaller:
+// between consecutive keys k1 < b < k2, b is nearer k1 iff b*b <= k1*k2.
+int b_index(long long batch) {
+    if (batch <= kTableB[0]) return 0;
+    for (int i = 0; i + 1 < kNumB; ++i) {
+        const long long k1 = kTableB[i], k2 = kTableB[i + 1];
+        if (batch == k1) return i;
+        if (batch < k2) return batch * batch <= k1 * k2 ? i : i + 1;
+    }
+    return kNumB - 1;
+}
+
+void table_lookup(glass_op_t op, int n, long long batch, int* scope, int* pack) {
+    const int ni = is_se3(op) ? 0 : n_index(n);
+    const int bi = b_index(batch);
+    *scope = kPlace[(int)op][ni][bi][0];
+    *pack = kPlace[(int)op][ni][bi][1];
+}
+
+bool valid_force(const glass_placement_t* f) {
+    if (!f) return true;
+    if (f->scope < GLASS_SCOPE_THREAD || f->scope > GLASS_SCOPE_WORKGROUP) return false;
+    return f->pack == 1 || f->pack == 2 || f->pack == 4 || f->pack == 8;
+}
+
+// Resolve the placement of a validated call: forced, else table, else the
+// wavefront / pack-1 fallback.
+glass_status_t resolve(const Shape& s, long long batch, const glass_placement_t* force, Geometry* g) {
+    if (force) {
+        if (!make_geometry(s, force->scope, force->pack, batch, g)) return GLASS_ERR_INFEASIBLE_PLACEMENT;
+        return GLASS_OK;
+    }
+    int order = s.n;
+    if (s.op == GLASS_OP_GEMM || s.op == GLASS_OP_GEMV) {
+        order = s.m > order ? s.m : order;
+        if (s.op == GLASS_OP_GEMM) order = s.k > order ? s.k : order;
+    }
+    int scope, pack;
+    table_lookup(s.op, order, batch, &scope, &pack);
+    if (make_geometry(s, scope, pack, batch, g)) return GLASS_OK;
+    if (make_geometry(s, GLASS_SCOPE_WAVE, 1, batch, g)) return GLASS_OK;
+    if (make_geometry(s, GLASS_SCOPE_WORKGROUP, 1, batch, g)) return GLASS_OK;
+    return GLASS_ERR_INFEASIBLE_PLACEMENT;
+}
+
+inline glass_status_t launched(int err) { return err == 0 ? GLASS_OK : GLASS_ERR_LAUNCH; }
+
+}  // namespace
+}  // namespace glass
+
+using namespace glass;
+
+extern "C" {
+
+glass_status_t glass_gemm_batched(int m, int n, int k, int batch, float alpha, const float* A, const float* B,
+                                  float beta, float* C, const glass_placement_t* force, void* stream) {
+    if (!valid_force(force)) return GLASS_ERR_INVALID_VALUE;
+    if (!size_ok(m) || !size_ok(n) || !size_ok(k)) return GLASS_ERR_UNSUPPORTED;
+    if (batch < 0) return GLASS_ERR_INVALID_VALUE;
+    if (batch == 0) return GLASS_OK;
+    if (!A || !B || !C) return GLASS_ERR_INVALID_VALUE;
+    Shape s{GLASS_OP_GEMM, m, n, k, 1, 0};
+    Geometry g;
+    glass_status_t st = resolve(s, batch, force, &g);
+    if (st != GLASS_OK) return st;
+    return launched(launch_gemm(s, g, batch, alpha, A, B, beta, C, stream));
+}
+
+glass_status_t glass_gemv_batched(int m, int n, int batch, float alpha, const float* A, const float* x,
+                                  float beta, float* y, const glass_placement_t* force, void* stream) {
+    if (!valid_force(force)) return GLASS_ERR_INVALID_VALUE;
+    if (!size_ok(m) || !size_ok(n)) return GLASS_ERR_UNSUPPORTED;
+    if (batch < 0) return GLASS_ERR_INVALID_VALUE;
+    if (batch == 0) return GLASS_OK;
+    if (!A || !x || !y) return GLASS_ERR_INVALID_VALUE;
+    Shape s{GLASS_OP_GEMV, m, n, n, 1, 0};
+    Geometry g;
+    glass_status_t st = resolve(s, batch, force, &g);
+    if (st != GLASS_OK) return st;
+    return launched(launch_gemv(s, g, batch, alpha, A, x, beta, y, stream));
+}
+
+glass_status_t glass_potrf_batched(int n, int batch, float* A, int32_t* info, const glass_placement_t* force,
+                                   void* stream) {
+    if (!valid_force(force)) return GLASS_ERR_INVALID_VALUE;
+    if (!size_ok(n)) return GLASS_ERR_UNSUPPORTED;
+    if (batch < 0) return GLASS_ERR_INVALID_VALUE;
+    if (batch == 0) return GLASS_OK;
+    if (!A) return GLASS_ERR_INVALID_VALUE;
+    Shape s{GLASS_OP_POTRF, n, n, n, 1, 0};
+    Geometry g;
+    glass_status_t st = resolve(s, batch, force, &g);
+    if (st != GLASS_OK) return st;
+    return launched(launch_potrf(s, g, batch, A, info, stream));
+}
+
+glass_status_t glass_potrs_batched(int n, int nrhs, int batch, const float* L, float* B,
+                                   const glass_placement_t* force, void* stream) {
+    if (!valid_force(force)) return GLASS_ERR_INVALID_VALUE;
+    if (!size_ok(n) || !size_ok(nrhs)) return GLASS_ERR_UNSUPPORTED;
+    if (batch < 0) return GLASS_ERR_INVALID_VALUE;
+    if (batch == 0) return GLASS_OK;
+    if (!L || !B) return GLASS_ERR_INVALID_VALUE;
+    Shape s{GLASS_OP_POTRS, n, n, n, nrhs, 0};
+    Geometry g;
+    glass_status_t st = resolve(s, batch, force, &g);
+    if (st != GLASS_OK) return st;
+    return launched(launch_potrs(s, g, batch, L, B, stream));
+}
+
+glass_status_t glass_posv_batched(int n, int nrhs, int batch, float* A, float* B, int32_t* info,
+                                  const glass_placement_t* force, void* stream) {
+    if (!valid_force(force)) return GLASS_ERR_INVALID_VALUE;
+    if (!size_ok(n) || !size_ok(nrhs)) return GLASS_ERR_UNSUPPORTED;
+    if (batch < 0) return GLASS_ERR_INVALID_VALUE;
+    if (batch == 0) return GLASS_OK;
+    if (!A || !B) return GLASS_ERR_INVALID_VALUE;
+    Shape s{GLASS_OP_POSV, n, n, n, nrhs, 0};
+    Geometry g;
+    glass_status_t st = resolve(s, batch, force, &g);
+    if (st != GLASS_OK) return st;
+    return launched(launch_posv(s, g, batch, A, B, info, stream));
+}
+
+glass_status_t glass_trsv_batched(int n, int batch, int trans, const float* L, float* x,
+                                  const glass_placement_t* force, void* stream) {
+    if (!valid_force(force) || (trans != 0 && trans != 1)) return GLASS_ERR_INVALID_VALUE;
+    if (!size_ok(n)) return GLASS_ERR_UNSUPPORTED;
+    if (batch < 0) return GLASS_ERR_INVALID_VALUE;
+    if (batch == 0) return GLASS_OK;
+    if (!L || !x) return GLASS_ERR_INVALID_VALUE;
+    Shape s{GLASS_OP_TRSV, n, n, n, 1, trans};
+    Geometry g;
+    glass_status_t st = resolve(s, batch, force, &g);
+    if (st != GLASS_OK) return st;
+    return launched(launch_trsv(s, g, batch, L, x, stream));
+}
+
+glass_status_t glass_se3_batched(glass_op_t op, int batch, const float* Ta, const float* Tb, float* Tout,
+                                 const glass_placement_t* force, void* stream) {
+    if (!valid_force(force) || !is_se3(op)) return GLASS_ERR_INVALID_VALUE;
+    if (batch < 0) return GLASS_ERR_INVALID_VALUE;
+    if (batch == 0) return GLASS_OK;
+    if (!Ta || !Tout || (op == GLASS_OP_SE3_COMPOSE && !Tb)) return GLASS_ERR_INVALID_VALUE;
+    Shape s{op, 4, 4, 4, 1, 0};
+    Geometry g;
+    glass_status_t st = resolve(s, batch, force, &g);
+    if (st != GLASS_OK) return st;
+    return launched(launch_se3(s, g, batch, Ta, Tb, Tout, stream));
+}
+
+glass_status_t glass_query_placement(glass_op_t op, int n, int batch, glass_placement_t* out) {
+    if ((int)op < GLASS_OP_GEMM || (int)op > GLASS_OP_SE3_INVERSE) return GLASS_ERR_INVALID_VALUE;
+    if (!is_se3(op) && !size_ok(n)) return GLASS_ERR_UNSUPPORTED;
+    if (batch < 1 || !out) return GLASS_ERR_INVALID_VALUE;
+    const int order = is_se3(op) ? 4 : n;
+    int scope, pack;
+    table_lookup(op, order, batch, &scope, &pack);
+    Shape s{op, order, order, order, 1, 0};
+    Geometry g;
+    if (!make_geometry(s, scope, pack, batch, &g)) {
+        scope = GLASS_SCOPE_WAVE;
+        pack = 1;
+        make_geometry(s, scope, pack, batch, &g);
+    }
+    out->scope = g.scope;
+    out->pack = g.pack;
+    out->wg_threads = g.threads;
+    out->problems_per_wg = g.problems_per_wg;
+    return GLASS_OK;
+}
+
+int glass_placement_feasible(glass_op_t op, int n, int nrhs, int scope, int pack) {
+    if ((int)op < GLASS_OP_GEMM || (int)op > GLASS_OP_SE3_INVERSE) return GLASS_ERR_INVALID_VALUE;
+    if (scope < GLASS_SCOPE_THREAD || scope > GLASS_SCOPE_WORKGROUP) return GLASS_ERR_INVALID_VALUE;
+    if (!is_se3(op) && !size_ok(n)) return GLASS_ERR_UNSUPPORTED;
+    if (!size_ok(nrhs)) return GLASS_ERR_UNSUPPORTED;
+    const int order = is_se3(op) ? 4 : n;
+    Shape s{op, order, order, order, nrhs, 0};
+    return make_geometry(s, scope, pack, 1, nullptr) ? 1 : 0;
+}
+
+const char* glass_table_provenance(void) { return kTableProvenance; }
+
+const char* glass_status_string(glass_status_t s) {
+    switch (s) {
+    case GLASS_OK: return "GLASS_OK";
+    case GLASS_ERR_INVALID_VALUE: return "GLASS_ERR_INVALID_VALUE";
+    case GLASS_ERR_UNSUPPORTED: return "GLASS_ERR_UNSUPPORTED";
+    case GLASS_ERR_INFEASIBLE_PLACEMENT: return "GLASS_ERR_INFEASIBLE_PLACEMENT";
+    case GLASS_ERR_LAUNCH: return "GLASS_ERR_LAUNCH";
+    }
+    return "GLASS_ERR_UNKNOWN";
+}
+
+}  // extern "C"

@@ -1,0 +1,643 @@
+// chol.hip -- batched Cholesky factorization (POTRF), Cholesky solve (POTRS),
+// fused factor-and-solve (POSV) and triangular solve (TRSV) for gfx950, each
+// at the three execution scopes of Sec. III-A:
+//
+//   thread    one problem per lane.  The workgroup's contiguous span of
+//             problems is staged through LDS with coalesced loads (in passes
+//             that bound LDS use), each lane then holds its problem's lower
+//             triangle in VGPRs at compile-time order N and factors / solves
+//             it fully unrolled.
+//   wave      one problem per 64-lane wavefront.  Lane i owns row i.  POTRF is
+//             right-looking: the pivot comes from v_readlane, the scaled
+//             column is broadcast through a wave-private LDS vector and every
+//             lane updates its row in VGPRs.  Substitutions are lane-parallel
+//             with v_readlane broadcasts of the solved unknown.
+//   workgroup one problem at a time per workgroup of T(n) lanes, the matrix
+//             resident in LDS, cooperative right-looking updates separated
+//             by workgroup barriers; P problems back to back.
+//
+// Arithmetic: FP32, fused multiply-add, correctly rounded sqrtf; a division
+// by a diagonal entry is done as a multiply by its reciprocal.  The failure
+// test is !(pivot > 0), as in the definition of info in glass.h.
+#include "device_common.hpp"
+#include "glass_internal.hpp"
+
+namespace glass {
+namespace {
+
+#define TI(i, j) ((i) * ((i) + 1) / 2 + (j))
+
+// ------------------------------------------------------------ thread scope --
+__device__ __forceinline__ int stage_q(int threads, int elems) {
+    int s = elems | 1;
+    int q = kStagePassFloats / s;
+    if (q < 1) q = 1;
+    return q < threads ? q : threads;
+}
+
+template <int N>
+GLASS_DEV void tri_load(float (&a)[N * (N + 1) / 2], const float* src) {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) a[TI(i, j)] = src[i * N + j];
+}
+
+template <int N>
+GLASS_DEV void tri_store_full(const float (&a)[N * (N + 1) / 2], float* dst) {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) dst[i * N + j] = j <= i ? a[TI(i, j)] : 0.f;
+}
+
+// Left-looking Cholesky of the lane's triangle; returns info.
+template <int N>
+GLASS_DEV int tri_potrf(float (&a)[N * (N + 1) / 2], float (&dinv)[N]) {
+    int info = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        float s = a[TI(j, j)];
+#pragma unroll
+        for (int p = 0; p < j; ++p) s = fmaf(-a[TI(j, p)], a[TI(j, p)], s);
+        if (!(s > 0.f) && info == 0) info = j + 1;
+        const float l = sqrtf(s);
+        const float inv = 1.0f / l;
+        a[TI(j, j)] = l;
+        dinv[j] = inv;
+#pragma unroll
+        for (int i = j + 1; i < N; ++i) {
+            float t = a[TI(i, j)];
+#pragma unroll
+            for (int p = 0; p < j; ++p) t = fmaf(-a[TI(i, p)], a[TI(j, p)], t);
+            a[TI(i, j)] = t * inv;
+        }
+    }
+    return info;
+}
+
+// x <- L^{-1} x (fwd) and/or L^{-T} x (bwd) for one column held in VGPRs.
+template <int N>
+GLASS_DEV void tri_fwd(const float (&a)[N * (N + 1) / 2], const float (&dinv)[N], float (&y)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        float t = y[i];
+#pragma unroll
+        for (int p = 0; p < i; ++p) t = fmaf(-a[TI(i, p)], y[p], t);
+        y[i] = t * dinv[i];
+    }
+}
+
+template <int N>
+GLASS_DEV void tri_bwd(const float (&a)[N * (N + 1) / 2], const float (&dinv)[N], float (&y)[N]) {
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+        float t = y[i];
+#pragma unroll
+        for (int p = i + 1; p < N; ++p) t = fmaf(-a[TI(p, i)], y[p], t);
+        y[i] = t * dinv[i];
+    }
+}
+
+// Stage the lanes' triangles in: passes of Q problems through LDS.
+template <int N>
+GLASS_DEV void thread_load_tri(float (&a)[N * (N + 1) / 2], const float* __restrict__ base, float* lds,
+                               int cnt, int tid, int nt) {
+    constexpr int SZ = N * N, S = SZ | 1;
+    const int Q = stage_q(nt, SZ);
+    const FastDiv fd = make_fastdiv(SZ);
+    for (int s = 0; s < cnt; s += Q) {
+        const int qn = min(Q, cnt - s);
+        stage_in(lds, base + (size_t)s * SZ, qn * SZ, fd, S, tid, nt);
+        __syncthreads();
+        if (tid >= s && tid < s + qn) tri_load<N>(a, lds + (tid - s) * S);
+        __syncthreads();
+    }
+}
+
+template <int N>
+GLASS_DEV void thread_store_tri(const float (&a)[N * (N + 1) / 2], float* __restrict__ base, float* lds,
+                                int cnt, int tid, int nt) {
+    constexpr int SZ = N * N, S = SZ | 1;
+    const int Q = stage_q(nt, SZ);
+    const FastDiv fd = make_fastdiv(SZ);
+    for (int s = 0; s < cnt; s += Q) {
+        const int qn = min(Q, cnt - s);
+        if (tid >= s && tid < s + qn) tri_store_full<N>(a, lds + (tid - s) * S);
+        __syncthreads();
+        stage_out(base + (size_t)s * SZ, lds, qn * SZ, fd, S, tid, nt);
+        __syncthreads();
+    }
+}
+
+// Solve the staged right-hand sides of every lane (all columns) in place.
+template <int N>
+GLASS_DEV void thread_solve_rhs(const float (&a)[N * (N + 1) / 2], const float (&dinv)[N], float* __restrict__ Bg,
+                                float* lds, int nrhs, int cnt, int tid, int nt, bool fwd, bool bwd,
+                                bool active) {
+    const int SZ = N * nrhs, S = SZ | 1;
+    const FastDiv fd = make_fastdiv(SZ);
+    stage_in(lds, Bg, cnt * SZ, fd, S, tid, nt);
+    __syncthreads();
+    if (active) {
+        float* b = lds + tid * S;
+        for (int c = 0; c < nrhs; ++c) {
+            float y[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) y[i] = b[i * nrhs + c];
+            if (fwd) tri_fwd<N>(a, dinv, y);
+            if (bwd) tri_bwd<N>(a, dinv, y);
+#pragma unroll
+            for (int i = 0; i < N; ++i) b[i * nrhs + c] = y[i];
+        }
+    }
+    __syncthreads();
+    stage_out(Bg, lds, cnt * SZ, fd, S, tid, nt);
+}
+
+template <int N>
+__global__ void __launch_bounds__(512) potrf_thread(int batch, float* __restrict__ A, int* __restrict__ info) {
+    extern __shared__ float lds[];
+    const int nt = blockDim.x, tid = threadIdx.x;
+    const long long p0 = (long long)blockIdx.x * nt;
+    const int cnt = (int)min((long long)nt, (long long)batch - p0);
+    float* base = A + p0 * (N * N);
+    float a[N * (N + 1) / 2];
+    float dinv[N];
+    thread_load_tri<N>(a, base, lds, cnt, tid, nt);
+    const bool active = tid < cnt;
+    int inf = 0;
+    if (active) inf = tri_potrf<N>(a, dinv);
+    if (info && active) info[p0 + tid] = inf;
+    thread_store_tri<N>(a, base, lds, cnt, tid, nt);
+}
+
+template <int N>
+__global__ void __launch_bounds__(512) posv_thread(int nrhs, int batch, float* __restrict__ A, float* __restrict__ B,
+                                                   int* __restrict__ info) {
+    extern __shared__ float lds[];
+    const int nt = blockDim.x, tid = threadIdx.x;
+    const long long p0 = (long long)blockIdx.x * nt;
+    const int cnt = (int)min((long long)nt, (long long)batch - p0);
+    float* base = A + p0 * (N * N);
+    float a[N * (N + 1) / 2];
+    float dinv[N];
+    thread_load_tri<N>(a, base, lds, cnt, tid, nt);
+    const bool active = tid < cnt;
+    int inf = 0;
+    if (active) inf = tri_potrf<N>(a, dinv);
+    if (info && active) info[p0 + tid] = inf;
+    thread_store_tri<N>(a, base, lds, cnt, tid, nt);
+    thread_solve_rhs<N>(a, dinv, B + p0 * N * nrhs, lds, nrhs, cnt, tid, nt, true, true, active && inf == 0);
+}
+
+template <int N>
+__global__ void __launch_bounds__(512) potrs_thread(int nrhs, int batch, const float* __restrict__ L,
+                                                    float* __restrict__ B) {
+    extern __shared__ float lds[];
+    const int nt = blockDim.x, tid = threadIdx.x;
+    const long long p0 = (long long)blockIdx.x * nt;
+    const int cnt = (int)min((long long)nt, (long long)batch - p0);
+    float a[N * (N + 1) / 2];
+    float dinv[N];
+    thread_load_tri<N>(a, L + p0 * (N * N), lds, cnt, tid, nt);
+#pragma unroll
+    for (int i = 0; i < N; ++i) dinv[i] = 1.0f / a[TI(i, i)];
+    thread_solve_rhs<N>(a, dinv, B + p0 * N * nrhs, lds, nrhs, cnt, tid, nt, true, true, tid < cnt);
+}
+
+template <int N>
+__global__ void __launch_bounds__(512) trsv_thread(int trans, int batch, const float* __restrict__ L,
+                                                   float* __restrict__ x) {
+    extern __shared__ float lds[];
+    const int nt = blockDim.x, tid = threadIdx.x;
+    const long long p0 = (long long)blockIdx.x * nt;
+    const int cnt = (int)min((long long)nt, (long long)batch - p0);
+    float a[N * (N + 1) / 2];
+    float dinv[N];
+    thread_load_tri<N>(a, L + p0 * (N * N), lds, cnt, tid, nt);
+#pragma unroll
+    for (int i = 0; i < N; ++i) dinv[i] = 1.0f / a[TI(i, i)];
+    thread_solve_rhs<N>(a, dinv, x + p0 * N, lds, 1, cnt, tid, nt, trans == 0, trans != 0, tid < cnt);
+}
+
+// -------------------------------------------------------------- wave scope --
+// Row `lane` of the staged matrix (lower part only, zeros elsewhere).
+template <int NB>
+GLASS_DEV void row_load(float (&a)[NB], const float* M, int n, int s, int lane) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) a[j] = (lane < n && j < n && j <= lane) ? M[lane * s + j] : 0.f;
+}
+
+template <int NB>
+GLASS_DEV void row_store(const float (&a)[NB], float* M, int n, int s, int lane) {
+    if (lane < n) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (j < n) M[lane * s + j] = j <= lane ? a[j] : 0.f;
+    }
+}
+
+// Right-looking wave Cholesky, lane i holding row i; returns info.
+template <int NB>
+GLASS_DEV int wave_potrf(float (&a)[NB], float* col, int n, int lane) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j >= n) break;
+        const float d = readlane(a[j], j);
+        if (!(d > 0.f)) return j + 1;
+        const float l = sqrtf(d);
+        const float inv = 1.0f / l;
+        const float v = lane == j ? l : a[j] * inv;
+        a[j] = v;
+        col[lane] = v;
+        wave_sync();
+#pragma unroll
+        for (int k = j + 1; k < NB; ++k) a[k] = fmaf(-v, col[k], a[k]);
+        wave_sync();
+    }
+    return 0;
+}
+
+// Lane-parallel substitutions for one problem whose factor L is staged in
+// LDS (M, row stride s; only the lower triangle is read) and whose
+// right-hand sides are staged in Bm ([n][nrhs], row stride sb).
+GLASS_DEV void wave_solve(const float* M, int s, float* Bm, int sb, int n, int nrhs, int lane, bool fwd,
+                          bool bwd) {
+    const bool row = lane < n;
+    const float myinv = row ? 1.0f / M[lane * s + lane] : 0.f;
+    for (int c = 0; c < nrhs; ++c) {
+        float acc = row ? Bm[lane * sb + c] : 0.f;
+        if (fwd) {
+            for (int k = 0; k < n; ++k) {
+                const float lik = (row && k < lane) ? M[lane * s + k] : 0.f;
+                const float yk = readlane(acc * myinv, k);
+                acc = lane == k ? yk : fmaf(-lik, yk, acc);
+            }
+        }
+        if (bwd) {
+            for (int k = n - 1; k >= 0; --k) {
+                const float lki = lane < k ? M[k * s + lane] : 0.f;
+                const float xk = readlane(acc * myinv, k);
+                acc = lane == k ? xk : fmaf(-lki, xk, acc);
+            }
+        }
+        if (row) Bm[lane * sb + c] = acc;
+    }
+}
+
+template <int NB>
+__global__ void __launch_bounds__(512) potrf_wave(int n, int batch, float* __restrict__ A, int* __restrict__ info,
+                                                  int region) {
+    extern __shared__ float lds[];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
+    if (p >= batch) return;
+    float* M = lds + (size_t)w * region;
+    const int s = n | 1;
+    float* col = M + ((n * s + 3) & ~3);
+    float* Ag = A + p * n * n;
+    const FastDiv fd = make_fastdiv(n);
+    stage_in(M, Ag, n * n, fd, s, lane, 64);
+    wave_sync();
+    float a[NB];
+    row_load<NB>(a, M, n, s, lane);
+    const int inf = wave_potrf<NB>(a, col, n, lane);
+    row_store<NB>(a, M, n, s, lane);
+    wave_sync();
+    stage_out(Ag, M, n * n, fd, s, lane, 64);
+    if (info && lane == 0) info[p] = inf;
+}
+
+template <int NB>
+__global__ void __launch_bounds__(512) posv_wave(int n, int nrhs, int batch, float* __restrict__ A,
+                                                 float* __restrict__ B, int* __restrict__ info, int region) {
+    extern __shared__ float lds[];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
+    if (p >= batch) return;
+    float* M = lds + (size_t)w * region;
+    const int s = n | 1, sb = nrhs | 1;
+    float* Bm = M + ((n * s + 3) & ~3);
+    float* col = Bm + ((n * sb + 3) & ~3);
+    float* Ag = A + p * n * n;
+    float* Bg = B + p * n * nrhs;
+    const FastDiv fd = make_fastdiv(n), fdb = make_fastdiv(nrhs);
+    stage_in(M, Ag, n * n, fd, s, lane, 64);
+    stage_in(Bm, Bg, n * nrhs, fdb, sb, lane, 64);
+    wave_sync();
+    float a[NB];
+    row_load<NB>(a, M, n, s, lane);
+    const int inf = wave_potrf<NB>(a, col, n, lane);
+    row_store<NB>(a, M, n, s, lane);
+    wave_sync();
+    stage_out(Ag, M, n * n, fd, s, lane, 64);
+    if (info && lane == 0) info[p] = inf;
+    if (inf == 0) {
+        wave_solve(M, s, Bm, sb, n, nrhs, lane, true, true);
+        wave_sync();
+        stage_out(Bg, Bm, n * nrhs, fdb, sb, lane, 64);
+    }
+}
+
+__global__ void __launch_bounds__(512) potrs_wave(int n, int nrhs, int batch, const float* __restrict__ L,
+                                                  float* __restrict__ B, int region) {
+    extern __shared__ float lds[];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
+    if (p >= batch) return;
+    float* M = lds + (size_t)w * region;
+    const int s = n | 1, sb = nrhs | 1;
+    float* Bm = M + ((n * s + 3) & ~3);
+    float* Bg = B + p * n * nrhs;
+    const FastDiv fdb = make_fastdiv(nrhs);
+    stage_in(M, L + p * n * n, n * n, make_fastdiv(n), s, lane, 64);
+    stage_in(Bm, Bg, n * nrhs, fdb, sb, lane, 64);
+    wave_sync();
+    wave_solve(M, s, Bm, sb, n, nrhs, lane, true, true);
+    wave_sync();
+    stage_out(Bg, Bm, n * nrhs, fdb, sb, lane, 64);
+}
+
+__global__ void __launch_bounds__(512) trsv_wave(int n, int trans, int batch, const float* __restrict__ L,
+                                                 float* __restrict__ x, int region) {
+    extern __shared__ float lds[];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
+    if (p >= batch) return;
+    float* M = lds + (size_t)w * region;
+    const int s = n | 1;
+    stage_in(M, L + p * n * n, n * n, make_fastdiv(n), s, lane, 64);
+    wave_sync();
+    const bool row = lane < n;
+    float v = row ? x[p * n + lane] : 0.f;
+    float* vm = M + ((n * s + 3) & ~3);
+    if (row) vm[lane] = v;
+    wave_sync();
+    wave_solve(M, s, vm, 1, n, 1, lane, trans == 0, trans != 0);
+    wave_sync();
+    if (row) x[p * n + lane] = vm[lane];
+}
+
+// --------------------------------------------------------- workgroup scope --
+// Right-looking Cholesky of the LDS-resident matrix M (row stride s) by the
+// whole workgroup; returns info (identical in every lane).
+GLASS_DEV int wg_potrf(float* M, int n, int s, int tid, int nt) {
+    const int tr = tid >> 4, tc = tid & 15, rstep = nt >> 4;
+    for (int j = 0; j < n; ++j) {
+        const float d = M[j * s + j];
+        if (!(d > 0.f)) return j + 1;
+        const float l = sqrtf(d);
+        const float inv = 1.0f / l;
+        __syncthreads();
+        for (int i = j + tid; i < n; i += nt) M[i * s + j] = i == j ? l : M[i * s + j] * inv;
+        __syncthreads();
+        for (int i = j + 1 + tr; i < n; i += rstep) {
+            const float lij = M[i * s + j];
+            for (int k = j + 1 + tc; k <= i; k += 16) M[i * s + k] = fmaf(-lij, M[k * s + j], M[i * s + k]);
+        }
+        __syncthreads();
+    }
+    return 0;
+}
+
+// Zero the strict upper triangle of M.
+GLASS_DEV void wg_zero_upper(float* M, int n, int s, int tid, int nt) {
+    const int tr = tid >> 4, tc = tid & 15, rstep = nt >> 4;
+    for (int i = tr; i < n; i += rstep)
+        for (int k = i + 1 + tc; k < n; k += 16) M[i * s + k] = 0.f;
+}
+
+// Workgroup substitutions on Bm ([n][nrhs], stride sb) with L in M.
+GLASS_DEV void wg_solve(const float* M, int s, float* Bm, int sb, int n, int nrhs, int tid, int nt, bool fwd,
+                        bool bwd) {
+    const FastDiv fr = make_fastdiv(nrhs);
+    const int tot = n * nrhs;
+    if (fwd) {
+        for (int k = 0; k < n; ++k) {
+            const float dk = 1.0f / M[k * s + k];
+            for (int idx = tid; idx < tot; idx += nt) {
+                const int i = (int)fdiv((uint32_t)idx, fr), c = idx - i * nrhs;
+                if (i > k) Bm[i * sb + c] = fmaf(-M[i * s + k], Bm[k * sb + c] * dk, Bm[i * sb + c]);
+            }
+            __syncthreads();
+        }
+        for (int idx = tid; idx < tot; idx += nt) {
+            const int i = (int)fdiv((uint32_t)idx, fr), c = idx - i * nrhs;
+            Bm[i * sb + c] *= 1.0f / M[i * s + i];
+        }
+        __syncthreads();
+    }
+    if (bwd) {
+        for (int k = n - 1; k >= 0; --k) {
+            const float dk = 1.0f / M[k * s + k];
+            for (int idx = tid; idx < tot; idx += nt) {
+                const int i = (int)fdiv((uint32_t)idx, fr), c = idx - i * nrhs;
+                if (i < k) Bm[i * sb + c] = fmaf(-M[k * s + i], Bm[k * sb + c] * dk, Bm[i * sb + c]);
+            }
+            __syncthreads();
+        }
+        for (int idx = tid; idx < tot; idx += nt) {
+            const int i = (int)fdiv((uint32_t)idx, fr), c = idx - i * nrhs;
+            Bm[i * sb + c] *= 1.0f / M[i * s + i];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) potrf_wg(int n, int batch, int pack, float* __restrict__ A,
+                                                int* __restrict__ info) {
+    extern __shared__ float lds[];
+    const int nt = blockDim.x, tid = threadIdx.x;
+    const int s = n | 1;
+    const FastDiv fd = make_fastdiv(n);
+    for (int q = 0; q < pack; ++q) {
+        const long long p = (long long)blockIdx.x * pack + q;
+        if (p >= batch) break;
+        float* Ag = A + p * n * n;
+        stage_in(lds, Ag, n * n, fd, s, tid, nt);
+        __syncthreads();
+        const int inf = wg_potrf(lds, n, s, tid, nt);
+        wg_zero_upper(lds, n, s, tid, nt);
+        __syncthreads();
+        stage_out(Ag, lds, n * n, fd, s, tid, nt);
+        if (info && tid == 0) info[p] = inf;
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) posv_wg(int n, int nrhs, int batch, int pack, float* __restrict__ A,
+                                               float* __restrict__ B, int* __restrict__ info) {
+    extern __shared__ float lds[];
+    const int nt = blockDim.x, tid = threadIdx.x;
+    const int s = n | 1, sb = nrhs | 1;
+    float* Bm = lds + ((n * s + 3) & ~3);
+    const FastDiv fd = make_fastdiv(n), fdb = make_fastdiv(nrhs);
+    for (int q = 0; q < pack; ++q) {
+        const long long p = (long long)blockIdx.x * pack + q;
+        if (p >= batch) break;
+        float* Ag = A + p * n * n;
+        float* Bg = B + p * n * nrhs;
+        stage_in(lds, Ag, n * n, fd, s, tid, nt);
+        stage_in(Bm, Bg, n * nrhs, fdb, sb, tid, nt);
+        __syncthreads();
+        const int inf = wg_potrf(lds, n, s, tid, nt);
+        wg_zero_upper(lds, n, s, tid, nt);
+        __syncthreads();
+        stage_out(Ag, lds, n * n, fd, s, tid, nt);
+        if (info && tid == 0) info[p] = inf;
+        if (inf == 0) {
+            wg_solve(lds, s, Bm, sb, n, nrhs, tid, nt, true, true);
+            stage_out(Bg, Bm, n * nrhs, fdb, sb, tid, nt);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) potrs_wg(int n, int nrhs, int batch, int pack, const float* __restrict__ L,
+                                                float* __restrict__ B) {
+    extern __shared__ float lds[];
+    const int nt = blockDim.x, tid = threadIdx.x;
+    const int s = n | 1, sb = nrhs | 1;
+    float* Bm = lds + ((n * s + 3) & ~3);
+    const FastDiv fd = make_fastdiv(n), fdb = make_fastdiv(nrhs);
+    for (int q = 0; q < pack; ++q) {
+        const long long p = (long long)blockIdx.x * pack + q;
+        if (p >= batch) break;
+        float* Bg = B + p * n * nrhs;
+        stage_in(lds, L + p * n * n, n * n, fd, s, tid, nt);
+        stage_in(Bm, Bg, n * nrhs, fdb, sb, tid, nt);
+        __syncthreads();
+        wg_solve(lds, s, Bm, sb, n, nrhs, tid, nt, true, true);
+        stage_out(Bg, Bm, n * nrhs, fdb, sb, tid, nt);
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) trsv_wg(int n, int trans, int batch, int pack, const float* __restrict__ L,
+                                               float* __restrict__ x) {
+    extern __shared__ float lds[];
+    const int nt = blockDim.x, tid = threadIdx.x;
+    const int s = n | 1;
+    float* vm = lds + ((n * s + 3) & ~3);
+    const FastDiv fd = make_fastdiv(n);
+    for (int q = 0; q < pack; ++q) {
+        const long long p = (long long)blockIdx.x * pack + q;
+        if (p >= batch) break;
+        stage_in(lds, L + p * n * n, n * n, fd, s, tid, nt);
+        for (int i = tid; i < n; i += nt) vm[i] = x[p * n + i];
+        __syncthreads();
+        wg_solve(lds, s, vm, 1, n, 1, tid, nt, trans == 0, trans != 0);
+        for (int i = tid; i < n; i += nt) x[p * n + i] = vm[i];
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------- launch --
+#define GLASS_CASES_1_16(X) \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+#define GLASS_BUCKETS(X) X(8) X(16) X(24) X(32) X(40) X(48) X(56) X(64)
+
+inline int bucket8(int n) { return ((n + 7) / 8) * 8; }
+
+inline int finish() { return (int)hipGetLastError(); }
+
+}  // namespace
+
+int launch_potrf(const Shape& sh, const Geometry& g, int batch, float* A, int32_t* info, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const int n = sh.n;
+    dim3 grid((unsigned)g.grid), block(g.threads);
+    if (g.scope == GLASS_SCOPE_THREAD) {
+        switch (n) {
+#define X(N) \
+    case N: hipLaunchKernelGGL(potrf_thread<N>, grid, block, g.lds_bytes, st, batch, A, info); break;
+            GLASS_CASES_1_16(X)
+#undef X
+        default: return (int)hipErrorInvalidValue;
+        }
+    } else if (g.scope == GLASS_SCOPE_WAVE) {
+        const int region = (int)region_floats(sh);
+        switch (bucket8(n)) {
+#define X(NB) \
+    case NB: hipLaunchKernelGGL(potrf_wave<NB>, grid, block, g.lds_bytes, st, n, batch, A, info, region); break;
+            GLASS_BUCKETS(X)
+#undef X
+        default: return (int)hipErrorInvalidValue;
+        }
+    } else {
+        hipLaunchKernelGGL(potrf_wg, grid, block, g.lds_bytes, st, n, batch, g.pack, A, info);
+    }
+    return finish();
+}
+
+int launch_posv(const Shape& sh, const Geometry& g, int batch, float* A, float* B, int32_t* info, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const int n = sh.n, r = sh.nrhs;
+    dim3 grid((unsigned)g.grid), block(g.threads);
+    if (g.scope == GLASS_SCOPE_THREAD) {
+        switch (n) {
+#define X(N) \
+    case N: hipLaunchKernelGGL(posv_thread<N>, grid, block, g.lds_bytes, st, r, batch, A, B, info); break;
+            GLASS_CASES_1_16(X)
+#undef X
+        default: return (int)hipErrorInvalidValue;
+        }
+    } else if (g.scope == GLASS_SCOPE_WAVE) {
+        const int region = (int)region_floats(sh);
+        switch (bucket8(n)) {
+#define X(NB) \
+    case NB: hipLaunchKernelGGL(posv_wave<NB>, grid, block, g.lds_bytes, st, n, r, batch, A, B, info, region); break;
+            GLASS_BUCKETS(X)
+#undef X
+        default: return (int)hipErrorInvalidValue;
+        }
+    } else {
+        hipLaunchKernelGGL(posv_wg, grid, block, g.lds_bytes, st, n, r, batch, g.pack, A, B, info);
+    }
+    return finish();
+}
+
+int launch_potrs(const Shape& sh, const Geometry& g, int batch, const float* L, float* B, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const int n = sh.n, r = sh.nrhs;
+    dim3 grid((unsigned)g.grid), block(g.threads);
+    if (g.scope == GLASS_SCOPE_THREAD) {
+        switch (n) {
+#define X(N) \
+    case N: hipLaunchKernelGGL(potrs_thread<N>, grid, block, g.lds_bytes, st, r, batch, L, B); break;
+            GLASS_CASES_1_16(X)
+#undef X
+        default: return (int)hipErrorInvalidValue;
+        }
+    } else if (g.scope == GLASS_SCOPE_WAVE) {
+        const int region = (int)region_floats(sh);
+        hipLaunchKernelGGL(potrs_wave, grid, block, g.lds_bytes, st, n, r, batch, L, B, region);
+    } else {
+        hipLaunchKernelGGL(potrs_wg, grid, block, g.lds_bytes, st, n, r, batch, g.pack, L, B);
+    }
+    return finish();
+}
+
+int launch_trsv(const Shape& sh, const Geometry& g, int batch, const float* L, float* x, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const int n = sh.n, tr = sh.trans;
+    dim3 grid((unsigned)g.grid), block(g.threads);
+    if (g.scope == GLASS_SCOPE_THREAD) {
+        switch (n) {
+#define X(N) \
+    case N: hipLaunchKernelGGL(trsv_thread<N>, grid, block, g.lds_bytes, st, tr, batch, L, x); break;
+            GLASS_CASES_1_16(X)
+#undef X
+        default: return (int)hipErrorInvalidValue;
+        }
+    } else if (g.scope == GLASS_SCOPE_WAVE) {
+        const int region = (int)region_floats(sh);
+        hipLaunchKernelGGL(trsv_wave, grid, block, g.lds_bytes, st, n, tr, batch, L, x, region);
+    } else {
+        hipLaunchKernelGGL(trsv_wg, grid, block, g.lds_bytes, st, n, tr, batch, g.pack, L, x);
+    }
+    return finish();
+}
+
+}  // namespace glass

@@ -1,0 +1,272 @@
+// gemm.hip -- batched C = alpha A B + beta C (Sec. III-B, BLAS L3) at the
+// three scopes of Sec. III-A.
+//
+//   thread     (m = n = k = N <= 12) one problem per lane: B is staged
+//              through LDS into VGPRs, A is staged whole and each lane turns
+//              its A rows into C rows in place; the epilogue is fused into the
+//              coalesced store.
+//   wave / wg  max(m, n, k) >= 16: FP32 MFMA (v_mfma_f32_16x16x4_f32), the
+//              operand fragments loaded straight from global memory (no LDS):
+//              lane l = 16q + r holds A[row r][k0 + 4q .. k0 + 4q + 3] as one
+//              16-byte load and feeds component c to MFMA step c, so step c
+//              contracts k in {k0 + c, k0 + 4 + c, k0 + 8 + c, k0 + 12 + c};
+//              the matching B fragment is B[k0 + 4q + c][col r].  The wave
+//              scope runs one problem per wavefront; the workgroup scope
+//              splits the 16-wide column tiles of one problem over its waves.
+//   small n    max(m, n, k) < 16 at wave / wg scope: operands staged in LDS,
+//              lanes over output elements.
+#include "device_common.hpp"
+#include "glass_internal.hpp"
+
+namespace glass {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int stage_q(int threads, int elems) {
+    int s = elems | 1;
+    int q = kStagePassFloats / s;
+    if (q < 1) q = 1;
+    return q < threads ? q : threads;
+}
+
+// ------------------------------------------------------------ thread scope --
+template <int N>
+__global__ void __launch_bounds__(512) gemm_thread(int batch, float alpha, const float* __restrict__ A,
+                                                   const float* __restrict__ B, float beta, float* __restrict__ C) {
+    extern __shared__ float lds[];
+    constexpr int SZ = N * N, S = SZ | 1;
+    const int nt = blockDim.x, tid = threadIdx.x;
+    const long long p0 = (long long)blockIdx.x * nt;
+    const int cnt = (int)min((long long)nt, (long long)batch - p0);
+    const FastDiv fd = make_fastdiv(SZ);
+    float b[SZ];
+    const int Q = stage_q(nt, SZ);
+    for (int s = 0; s < cnt; s += Q) {
+        const int qn = min(Q, cnt - s);
+        stage_in(lds, B + (p0 + s) * SZ, qn * SZ, fd, S, tid, nt);
+        __syncthreads();
+        if (tid >= s && tid < s + qn) {
+            const float* src = lds + (tid - s) * S;
+#pragma unroll
+            for (int e = 0; e < SZ; ++e) b[e] = src[e];
+        }
+        __syncthreads();
+    }
+    stage_in(lds, A + p0 * SZ, cnt * SZ, fd, S, tid, nt);
+    __syncthreads();
+    if (tid < cnt) {
+        float* a = lds + tid * S;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            float ar[N];
+#pragma unroll
+            for (int k = 0; k < N; ++k) ar[k] = a[i * N + k];
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                float c = 0.f;
+#pragma unroll
+                for (int k = 0; k < N; ++k) c = fmaf(ar[k], b[k * N + j], c);
+                a[i * N + j] = alpha * c;
+            }
+        }
+    }
+    __syncthreads();
+    stage_out_beta(C + p0 * SZ, lds, cnt * SZ, fd, S, beta, tid, nt);
+}
+
+// ------------------------------------------------- small n, wave / wg scope --
+GLASS_DEV void gemm_small_problem(int m, int n, int k, float alpha, const float* __restrict__ Ag,
+                                  const float* __restrict__ Bg, float beta, float* __restrict__ Cg, float* As,
+                                  int tid, int nt, bool wave) {
+    const int sk = k | 1, sn = n | 1;
+    float* Bs = As + ((m * sk + 3) & ~3);
+    stage_in(As, Ag, m * k, make_fastdiv(k), sk, tid, nt);
+    stage_in(Bs, Bg, k * n, make_fastdiv(n), sn, tid, nt);
+    if (wave) wave_sync(); else __syncthreads();
+    const FastDiv fn = make_fastdiv(n);
+    for (int e = tid; e < m * n; e += nt) {
+        const int i = (int)fdiv((uint32_t)e, fn), j = e - i * n;
+        float c = 0.f;
+        for (int p = 0; p < k; ++p) c = fmaf(As[i * sk + p], Bs[p * sn + j], c);
+        float out = alpha * c;
+        if (beta != 0.f) out = fmaf(beta, Cg[e], out);
+        Cg[e] = out;
+    }
+}
+
+__global__ void __launch_bounds__(512) gemm_small_wave(int m, int n, int k, int batch, float alpha,
+                                                       const float* __restrict__ A, const float* __restrict__ B,
+                                                       float beta, float* __restrict__ C, int region) {
+    extern __shared__ float lds[];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
+    if (p >= batch) return;
+    gemm_small_problem(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lds + (size_t)w * region,
+                       lane, 64, true);
+}
+
+__global__ void __launch_bounds__(256) gemm_small_wg(int m, int n, int k, int batch, int pack, float alpha,
+                                                     const float* __restrict__ A, const float* __restrict__ B,
+                                                     float beta, float* __restrict__ C) {
+    extern __shared__ float lds[];
+    for (int q = 0; q < pack; ++q) {
+        const long long p = (long long)blockIdx.x * pack + q;
+        if (p >= batch) break;
+        gemm_small_problem(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lds, threadIdx.x,
+                           blockDim.x, false);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- MFMA path --
+// One wave computes the 16x16 column tiles jt = jt0, jt0 + jstep, ... of one
+// problem.  TB = ceil(max(m, n, k) / 16) <= 4 bounds the fragment arrays.
+template <int TB, bool VEC>
+GLASS_DEV void mfma_problem(int m, int n, int k, float alpha, const float* __restrict__ Ag,
+                            const float* __restrict__ Bg, float beta, float* __restrict__ Cg, int lane, int jt0,
+                            int jstep) {
+    const int q = lane >> 4, r = lane & 15;
+    const int MT = (m + 15) >> 4, NT = (n + 15) >> 4, KT = (k + 15) >> 4;
+    for (int jt = jt0; jt < NT; jt += jstep) {
+        const int j = jt * 16 + r;
+        float bf[TB][4];
+#pragma unroll
+        for (int kb = 0; kb < TB; ++kb)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int kk = kb * 16 + 4 * q + c;
+                bf[kb][c] = (kb < KT && kk < k && j < n) ? Bg[kk * n + j] : 0.f;
+            }
+        for (int it = 0; it < MT; ++it) {
+            const int i = it * 16 + r;
+            float af[TB][4];
+#pragma unroll
+            for (int kb = 0; kb < TB; ++kb) {
+                const int k0 = kb * 16 + 4 * q;
+                if (VEC) {
+                    floatx4 v = {0.f, 0.f, 0.f, 0.f};
+                    if (kb < KT && i < m && k0 < k) v = *reinterpret_cast<const floatx4*>(Ag + i * k + k0);
+                    af[kb][0] = v[0];
+                    af[kb][1] = v[1];
+                    af[kb][2] = v[2];
+                    af[kb][3] = v[3];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        af[kb][c] = (kb < KT && i < m && k0 + c < k) ? Ag[i * k + k0 + c] : 0.f;
+                }
+            }
+            floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < TB; ++kb) {
+                if (kb < KT) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[kb][c], bf[kb][c], acc, 0, 0, 0);
+                }
+            }
+            if (j < n) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = it * 16 + 4 * q + e;
+                    if (row < m) {
+                        float out = alpha * acc[e];
+                        if (beta != 0.f) out = fmaf(beta, Cg[row * n + j], out);
+                        Cg[row * n + j] = out;
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int TB, bool VEC>
+__global__ void __launch_bounds__(512) gemm_mfma_wave(int m, int n, int k, int batch, float alpha,
+                                                      const float* __restrict__ A, const float* __restrict__ B,
+                                                      float beta, float* __restrict__ C) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
+    if (p >= batch) return;
+    mfma_problem<TB, VEC>(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lane, 0, 1);
+}
+
+template <int TB, bool VEC>
+__global__ void __launch_bounds__(256) gemm_mfma_wg(int m, int n, int k, int batch, int pack, float alpha,
+                                                    const float* __restrict__ A, const float* __restrict__ B,
+                                                    float beta, float* __restrict__ C) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int q = 0; q < pack; ++q) {
+        const long long p = (long long)blockIdx.x * pack + q;
+        if (p >= batch) break;
+        mfma_problem<TB, VEC>(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lane, w, nw);
+    }
+}
+
+#define GLASS_CASES_1_12(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
+
+}  // namespace
+
+int launch_gemm(const Shape& sh, const Geometry& g, int batch, float alpha, const float* A, const float* B,
+                float beta, float* C, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const int m = sh.m, n = sh.n, k = sh.k;
+    dim3 grid((unsigned)g.grid), block(g.threads);
+    if (g.scope == GLASS_SCOPE_THREAD) {
+        switch (n) {
+#define X(N) \
+    case N: hipLaunchKernelGGL(gemm_thread<N>, grid, block, g.lds_bytes, st, batch, alpha, A, B, beta, C); break;
+            GLASS_CASES_1_12(X)
+#undef X
+        default: return (int)hipErrorInvalidValue;
+        }
+        return (int)hipGetLastError();
+    }
+    if (!gemm_uses_mfma(sh)) {
+        if (g.scope == GLASS_SCOPE_WAVE)
+            hipLaunchKernelGGL(gemm_small_wave, grid, block, g.lds_bytes, st, m, n, k, batch, alpha, A, B, beta, C,
+                               (int)region_floats(sh));
+        else
+            hipLaunchKernelGGL(gemm_small_wg, grid, block, g.lds_bytes, st, m, n, k, batch, g.pack, alpha, A, B,
+                               beta, C);
+        return (int)hipGetLastError();
+    }
+    int mx = m > n ? m : n;
+    mx = mx > k ? mx : k;
+    const int tb = (mx + 15) / 16;
+    const bool vec = (k % 4 == 0) && ((uintptr_t)A % 16 == 0);
+    if (g.scope == GLASS_SCOPE_WAVE) {
+#define X(TB)                                                                                              \
+    case TB:                                                                                               \
+        if (vec)                                                                                           \
+            hipLaunchKernelGGL((gemm_mfma_wave<TB, true>), grid, block, 0, st, m, n, k, batch, alpha, A, B, \
+                               beta, C);                                                                   \
+        else                                                                                               \
+            hipLaunchKernelGGL((gemm_mfma_wave<TB, false>), grid, block, 0, st, m, n, k, batch, alpha, A,  \
+                               B, beta, C);                                                                \
+        break;
+        switch (tb) {
+            X(1) X(2) X(3) X(4)
+        default: return (int)hipErrorInvalidValue;
+        }
+#undef X
+    } else {
+#define X(TB)                                                                                                 \
+    case TB:                                                                                                  \
+        if (vec)                                                                                              \
+            hipLaunchKernelGGL((gemm_mfma_wg<TB, true>), grid, block, 0, st, m, n, k, batch, g.pack, alpha, A, \
+                               B, beta, C);                                                                   \
+        else                                                                                                  \
+            hipLaunchKernelGGL((gemm_mfma_wg<TB, false>), grid, block, 0, st, m, n, k, batch, g.pack, alpha,  \
+                               A, B, beta, C);                                                                \
+        break;
+        switch (tb) {
+            X(1) X(2) X(3) X(4)
+        default: return (int)hipErrorInvalidValue;
+        }
+#undef X
+    }
+    return (int)hipGetLastError();
+}
+
+}  // namespace glass

@@ -1,0 +1,169 @@
+// glass_internal.hpp -- host-side contract between the C-ABI layer and the
+// kernel launchers: placement geometry, LDS budgets and the feasibility rule.
+// Both the dispatcher (api.cpp) and the launchers (*.hip) size everything from
+// the functions below, so a placement judged feasible is exactly what runs.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/glass.h"
+
+namespace glass {
+
+constexpr int kMaxN = 64;
+constexpr int kWave = 64;
+constexpr size_t kLdsBudgetBytes = 65536;  // fixed per-workgroup LDS budget
+constexpr int kThreadMaxN = 16;            // thread scope: problem in one lane's VGPRs
+constexpr int kThreadGemmMaxN = 12;        // thread GEMM holds all of B in VGPRs
+constexpr int kStagePassFloats = 8192;     // thread scope: floats staged per LDS pass
+
+inline int odd_up(int x) { return x | 1; }
+inline int round4(int x) { return (x + 3) & ~3; }
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// Workgroup size of the workgroup scope: 64 * min(4, ceil(n/16)).
+inline int wg_scope_threads(int n) {
+    int w = ceil_div(n, 16);
+    if (w < 1) w = 1;
+    if (w > 4) w = 4;
+    return 64 * w;
+}
+
+// Problems per LDS staging pass of the thread scope (see thread kernels).
+inline int thread_stage_q(int threads, int elems) {
+    int s = odd_up(elems);
+    int q = kStagePassFloats / s;
+    if (q < 1) q = 1;
+    return q < threads ? q : threads;
+}
+
+struct Shape {
+    glass_op_t op;
+    int m, n, k;     // GEMM: C m x n, inner k. GEMV: A m x n. square ops: m=n=k=order
+    int nrhs;        // POTRS / POSV
+    int trans;       // TRSV
+};
+
+struct Geometry {
+    int scope, pack;
+    int threads;           // workgroup size
+    int problems_per_wg;
+    size_t lds_bytes;      // dynamic LDS per workgroup
+    long long grid;        // number of workgroups
+};
+
+inline bool gemm_uses_mfma(const Shape& s) {
+    int mx = s.m > s.n ? s.m : s.n;
+    mx = mx > s.k ? mx : s.k;
+    return mx >= 16;
+}
+
+// LDS floats of one problem region used by the wave and workgroup scopes.
+inline size_t region_floats(const Shape& s) {
+    const int n = s.n;
+    switch (s.op) {
+    case GLASS_OP_POTRF:
+    case GLASS_OP_TRSV:
+        return (size_t)round4(n * odd_up(n)) + kWave;
+    case GLASS_OP_POTRS:
+    case GLASS_OP_POSV:
+        return (size_t)round4(n * odd_up(n)) + (size_t)round4(n * odd_up(s.nrhs)) + kWave;
+    case GLASS_OP_GEMV:
+        return (size_t)round4(s.m * odd_up(n)) + (size_t)round4(n) + 4 * kWave;  // + partial sums
+    case GLASS_OP_GEMM:
+        if (gemm_uses_mfma(s)) return 0;
+        return (size_t)round4(s.m * odd_up(s.k)) + (size_t)round4(s.k * odd_up(s.n));
+    default:
+        return 0;
+    }
+}
+
+// LDS floats of a thread-scope workgroup of `t` lanes.
+inline size_t thread_lds_floats(const Shape& s, int t) {
+    const int n = s.n;
+    const int sz = odd_up(n * n);
+    const size_t pass = (size_t)thread_stage_q(t, n * n) * sz;
+    switch (s.op) {
+    case GLASS_OP_POTRF:
+        return pass;
+    case GLASS_OP_POTRS:
+    case GLASS_OP_POSV: {
+        size_t b = (size_t)t * odd_up(n * s.nrhs);
+        return pass > b ? pass : b;
+    }
+    case GLASS_OP_TRSV: {
+        size_t b = (size_t)t * odd_up(n);
+        return pass > b ? pass : b;
+    }
+    case GLASS_OP_GEMV:
+        return pass + 2 * (size_t)t * odd_up(n);
+    case GLASS_OP_GEMM:
+        return (size_t)t * sz;
+    case GLASS_OP_SE3_COMPOSE:
+        return 2 * (size_t)t * 17;
+    case GLASS_OP_SE3_INVERSE:
+        return (size_t)t * 17;
+    }
+    return 0;
+}
+
+// The feasibility rule and the launch geometry of a placement.  Returns false
+// when the placement cannot run this shape.
+inline bool make_geometry(const Shape& s, int scope, int pack, long long batch, Geometry* g) {
+    if (pack != 1 && pack != 2 && pack != 4 && pack != 8) return false;
+    const bool se3 = s.op == GLASS_OP_SE3_COMPOSE || s.op == GLASS_OP_SE3_INVERSE;
+    Geometry out{};
+    out.scope = scope;
+    out.pack = pack;
+    if (scope == GLASS_SCOPE_THREAD) {
+        if (!se3) {
+            if (s.op == GLASS_OP_GEMM) {
+                if (!(s.m == s.n && s.n == s.k) || s.n > kThreadGemmMaxN) return false;
+            } else if (s.op == GLASS_OP_GEMV) {
+                if (s.m != s.n || s.n > kThreadMaxN) return false;
+            } else if (s.n > kThreadMaxN) {
+                return false;
+            }
+        }
+        out.threads = kWave * pack;
+        out.problems_per_wg = out.threads;
+        out.lds_bytes = thread_lds_floats(s, out.threads) * sizeof(float);
+    } else if (scope == GLASS_SCOPE_WAVE) {
+        out.threads = kWave * pack;
+        out.problems_per_wg = pack;
+        out.lds_bytes = region_floats(s) * pack * sizeof(float);
+    } else if (scope == GLASS_SCOPE_WORKGROUP) {
+        int order = s.n;
+        if (s.op == GLASS_OP_GEMM || s.op == GLASS_OP_GEMV) {
+            order = s.m > order ? s.m : order;
+            if (s.op == GLASS_OP_GEMM) order = s.k > order ? s.k : order;
+        }
+        out.threads = se3 ? kWave : wg_scope_threads(order);
+        out.problems_per_wg = pack;
+        out.lds_bytes = region_floats(s) * sizeof(float);
+    } else {
+        return false;
+    }
+    if (out.lds_bytes > kLdsBudgetBytes) return false;
+    out.grid = batch > 0 ? (batch + out.problems_per_wg - 1) / out.problems_per_wg : 0;
+    if (g) *g = out;
+    return true;
+}
+
+// Kernel launchers (defined in the .hip files).  Each assumes a validated
+// shape and a geometry produced by make_geometry for it; returns hipSuccess
+// or the launch error as int.
+int launch_gemm(const Shape& s, const Geometry& g, int batch, float alpha, const float* A,
+                const float* B, float beta, float* C, void* stream);
+int launch_gemv(const Shape& s, const Geometry& g, int batch, float alpha, const float* A,
+                const float* x, float beta, float* y, void* stream);
+int launch_potrf(const Shape& s, const Geometry& g, int batch, float* A, int32_t* info, void* stream);
+int launch_potrs(const Shape& s, const Geometry& g, int batch, const float* L, float* B, void* stream);
+int launch_posv(const Shape& s, const Geometry& g, int batch, float* A, float* B, int32_t* info,
+                void* stream);
+int launch_trsv(const Shape& s, const Geometry& g, int batch, const float* L, float* x, void* stream);
+int launch_se3(const Shape& s, const Geometry& g, int batch, const float* Ta, const float* Tb,
+               float* Tout, void* stream);
+
+}  // namespace glass

@@ -1,0 +1,121 @@
+"""Host-side checks of the C-ABI that need no GPU: the library loads and
+exports every function include/glass.h declares, argument validation returns
+the documented status without touching the device, the advisor's lookup rule
+matches an independent re-implementation over the shipped table, and the
+feasibility rule has the documented shape."""
+from __future__ import annotations
+
+import os
+import re
+
+import pytest
+
+import oracle.placement_ref as pref
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "glass.h")
+
+
+@pytest.fixture(scope="module")
+def glass():
+    from paper_2609_28179_amd import glass as g
+    return g
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(glass_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(glass):
+    names = declared_functions()
+    assert len(names) >= 11
+    for name in names:
+        assert hasattr(glass._lib, name), name
+    assert set(names) == set(glass.EXPORTED)
+
+
+FAKE = 0x10000  # never dereferenced: every call below fails validation first
+
+
+def test_validation_paths(glass):
+    g = glass
+    S = 0  # explicit NULL stream: no torch stream lookup on a machine without GPU
+    assert g.glass_posv_batched(0, 1, 4, FAKE, FAKE, None, stream=S) == g.ERR_UNSUPPORTED
+    assert g.glass_posv_batched(65, 1, 4, FAKE, FAKE, None, stream=S) == g.ERR_UNSUPPORTED
+    assert g.glass_posv_batched(6, 0, 4, FAKE, FAKE, None, stream=S) == g.ERR_UNSUPPORTED
+    assert g.glass_posv_batched(6, 65, 4, FAKE, FAKE, None, stream=S) == g.ERR_UNSUPPORTED
+    assert g.glass_posv_batched(6, 1, -1, FAKE, FAKE, None, stream=S) == g.ERR_INVALID_VALUE
+    assert g.glass_posv_batched(6, 1, 0, None, None, None, stream=S) == g.OK
+    assert g.glass_posv_batched(6, 1, 3, None, FAKE, None, stream=S) == g.ERR_INVALID_VALUE
+    assert g.glass_potrf_batched(6, 3, None, None, stream=S) == g.ERR_INVALID_VALUE
+    assert g.glass_potrs_batched(6, 1, 3, FAKE, None, stream=S) == g.ERR_INVALID_VALUE
+    assert g.glass_trsv_batched(6, 3, 2, FAKE, FAKE, stream=S) == g.ERR_INVALID_VALUE
+    assert g.glass_trsv_batched(6, 3, 0, None, FAKE, stream=S) == g.ERR_INVALID_VALUE
+    assert g.glass_gemm_batched(6, 70, 6, 3, 1.0, FAKE, FAKE, 0.0, FAKE, stream=S) == g.ERR_UNSUPPORTED
+    assert g.glass_gemm_batched(6, 6, 6, 3, 1.0, FAKE, None, 0.0, FAKE, stream=S) == g.ERR_INVALID_VALUE
+    assert g.glass_gemv_batched(6, 6, 3, 1.0, FAKE, FAKE, 0.0, None, stream=S) == g.ERR_INVALID_VALUE
+    assert g.glass_se3_batched(g.OP_GEMM, 3, FAKE, FAKE, FAKE, stream=S) == g.ERR_INVALID_VALUE
+    assert g.glass_se3_batched(g.OP_SE3_COMPOSE, 3, FAKE, None, FAKE, stream=S) == g.ERR_INVALID_VALUE
+    assert g.glass_se3_batched(g.OP_SE3_INVERSE, 0, None, None, None, stream=S) == g.OK
+    # forced placements: bad enum values are invalid, impossible ones infeasible
+    assert g.glass_potrf_batched(6, 3, FAKE, None, force=(5, 1), stream=S) == g.ERR_INVALID_VALUE
+    assert g.glass_potrf_batched(6, 3, FAKE, None, force=("wave", 3), stream=S) == g.ERR_INVALID_VALUE
+    assert g.glass_potrf_batched(32, 3, FAKE, None, force=("thread", 1), stream=S) == g.ERR_INFEASIBLE_PLACEMENT
+    assert g.glass_gemm_batched(4, 5, 4, 3, 1.0, FAKE, FAKE, 0.0, FAKE, force=("thread", 1), stream=S) \
+        == g.ERR_INFEASIBLE_PLACEMENT
+    for s in (0, -1, -2, -3, -4):
+        assert g.status_string(s).startswith("GLASS_")
+
+
+def test_query_placement_matches_reference_lookup(glass):
+    table = pref.load_table(os.path.join(ROOT, "paper_2609_28179_amd", "csrc", "glass_table_gfx950.inc"))
+    batches = [1, 2, 3, 4, 5, 8, 15, 16, 17, 63, 64, 65, 255, 256, 257, 1000, 1024, 1025, 4095, 4096,
+               4097, 16384, 16385, 30000, 65535, 65536, 65537, 1 << 20]
+    for opname, op in glass.OPS.items():
+        for n in range(1, 65):
+            for b in batches:
+                got = glass.glass_query_placement(op, n, b)
+                scope, pack = pref.lookup(table, op, n, b)
+                if glass.glass_placement_feasible(op, n, 1, scope, pack) != 1:
+                    scope, pack = glass.SCOPE_WAVE, 1
+                assert (got.scope, got.pack) == (scope, pack), (opname, n, b)
+                assert got.problems_per_wg == (64 * pack if scope == 0 else pack)
+    with pytest.raises(glass.GlassError):
+        glass.glass_query_placement(glass.OP_POSV, 0, 16)
+    with pytest.raises(glass.GlassError):
+        glass.glass_query_placement(glass.OP_POSV, 8, 0)
+
+
+def test_batch_key_rule_examples():
+    keys = [1, 16, 256, 4096, 65536]
+    # geometric midpoint of 16 and 256 is 64: ties go to the smaller key
+    assert pref.batch_key(keys, 64) == 16
+    assert pref.batch_key(keys, 65) == 256
+    assert pref.batch_key(keys, 4) == 1
+    assert pref.batch_key(keys, 5) == 16
+    assert pref.batch_key(keys, 1 << 30) == 65536
+    assert pref.n_key([3, 4, 6, 7, 12, 16, 32, 64], 1) == 3
+    assert pref.n_key([3, 4, 6, 7, 12, 16, 32, 64], 13) == 16
+    assert pref.n_key([3, 4, 6, 7, 12, 16, 32, 64], 33) == 64
+
+
+def test_feasibility_rule_shape(glass):
+    g = glass
+    for op in ("potrf", "posv", "potrs", "trsv", "gemv"):
+        assert g.glass_placement_feasible(g.OPS[op], 16, 1, g.SCOPE_THREAD, 1) == 1
+        assert g.glass_placement_feasible(g.OPS[op], 17, 1, g.SCOPE_THREAD, 1) == 0
+    assert g.glass_placement_feasible(g.OP_GEMM, 12, 1, g.SCOPE_THREAD, 1) == 1
+    assert g.glass_placement_feasible(g.OP_GEMM, 13, 1, g.SCOPE_THREAD, 1) == 0
+    for op in g.OPS.values():
+        for n in range(1, 65):
+            # the table fallback must always be runnable
+            assert g.glass_placement_feasible(op, n, 1, g.SCOPE_WAVE, 1) == 1
+            assert g.glass_placement_feasible(op, n, 64, g.SCOPE_WAVE, 1) == 1
+            assert g.glass_placement_feasible(op, n, 1, g.SCOPE_WORKGROUP, 8) == 1
+            # monotone in n: feasible at n implies feasible below n
+            for scope in range(3):
+                for pack in (1, 2, 4, 8):
+                    if n > 1 and g.glass_placement_feasible(op, n, 1, scope, pack) == 1:
+                        assert g.glass_placement_feasible(op, n - 1, 1, scope, pack) == 1
