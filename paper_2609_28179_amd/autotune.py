@@ -1,0 +1,214 @@
+"""Offline placement sweep and static-table emission (Sec. III-A: measure once
+on the target GPU, store the choice in an architecture-specific table;
+Sec. IV-A: paired randomized rounds, fresh inputs for destructive ops, raw
+samples kept, a 5 % dispatch margin).
+
+  python -m paper_2609_28179_amd.autotune sweep [--rounds 20] [--out FILE]
+  python -m paper_2609_28179_amd.autotune emit  [--sweep FILE] [--out INC]
+  python -m paper_2609_28179_amd.autotune summary [--sweep FILE]
+
+The sweep covers the 250 cells {GEMM, GEMV, POTRF, POTRS, POSV, TRSV} x
+n in {3,4,6,7,12,16,32,64} x batch in {1,16,256,4096,65536} plus SE(3)
+compose / inverse x batch, each at every feasible (scope, pack).  It appends
+one JSON record per (cell, placement) and resumes by skipping cells already
+complete.  The winner of a cell is the placement with the smallest median;
+exact ties go to thread < wave < workgroup, then to the smaller pack.  The
+placements within 5 % of the winner form the cell's margin set.
+"""
+from __future__ import annotations
+
+import argparse
+import datetime
+import json
+import os
+import random
+import subprocess
+import sys
+
+import numpy as np
+
+from . import timing
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_SWEEP = os.path.join(PKG, "tuning", "sweep_gfx950.jsonl")
+DEFAULT_INC = os.path.join(PKG, "csrc", "glass_table_gfx950.inc")
+OP_ORDER = ("gemm", "gemv", "potrf", "potrs", "posv", "trsv", "se3_compose", "se3_inverse")
+MARGIN = 1.05
+
+
+def _git_hash():
+    try:
+        return subprocess.check_output(["git", "rev-parse", "--short", "HEAD"], cwd=PKG,
+                                       stderr=subprocess.DEVNULL).decode().strip()
+    except Exception:
+        return "unknown"
+
+
+def load(path):
+    meta, recs = None, []
+    if not os.path.exists(path):
+        return meta, recs
+    for line in open(path):
+        line = line.strip()
+        if not line:
+            continue
+        r = json.loads(line)
+        if r.get("kind") == "meta":
+            meta = r
+        else:
+            recs.append(r)
+    return meta, recs
+
+
+def sweep(args):
+    import torch
+    from . import glass
+
+    dev = torch.device("cuda:0")
+    os.makedirs(os.path.dirname(args.out), exist_ok=True)
+    meta, recs = load(args.out)
+    done = {(r["op"], r["n"], r["batch"]) for r in recs}
+    cells = timing.sweep_cells()
+    if args.ops:
+        cells = [c for c in cells if c[0] in args.ops.split(",")]
+    if args.max_batch:
+        cells = [c for c in cells if c[2] <= args.max_batch]
+    with open(args.out, "a") as f:
+        if meta is None:
+            p = torch.cuda.get_device_properties(0)
+            meta = {"kind": "meta", "gpu": p.name, "arch": p.gcnArchName, "cus": p.multi_processor_count,
+                    "torch": torch.__version__, "hip": torch.version.hip, "git": _git_hash(),
+                    "date": datetime.datetime.utcnow().isoformat(timespec="seconds"),
+                    "floor_us": timing.floor_us(torch, dev), "copy_gbps": timing.copy_bandwidth(torch, dev),
+                    "rounds": args.rounds, "protocol": "graph of S launches per sample, S sets >= 1 GiB"}
+            f.write(json.dumps(meta) + "\n")
+            f.flush()
+            print(f"floor {meta['floor_us']:.2f} us, copy {meta['copy_gbps']:.0f} GB/s", flush=True)
+        rng = random.Random(args.seed)
+        for ci, (op, n, batch) in enumerate(cells):
+            if (op, n, batch) in done:
+                continue
+            pls = timing.feasible_placements(glass, op, n)
+            cell = timing.Cell(torch, op, n, batch, dev, seed=1000 + ci)
+            samples = timing.time_cell(glass, torch, cell, pls, rounds=args.rounds, warmup=args.warmup, rng=rng)
+            ab = timing.alg_bytes(op, n) * batch
+            best = None
+            for (scope, pack), s in samples.items():
+                med = float(np.median(s))
+                rec = {"op": op, "n": n, "batch": batch, "scope": scope, "pack": pack, "nsets": cell.nsets,
+                       "set_bytes": cell.set_bytes, "alg_bytes": ab, "median_us": med,
+                       "p25_us": float(np.percentile(s, 25)), "p75_us": float(np.percentile(s, 75)),
+                       "gbps": ab / (med * 1e-6) / 1e9, "samples_us": [round(v, 4) for v in s]}
+                f.write(json.dumps(rec) + "\n")
+                if best is None or med < best[0]:
+                    best = (med, scope, pack)
+            f.flush()
+            print(f"[{ci + 1}/{len(cells)}] {op} n={n} batch={batch}: best {glass.SCOPE_NAMES[best[1]]}/P={best[2]} "
+                  f"{best[0]:.2f} us ({ab / (best[0] * 1e-6) / 1e9:.0f} GB/s) over {len(pls)} placements",
+                  flush=True)
+            del cell
+            torch.cuda.empty_cache()
+
+
+def choose(recs):
+    """Per cell: (winner (scope, pack), median, margin set, all medians)."""
+    by_cell = {}
+    for r in recs:
+        by_cell.setdefault((r["op"], r["n"], r["batch"]), {})[(r["scope"], r["pack"])] = r["median_us"]
+    out = {}
+    for cell, meds in by_cell.items():
+        order = sorted(meds.items(), key=lambda kv: (kv[1], kv[0][0], kv[0][1]))
+        (win, wmed) = order[0]
+        margin = sorted(pl for pl, m in meds.items() if m <= wmed * MARGIN)
+        out[cell] = {"winner": win, "median_us": wmed, "margin": margin, "medians": meds}
+    return out
+
+
+def emit(args):
+    meta, recs = load(args.sweep)
+    ch = choose(recs)
+    nk, bk = timing.SWEEP_N, timing.SWEEP_B
+    lines = []
+    missing = 0
+    for op in OP_ORDER:
+        rows = []
+        for n in nk:
+            ents = []
+            for b in bk:
+                key = (op, 4 if op.startswith("se3") else n, b)
+                if key in ch:
+                    s, p = ch[key]["winner"]
+                else:
+                    s, p = 1, 1
+                    missing += 1
+                ents.append("{%d, %d}" % (s, p))
+            rows.append("{" + ", ".join(ents) + "}")
+        lines.append("    {  // %s\n        " % op + ",\n        ".join(rows) + "}")
+    prov = (f"gfx950 / {meta.get('gpu', '?')} / torch {meta.get('torch', '?')} hip {meta.get('hip', '?')} / "
+            f"git {meta.get('git', '?')} / sweep {meta.get('date', '?')} / {len(ch)} cells"
+            if meta else "gfx950 / no sweep")
+    text = (
+        "// glass_table_gfx950.inc -- measured placement table for gfx950, generated by\n"
+        "// paper_2609_28179_amd/autotune.py emit from the sweep records in\n"
+        "// paper_2609_28179_amd/tuning/sweep_gfx950.jsonl.  Do not edit by hand.\n"
+        "// Layout: kPlace[op][n_index][batch_index] = {scope, pack}; scope 0 thread,\n"
+        "// 1 wave, 2 workgroup.  The SE(3) rows repeat across n (n does not apply).\n"
+        f"static const char kTableProvenance[] = \"{prov}\";\n"
+        f"static const int kTableN[{len(nk)}] = {{{', '.join(map(str, nk))}}};\n"
+        f"static const int kTableB[{len(bk)}] = {{{', '.join(map(str, bk))}}};\n"
+        f"static const unsigned char kPlace[8][{len(nk)}][{len(bk)}][2] = {{\n" + ",\n".join(lines) + "\n};\n")
+    with open(args.out, "w") as f:
+        f.write(text)
+    print(f"wrote {args.out} ({len(ch)} measured cells, {missing} defaulted)")
+
+
+def summary(args):
+    meta, recs = load(args.sweep)
+    ch = choose(recs)
+    ratios, gaps, lines = [], [], []
+    for (op, n, b), c in sorted(ch.items(), key=lambda kv: (OP_ORDER.index(kv[0][0]), kv[0][1], kv[0][2])):
+        meds = c["medians"]
+        fixed = meds.get((1, 1))
+        worst = max(meds.values())
+        ratios.append(fixed / c["median_us"])
+        gaps.append(worst / c["median_us"])
+        ab = timing.alg_bytes(op, n) * b
+        lines.append(f"| {op} | {n} | {b} | {'TWG'[c['winner'][0]]}{c['winner'][1]} | {c['median_us']:.2f} | "
+                     f"{fixed:.2f} | {fixed / c['median_us']:.2f} | {worst / c['median_us']:.1f} | "
+                     f"{ab / (c['median_us'] * 1e-6) / 1e9:.0f} | {len(c['margin'])} |")
+    g = lambda v: float(np.exp(np.mean(np.log(v))))
+    head = [f"floor {meta['floor_us']:.2f} us/launch, copy {meta['copy_gbps']:.0f} GB/s" if meta else "",
+            f"cells {len(ch)}; tuned / fixed-wave(P=1) speedup: geomean {g(ratios):.2f}x, max {max(ratios):.1f}x; "
+            f"best/worst placement gap: median {np.median(gaps):.1f}x, max {max(gaps):.1f}x",
+            "",
+            "| op | n | batch | tuned | tuned us | wave/P1 us | speedup | worst/best | alg GB/s | margin set |",
+            "|---|---|---|---|---|---|---|---|---|---|"]
+    text = "\n".join(head + lines) + "\n"
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    print(text)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("sweep")
+    s.add_argument("--out", default=DEFAULT_SWEEP)
+    s.add_argument("--rounds", type=int, default=20)
+    s.add_argument("--warmup", type=int, default=3)
+    s.add_argument("--seed", type=int, default=0)
+    s.add_argument("--ops", default="")
+    s.add_argument("--max-batch", type=int, default=0)
+    e = sub.add_parser("emit")
+    e.add_argument("--sweep", default=DEFAULT_SWEEP)
+    e.add_argument("--out", default=DEFAULT_INC)
+    m = sub.add_parser("summary")
+    m.add_argument("--sweep", default=DEFAULT_SWEEP)
+    m.add_argument("--out", default="")
+    args = ap.parse_args(argv)
+    {"sweep": sweep, "emit": emit, "summary": summary}[args.cmd](args)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -16,9 +16,10 @@
 //             resident in LDS, cooperative right-looking updates separated
 //             by workgroup barriers; P problems back to back.
 //
-// Arithmetic: FP32, fused multiply-add, correctly rounded sqrtf; a division
-// by a diagonal entry is done as a multiply by its reciprocal.  The failure
-// test is !(pivot > 0), as in the definition of info in glass.h.
+// Arithmetic: FP32 with fused multiply-adds.  A pivot d gives inv = rsq(d)
+// (v_rsq_f32) and L_jj = d * inv; divisions by a diagonal entry are multiplies
+// by its reciprocal.  The failure test is !(pivot > 0), as in the definition
+// of info in glass.h.
 #include "device_common.hpp"
 #include "glass_internal.hpp"
 
@@ -61,8 +62,8 @@ GLASS_DEV int tri_potrf(float (&a)[N * (N + 1) / 2], float (&dinv)[N]) {
 #pragma unroll
         for (int p = 0; p < j; ++p) s = fmaf(-a[TI(j, p)], a[TI(j, p)], s);
         if (!(s > 0.f) && info == 0) info = j + 1;
-        const float l = sqrtf(s);
-        const float inv = 1.0f / l;
+        const float inv = rsq(s);
+        const float l = s * inv;
         a[TI(j, j)] = l;
         dinv[j] = inv;
 #pragma unroll
@@ -108,7 +109,7 @@ GLASS_DEV void thread_load_tri(float (&a)[N * (N + 1) / 2], const float* __restr
     const FastDiv fd = make_fastdiv(SZ);
     for (int s = 0; s < cnt; s += Q) {
         const int qn = min(Q, cnt - s);
-        stage_in(lds, base + (size_t)s * SZ, qn * SZ, fd, S, tid, nt);
+        stage_in<(N <= 8 ? 8 : 4)>(lds, base + (size_t)s * SZ, qn * SZ, fd, S, tid, nt);
         __syncthreads();
         if (tid >= s && tid < s + qn) tri_load<N>(a, lds + (tid - s) * S);
         __syncthreads();
@@ -137,7 +138,7 @@ GLASS_DEV void thread_solve_rhs(const float (&a)[N * (N + 1) / 2], const float (
                                 bool active) {
     const int SZ = N * nrhs, S = SZ | 1;
     const FastDiv fd = make_fastdiv(SZ);
-    stage_in(lds, Bg, cnt * SZ, fd, S, tid, nt);
+    stage_in<2>(lds, Bg, cnt * SZ, fd, S, tid, nt);
     __syncthreads();
     if (active) {
         float* b = lds + tid * S;
@@ -222,11 +223,15 @@ __global__ void __launch_bounds__(512) trsv_thread(int trans, int batch, const f
 }
 
 // -------------------------------------------------------------- wave scope --
-// Row `lane` of the staged matrix (lower part only, zeros elsewhere).
+// Row `lane` of the staged matrix, lower part only.  Rows and columns beyond
+// n are padded with an identity block, so factoring all NB columns leaves the
+// leading n x n factor unchanged (every padded pivot is exactly 1 and every
+// padded coupling exactly 0) and the column loop needs no data-dependent exit.
 template <int NB>
 GLASS_DEV void row_load(float (&a)[NB], const float* M, int n, int s, int lane) {
 #pragma unroll
-    for (int j = 0; j < NB; ++j) a[j] = (lane < n && j < n && j <= lane) ? M[lane * s + j] : 0.f;
+    for (int j = 0; j < NB; ++j)
+        a[j] = (lane < n && j < n && j <= lane) ? M[lane * s + j] : (j == lane && j >= n ? 1.f : 0.f);
 }
 
 template <int NB>
@@ -238,17 +243,16 @@ GLASS_DEV void row_store(const float (&a)[NB], float* M, int n, int s, int lane)
     }
 }
 
-// Right-looking wave Cholesky, lane i holding row i; returns info.
+// Right-looking wave Cholesky, lane i holding row i (identity-padded to NB by
+// row_load); returns info.
 template <int NB>
-GLASS_DEV int wave_potrf(float (&a)[NB], float* col, int n, int lane) {
+GLASS_DEV int wave_potrf(float (&a)[NB], float* col, int lane) {
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-        if (j >= n) break;
         const float d = readlane(a[j], j);
         if (!(d > 0.f)) return j + 1;
-        const float l = sqrtf(d);
-        const float inv = 1.0f / l;
-        const float v = lane == j ? l : a[j] * inv;
+        const float inv = rsq(d);
+        const float v = lane == j ? d * inv : a[j] * inv;
         a[j] = v;
         col[lane] = v;
         wave_sync();
@@ -298,11 +302,11 @@ __global__ void __launch_bounds__(512) potrf_wave(int n, int batch, float* __res
     float* col = M + ((n * s + 3) & ~3);
     float* Ag = A + p * n * n;
     const FastDiv fd = make_fastdiv(n);
-    stage_in(M, Ag, n * n, fd, s, lane, 64);
+    stage_in<WaveU<NB>::v>(M, Ag, n * n, fd, s, lane, 64);
     wave_sync();
     float a[NB];
     row_load<NB>(a, M, n, s, lane);
-    const int inf = wave_potrf<NB>(a, col, n, lane);
+    const int inf = wave_potrf<NB>(a, col, lane);
     row_store<NB>(a, M, n, s, lane);
     wave_sync();
     stage_out(Ag, M, n * n, fd, s, lane, 64);
@@ -323,12 +327,12 @@ __global__ void __launch_bounds__(512) posv_wave(int n, int nrhs, int batch, flo
     float* Ag = A + p * n * n;
     float* Bg = B + p * n * nrhs;
     const FastDiv fd = make_fastdiv(n), fdb = make_fastdiv(nrhs);
-    stage_in(M, Ag, n * n, fd, s, lane, 64);
-    stage_in(Bm, Bg, n * nrhs, fdb, sb, lane, 64);
+    stage_in<WaveU<NB>::v>(M, Ag, n * n, fd, s, lane, 64);
+    stage_in<2>(Bm, Bg, n * nrhs, fdb, sb, lane, 64);
     wave_sync();
     float a[NB];
     row_load<NB>(a, M, n, s, lane);
-    const int inf = wave_potrf<NB>(a, col, n, lane);
+    const int inf = wave_potrf<NB>(a, col, lane);
     row_store<NB>(a, M, n, s, lane);
     wave_sync();
     stage_out(Ag, M, n * n, fd, s, lane, 64);
@@ -340,6 +344,7 @@ __global__ void __launch_bounds__(512) posv_wave(int n, int nrhs, int batch, flo
     }
 }
 
+template <int U>
 __global__ void __launch_bounds__(512) potrs_wave(int n, int nrhs, int batch, const float* __restrict__ L,
                                                   float* __restrict__ B, int region) {
     extern __shared__ float lds[];
@@ -351,14 +356,15 @@ __global__ void __launch_bounds__(512) potrs_wave(int n, int nrhs, int batch, co
     float* Bm = M + ((n * s + 3) & ~3);
     float* Bg = B + p * n * nrhs;
     const FastDiv fdb = make_fastdiv(nrhs);
-    stage_in(M, L + p * n * n, n * n, make_fastdiv(n), s, lane, 64);
-    stage_in(Bm, Bg, n * nrhs, fdb, sb, lane, 64);
+    stage_in<U>(M, L + p * n * n, n * n, make_fastdiv(n), s, lane, 64);
+    stage_in<2>(Bm, Bg, n * nrhs, fdb, sb, lane, 64);
     wave_sync();
     wave_solve(M, s, Bm, sb, n, nrhs, lane, true, true);
     wave_sync();
     stage_out(Bg, Bm, n * nrhs, fdb, sb, lane, 64);
 }
 
+template <int U>
 __global__ void __launch_bounds__(512) trsv_wave(int n, int trans, int batch, const float* __restrict__ L,
                                                  float* __restrict__ x, int region) {
     extern __shared__ float lds[];
@@ -367,7 +373,7 @@ __global__ void __launch_bounds__(512) trsv_wave(int n, int trans, int batch, co
     if (p >= batch) return;
     float* M = lds + (size_t)w * region;
     const int s = n | 1;
-    stage_in(M, L + p * n * n, n * n, make_fastdiv(n), s, lane, 64);
+    stage_in<U>(M, L + p * n * n, n * n, make_fastdiv(n), s, lane, 64);
     wave_sync();
     const bool row = lane < n;
     float v = row ? x[p * n + lane] : 0.f;
@@ -387,8 +393,8 @@ GLASS_DEV int wg_potrf(float* M, int n, int s, int tid, int nt) {
     for (int j = 0; j < n; ++j) {
         const float d = M[j * s + j];
         if (!(d > 0.f)) return j + 1;
-        const float l = sqrtf(d);
-        const float inv = 1.0f / l;
+        const float inv = rsq(d);
+        const float l = d * inv;
         __syncthreads();
         for (int i = j + tid; i < n; i += nt) M[i * s + j] = i == j ? l : M[i * s + j] * inv;
         __syncthreads();
@@ -455,7 +461,7 @@ __global__ void __launch_bounds__(256) potrf_wg(int n, int batch, int pack, floa
         const long long p = (long long)blockIdx.x * pack + q;
         if (p >= batch) break;
         float* Ag = A + p * n * n;
-        stage_in(lds, Ag, n * n, fd, s, tid, nt);
+        stage_in<4>(lds, Ag, n * n, fd, s, tid, nt);
         __syncthreads();
         const int inf = wg_potrf(lds, n, s, tid, nt);
         wg_zero_upper(lds, n, s, tid, nt);
@@ -478,8 +484,8 @@ __global__ void __launch_bounds__(256) posv_wg(int n, int nrhs, int batch, int p
         if (p >= batch) break;
         float* Ag = A + p * n * n;
         float* Bg = B + p * n * nrhs;
-        stage_in(lds, Ag, n * n, fd, s, tid, nt);
-        stage_in(Bm, Bg, n * nrhs, fdb, sb, tid, nt);
+        stage_in<4>(lds, Ag, n * n, fd, s, tid, nt);
+        stage_in<2>(Bm, Bg, n * nrhs, fdb, sb, tid, nt);
         __syncthreads();
         const int inf = wg_potrf(lds, n, s, tid, nt);
         wg_zero_upper(lds, n, s, tid, nt);
@@ -505,8 +511,8 @@ __global__ void __launch_bounds__(256) potrs_wg(int n, int nrhs, int batch, int 
         const long long p = (long long)blockIdx.x * pack + q;
         if (p >= batch) break;
         float* Bg = B + p * n * nrhs;
-        stage_in(lds, L + p * n * n, n * n, fd, s, tid, nt);
-        stage_in(Bm, Bg, n * nrhs, fdb, sb, tid, nt);
+        stage_in<4>(lds, L + p * n * n, n * n, fd, s, tid, nt);
+        stage_in<2>(Bm, Bg, n * nrhs, fdb, sb, tid, nt);
         __syncthreads();
         wg_solve(lds, s, Bm, sb, n, nrhs, tid, nt, true, true);
         stage_out(Bg, Bm, n * nrhs, fdb, sb, tid, nt);
@@ -524,7 +530,7 @@ __global__ void __launch_bounds__(256) trsv_wg(int n, int trans, int batch, int 
     for (int q = 0; q < pack; ++q) {
         const long long p = (long long)blockIdx.x * pack + q;
         if (p >= batch) break;
-        stage_in(lds, L + p * n * n, n * n, fd, s, tid, nt);
+        stage_in<4>(lds, L + p * n * n, n * n, fd, s, tid, nt);
         for (int i = tid; i < n; i += nt) vm[i] = x[p * n + i];
         __syncthreads();
         wg_solve(lds, s, vm, 1, n, 1, tid, nt, trans == 0, trans != 0);
@@ -539,6 +545,10 @@ __global__ void __launch_bounds__(256) trsv_wg(int n, int trans, int batch, int 
 #define GLASS_BUCKETS(X) X(8) X(16) X(24) X(32) X(40) X(48) X(56) X(64)
 
 inline int bucket8(int n) { return ((n + 7) / 8) * 8; }
+
+// U of stage_in for a wave staging an n x n problem in one chunk.
+inline int wave_u(int n) { return n * n <= 512 ? 2 : n * n <= 1024 ? 4 : n * n <= 2048 ? 8 : 16; }
+#define GLASS_WAVE_U(X) X(2) X(4) X(8) X(16)
 
 inline int finish() { return (int)hipGetLastError(); }
 
@@ -612,7 +622,12 @@ int launch_potrs(const Shape& sh, const Geometry& g, int batch, const float* L, 
         }
     } else if (g.scope == GLASS_SCOPE_WAVE) {
         const int region = (int)region_floats(sh);
-        hipLaunchKernelGGL(potrs_wave, grid, block, g.lds_bytes, st, n, r, batch, L, B, region);
+        switch (wave_u(n)) {
+#define X(U) \
+    case U: hipLaunchKernelGGL(potrs_wave<U>, grid, block, g.lds_bytes, st, n, r, batch, L, B, region); break;
+            GLASS_WAVE_U(X)
+#undef X
+        }
     } else {
         hipLaunchKernelGGL(potrs_wg, grid, block, g.lds_bytes, st, n, r, batch, g.pack, L, B);
     }
@@ -633,7 +648,12 @@ int launch_trsv(const Shape& sh, const Geometry& g, int batch, const float* L, f
         }
     } else if (g.scope == GLASS_SCOPE_WAVE) {
         const int region = (int)region_floats(sh);
-        hipLaunchKernelGGL(trsv_wave, grid, block, g.lds_bytes, st, n, tr, batch, L, x, region);
+        switch (wave_u(n)) {
+#define X(U) \
+    case U: hipLaunchKernelGGL(trsv_wave<U>, grid, block, g.lds_bytes, st, n, tr, batch, L, x, region); break;
+            GLASS_WAVE_U(X)
+#undef X
+        }
     } else {
         hipLaunchKernelGGL(trsv_wg, grid, block, g.lds_bytes, st, n, tr, batch, g.pack, L, x);
     }

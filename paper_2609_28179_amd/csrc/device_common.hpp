@@ -41,46 +41,127 @@ GLASS_DEV float readlane(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-// Copy src[0 .. len) (contiguous, global) into LDS re-laid as rows of
-// `cols.d` floats at row stride `ldst`: element g lands at
-// dst[(g / cols) * ldst + g % cols].  `nt` cooperating lanes, this one is
-// `tid`.  Four loads are issued before their LDS writes.
-GLASS_DEV void stage_in(float* dst, const float* __restrict__ src, int len, FastDiv cols, int ldst,
-                        int tid, int nt) {
-    const int pad = ldst - (int)cols.d;
-    for (int base = 0; base < len; base += 4 * nt) {
-        float v[4];
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+GLASS_DEV bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// Write 4 consecutive span elements starting at element g into the padded
+// LDS layout (rows of cols.d floats at stride ldst).
+GLASS_DEV void lds_put4(float* dst, int g, const f4_t& v, FastDiv cols, int ldst) {
+    int r = (int)fdiv((uint32_t)g, cols), c = g - r * (int)cols.d;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int g = base + u * nt + tid;
-            v[u] = g < len ? src[g] : 0.f;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int g = base + u * nt + tid;
-            if (g < len) dst[g + (int)fdiv((uint32_t)g, cols) * pad] = v[u];
+    for (int e = 0; e < 4; ++e) {
+        dst[r * ldst + c] = v[e];
+        if (++c == (int)cols.d) {
+            c = 0;
+            ++r;
         }
     }
 }
 
-// Inverse of stage_in: dst[g] = src_lds[(g / cols) * ldst + g % cols].
-GLASS_DEV void stage_out(float* __restrict__ dst, const float* src, int len, FastDiv cols, int ldst,
-                         int tid, int nt) {
-    const int pad = ldst - (int)cols.d;
-    for (int g = tid; g < len; g += nt) dst[g] = src[g + (int)fdiv((uint32_t)g, cols) * pad];
+GLASS_DEV f4_t lds_get4(const float* src, int g, FastDiv cols, int ldst) {
+    int r = (int)fdiv((uint32_t)g, cols), c = g - r * (int)cols.d;
+    f4_t v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        v[e] = src[r * ldst + c];
+        if (++c == (int)cols.d) {
+            c = 0;
+            ++r;
+        }
+    }
+    return v;
+}
+
+// Raw buffer descriptor over `bytes` bytes at p (dword 3 = 0x00020000: 32-bit
+// data format, the raw-buffer setting of gfx9-family parts).  Loads outside
+// [0, bytes) return 0 and do not touch memory.
+GLASS_DEV __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+// Copy src[0 .. len) (contiguous, global) into LDS re-laid as rows of
+// `cols.d` floats at row stride `ldst`: element g lands at
+// dst[(g / cols) * ldst + g % cols].  `nt` cooperating lanes, this one is
+// `tid`.  All loads are 16-byte buffer loads from the 16-byte-aligned
+// address at or below src (that block lies in the same page as src, and the
+// up to 12 extra bytes on either side are loaded but never stored), and every
+// lane issues its U loads of a chunk before the first LDS write, so a
+// wavefront keeps U KiB in flight: the staging of a batch span is bandwidth-,
+// not latency-bound.  The per-load offsets are scalar, so the loads in flight
+// cost only their data VGPRs.
+template <int U>
+GLASS_DEV void stage_in(float* dst, const float* __restrict__ src, int len, FastDiv cols, int ldst, int tid,
+                        int nt) {
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(src);
+    const int shift = (int)((addr & 15) >> 2);
+    const float* base_p = reinterpret_cast<const float*>(addr & ~(uintptr_t)15);
+    const int n4 = (shift + len + 3) >> 2;
+    const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(base_p, (uint32_t)n4 * 16u);
+    const int d = (int)cols.d;
+    for (int base = 0; base < n4; base += U * nt) {
+        f4_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            v[u] = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, tid * 16, (base + u * nt) * 16, 0));
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int q = base + u * nt + tid;
+            if (q < n4) {
+                int g = 4 * q - shift;
+                const int g0 = g < 0 ? 0 : g;
+                int r = (int)fdiv((uint32_t)g0, cols), c = g0 - r * d;
+#pragma unroll
+                for (int e = 0; e < 4; ++e, ++g) {
+                    if (g >= 0 && g < len) {
+                        dst[r * ldst + c] = v[u][e];
+                        if (++c == d) {
+                            c = 0;
+                            ++r;
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Loads per lane (U of stage_in) that cover an n x n problem staged by one
+// wavefront in a single chunk, for the largest n of a size bucket.
+template <int NB>
+struct WaveU {
+    static constexpr int v = NB * NB <= 512 ? 2 : NB * NB <= 1024 ? 4 : NB * NB <= 2048 ? 8 : 16;
+};
+
+// Inverse of stage_in: dst[g] = src_lds[(g / cols) * ldst + g % cols], with
+// 16-byte stores when dst is 16-byte aligned.
+GLASS_DEV void stage_out(float* __restrict__ dst, const float* src, int len, FastDiv cols, int ldst, int tid,
+                         int nt) {
+    if (aligned16(dst)) {
+        const int len4 = len >> 2;
+        f4_t* d4 = reinterpret_cast<f4_t*>(dst);
+        for (int q = tid; q < len4; q += nt) d4[q] = lds_get4(src, q * 4, cols, ldst);
+        const int g = (len4 << 2) + tid;
+        if (g < len) dst[g] = src[g + (int)fdiv((uint32_t)g, cols) * (ldst - (int)cols.d)];
+    } else {
+        const int pad = ldst - (int)cols.d;
+        for (int g = tid; g < len; g += nt) dst[g] = src[g + (int)fdiv((uint32_t)g, cols) * pad];
+    }
 }
 
 // stage_out with a BLAS epilogue: dst[g] = v + beta * dst_old[g] (dst_old not
 // read when beta == 0).  `v` already carries alpha.
-GLASS_DEV void stage_out_beta(float* __restrict__ dst, const float* src, int len, FastDiv cols,
-                              int ldst, float beta, int tid, int nt) {
-    const int pad = ldst - (int)cols.d;
+GLASS_DEV void stage_out_beta(float* __restrict__ dst, const float* src, int len, FastDiv cols, int ldst,
+                              float beta, int tid, int nt) {
     if (beta == 0.f) {
-        for (int g = tid; g < len; g += nt) dst[g] = src[g + (int)fdiv((uint32_t)g, cols) * pad];
-    } else {
-        for (int g = tid; g < len; g += nt)
-            dst[g] = fmaf(beta, dst[g], src[g + (int)fdiv((uint32_t)g, cols) * pad]);
+        stage_out(dst, src, len, cols, ldst, tid, nt);
+        return;
     }
+    const int pad = ldst - (int)cols.d;
+    for (int g = tid; g < len; g += nt) dst[g] = fmaf(beta, dst[g], src[g + (int)fdiv((uint32_t)g, cols) * pad]);
 }
+
+// Reciprocal square root of a positive pivot (v_rsq_f32, about 1 ulp).
+GLASS_DEV float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
 }  // namespace glass

@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(512) gemm_thread(int batch, float alpha, const
     const int Q = stage_q(nt, SZ);
     for (int s = 0; s < cnt; s += Q) {
         const int qn = min(Q, cnt - s);
-        stage_in(lds, B + (p0 + s) * SZ, qn * SZ, fd, S, tid, nt);
+        stage_in<(N <= 8 ? 8 : 4)>(lds, B + (p0 + s) * SZ, qn * SZ, fd, S, tid, nt);
         __syncthreads();
         if (tid >= s && tid < s + qn) {
             const float* src = lds + (tid - s) * S;
@@ -53,7 +53,7 @@ __global__ void __launch_bounds__(512) gemm_thread(int batch, float alpha, const
         }
         __syncthreads();
     }
-    stage_in(lds, A + p0 * SZ, cnt * SZ, fd, S, tid, nt);
+    stage_in<(N <= 8 ? 8 : 4)>(lds, A + p0 * SZ, cnt * SZ, fd, S, tid, nt);
     __syncthreads();
     if (tid < cnt) {
         float* a = lds + tid * S;
@@ -81,8 +81,8 @@ GLASS_DEV void gemm_small_problem(int m, int n, int k, float alpha, const float*
                                   int tid, int nt, bool wave) {
     const int sk = k | 1, sn = n | 1;
     float* Bs = As + ((m * sk + 3) & ~3);
-    stage_in(As, Ag, m * k, make_fastdiv(k), sk, tid, nt);
-    stage_in(Bs, Bg, k * n, make_fastdiv(n), sn, tid, nt);
+    stage_in<2>(As, Ag, m * k, make_fastdiv(k), sk, tid, nt);
+    stage_in<2>(Bs, Bg, k * n, make_fastdiv(n), sn, tid, nt);
     if (wave) wave_sync(); else __syncthreads();
     const FastDiv fn = make_fastdiv(n);
     for (int e = tid; e < m * n; e += nt) {
@@ -122,58 +122,74 @@ __global__ void __launch_bounds__(256) gemm_small_wg(int m, int n, int k, int ba
 // ---------------------------------------------------------------- MFMA path --
 // One wave computes the 16x16 column tiles jt = jt0, jt0 + jstep, ... of one
 // problem.  TB = ceil(max(m, n, k) / 16) <= 4 bounds the fragment arrays.
-template <int TB, bool VEC>
+// Every A and B fragment the wave needs is loaded before the first MFMA, so
+// all of a problem's loads are in flight together.  JJ bounds the number of
+// column tiles one wave owns (TB at wave scope, 1 at workgroup scope where
+// the T(n)/64 waves split the ceil(n/16) <= T(n)/64 column tiles).
+template <int TB, bool VEC, int JJ>
 GLASS_DEV void mfma_problem(int m, int n, int k, float alpha, const float* __restrict__ Ag,
                             const float* __restrict__ Bg, float beta, float* __restrict__ Cg, int lane, int jt0,
                             int jstep) {
     const int q = lane >> 4, r = lane & 15;
     const int MT = (m + 15) >> 4, NT = (n + 15) >> 4, KT = (k + 15) >> 4;
-    for (int jt = jt0; jt < NT; jt += jstep) {
-        const int j = jt * 16 + r;
-        float bf[TB][4];
+    float af[TB][TB][4];
+#pragma unroll
+    for (int it = 0; it < TB; ++it) {
+        const int i = it * 16 + r;
+#pragma unroll
+        for (int kb = 0; kb < TB; ++kb) {
+            const int k0 = kb * 16 + 4 * q;
+            const bool in = it < MT && kb < KT && i < m;
+            if (VEC) {
+                floatx4 v = {0.f, 0.f, 0.f, 0.f};
+                if (in && k0 < k) v = *reinterpret_cast<const floatx4*>(Ag + i * k + k0);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) af[it][kb][c] = v[c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) af[it][kb][c] = (in && k0 + c < k) ? Ag[i * k + k0 + c] : 0.f;
+            }
+        }
+    }
+    float bf[JJ][TB][4];
+#pragma unroll
+    for (int jj = 0; jj < JJ; ++jj) {
+        const int j = (jt0 + jj * jstep) * 16 + r;
 #pragma unroll
         for (int kb = 0; kb < TB; ++kb)
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int kk = kb * 16 + 4 * q + c;
-                bf[kb][c] = (kb < KT && kk < k && j < n) ? Bg[kk * n + j] : 0.f;
+                bf[jj][kb][c] = (kb < KT && kk < k && j < n) ? Bg[kk * n + j] : 0.f;
             }
-        for (int it = 0; it < MT; ++it) {
-            const int i = it * 16 + r;
-            float af[TB][4];
+    }
 #pragma unroll
-            for (int kb = 0; kb < TB; ++kb) {
-                const int k0 = kb * 16 + 4 * q;
-                if (VEC) {
-                    floatx4 v = {0.f, 0.f, 0.f, 0.f};
-                    if (kb < KT && i < m && k0 < k) v = *reinterpret_cast<const floatx4*>(Ag + i * k + k0);
-                    af[kb][0] = v[0];
-                    af[kb][1] = v[1];
-                    af[kb][2] = v[2];
-                    af[kb][3] = v[3];
-                } else {
+    for (int jj = 0; jj < JJ; ++jj) {
+        const int jt = jt0 + jj * jstep;
+        const int j = jt * 16 + r;
+        if (jt < NT) {
 #pragma unroll
-                    for (int c = 0; c < 4; ++c)
-                        af[kb][c] = (kb < KT && i < m && k0 + c < k) ? Ag[i * k + k0 + c] : 0.f;
-                }
-            }
-            floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+            for (int it = 0; it < TB; ++it) {
+                if (it < MT) {
+                    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int kb = 0; kb < TB; ++kb) {
-                if (kb < KT) {
+                    for (int kb = 0; kb < TB; ++kb) {
+                        if (kb < KT) {
 #pragma unroll
-                    for (int c = 0; c < 4; ++c)
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[kb][c], bf[kb][c], acc, 0, 0, 0);
-                }
-            }
-            if (j < n) {
+                            for (int c = 0; c < 4; ++c)
+                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[it][kb][c], bf[jj][kb][c], acc, 0, 0, 0);
+                        }
+                    }
+                    if (j < n) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int row = it * 16 + 4 * q + e;
-                    if (row < m) {
-                        float out = alpha * acc[e];
-                        if (beta != 0.f) out = fmaf(beta, Cg[row * n + j], out);
-                        Cg[row * n + j] = out;
+                        for (int e = 0; e < 4; ++e) {
+                            const int row = it * 16 + 4 * q + e;
+                            if (row < m) {
+                                float out = alpha * acc[e];
+                                if (beta != 0.f) out = fmaf(beta, Cg[row * n + j], out);
+                                Cg[row * n + j] = out;
+                            }
+                        }
                     }
                 }
             }
@@ -188,7 +204,7 @@ __global__ void __launch_bounds__(512) gemm_mfma_wave(int m, int n, int k, int b
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
-    mfma_problem<TB, VEC>(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lane, 0, 1);
+    mfma_problem<TB, VEC, TB>(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lane, 0, 1);
 }
 
 template <int TB, bool VEC>
@@ -199,7 +215,7 @@ __global__ void __launch_bounds__(256) gemm_mfma_wg(int m, int n, int k, int bat
     for (int q = 0; q < pack; ++q) {
         const long long p = (long long)blockIdx.x * pack + q;
         if (p >= batch) break;
-        mfma_problem<TB, VEC>(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lane, w, nw);
+        mfma_problem<TB, VEC, 1>(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lane, w, nw);
     }
 }
 

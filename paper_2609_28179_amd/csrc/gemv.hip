@@ -31,7 +31,7 @@ __global__ void __launch_bounds__(512) gemv_thread(int batch, float alpha, const
     float* xs = lds + Q * S;
     float* ys = xs + nt * SV;
     const FastDiv fv = make_fastdiv(N);
-    stage_in(xs, x + p0 * N, cnt * N, fv, SV, tid, nt);
+    stage_in<2>(xs, x + p0 * N, cnt * N, fv, SV, tid, nt);
     __syncthreads();
     float xr[N];
     if (tid < cnt) {
@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(512) gemv_thread(int batch, float alpha, const
     const FastDiv fa = make_fastdiv(SZ);
     for (int s = 0; s < cnt; s += Q) {
         const int qn = min(Q, cnt - s);
-        stage_in(lds, A + (p0 + s) * SZ, qn * SZ, fa, S, tid, nt);
+        stage_in<(N <= 8 ? 8 : 4)>(lds, A + (p0 + s) * SZ, qn * SZ, fa, S, tid, nt);
         __syncthreads();
         if (tid >= s && tid < s + qn) {
             const float* a = lds + (tid - s) * S;
@@ -58,6 +58,7 @@ __global__ void __launch_bounds__(512) gemv_thread(int batch, float alpha, const
     stage_out_beta(y + p0 * N, ys, cnt * N, fv, SV, beta, tid, nt);
 }
 
+template <int U>
 __global__ void __launch_bounds__(512) gemv_wave(int m, int n, int batch, float alpha, const float* __restrict__ A,
                                                  const float* __restrict__ x, float beta, float* __restrict__ y,
                                                  int region) {
@@ -68,7 +69,7 @@ __global__ void __launch_bounds__(512) gemv_wave(int m, int n, int batch, float 
     float* As = lds + (size_t)w * region;
     const int s = n | 1;
     float* xs = As + ((m * s + 3) & ~3);
-    stage_in(As, A + p * m * n, m * n, make_fastdiv(n), s, lane, 64);
+    stage_in<U>(As, A + p * m * n, m * n, make_fastdiv(n), s, lane, 64);
     for (int j = lane; j < n; j += 64) xs[j] = x[p * n + j];
     wave_sync();
     if (lane < m) {
@@ -93,7 +94,7 @@ __global__ void __launch_bounds__(256) gemv_wg(int m, int n, int batch, int pack
     for (int q = 0; q < pack; ++q) {
         const long long p = (long long)blockIdx.x * pack + q;
         if (p >= batch) break;
-        stage_in(lds, A + p * m * n, m * n, fd, s, tid, nt);
+        stage_in<4>(lds, A + p * m * n, m * n, fd, s, tid, nt);
         for (int j = tid; j < n; j += nt) xs[j] = x[p * n + j];
         __syncthreads();
         if (row < m) {
@@ -128,8 +129,17 @@ int launch_gemv(const Shape& sh, const Geometry& g, int batch, float alpha, cons
         default: return (int)hipErrorInvalidValue;
         }
     } else if (g.scope == GLASS_SCOPE_WAVE) {
-        hipLaunchKernelGGL(gemv_wave, grid, block, g.lds_bytes, st, sh.m, sh.n, batch, alpha, A, x, beta, y,
-                           (int)region_floats(sh));
+        const int mn = sh.m * sh.n;
+        const int u = mn <= 512 ? 2 : mn <= 1024 ? 4 : mn <= 2048 ? 8 : 16;
+        switch (u) {
+#define X(U)                                                                                                  \
+    case U:                                                                                                   \
+        hipLaunchKernelGGL(gemv_wave<U>, grid, block, g.lds_bytes, st, sh.m, sh.n, batch, alpha, A, x, beta, y, \
+                           (int)region_floats(sh));                                                           \
+        break;
+            X(2) X(4) X(8) X(16)
+#undef X
+        }
     } else {
         hipLaunchKernelGGL(gemv_wg, grid, block, g.lds_bytes, st, sh.m, sh.n, batch, g.pack, alpha, A, x, beta, y);
     }

@@ -49,8 +49,8 @@ __global__ void __launch_bounds__(512) se3_thread(int inverse, int batch, const 
     const FastDiv f16 = make_fastdiv(16);
     float* sa = lds;
     float* sb = lds + nt * kS;
-    stage_in(sa, Ta + p0 * 16, cnt * 16, f16, kS, tid, nt);
-    if (!inverse) stage_in(sb, Tb + p0 * 16, cnt * 16, f16, kS, tid, nt);
+    stage_in<4>(sa, Ta + p0 * 16, cnt * 16, f16, kS, tid, nt);
+    if (!inverse) stage_in<4>(sb, Tb + p0 * 16, cnt * 16, f16, kS, tid, nt);
     __syncthreads();
     if (tid < cnt) {
         float a[12], o[12];
