@@ -7,11 +7,15 @@
 //             that bound LDS use), each lane then holds its problem's lower
 //             triangle in VGPRs at compile-time order N and factors / solves
 //             it fully unrolled.
-//   wave      one problem per 64-lane wavefront.  Lane i owns row i.  POTRF is
-//             right-looking: the pivot comes from v_readlane, the scaled
-//             column is broadcast through a wave-private LDS vector and every
-//             lane updates its row in VGPRs.  Substitutions are lane-parallel
-//             with v_readlane broadcasts of the solved unknown.
+//   wave      one problem per 64-lane wavefront.  Lane i owns row i, loaded
+//             straight from global memory (lower triangle only).  POTRF is
+//             right-looking in VGPRs: the pivot comes from v_readlane and the
+//             scaled column is broadcast with DPP row_newbcast folded into the
+//             v_fmac of the update (no LDS).  Forward substitution broadcasts
+//             the solved unknown with v_readlane; L leaves through an 8-row
+//             LDS chunk as coalesced stores, walked bottom-up so the same
+//             chunk also feeds the backward substitution (which needs L by
+//             columns).
 //   workgroup one problem at a time per workgroup of T(n) lanes, the matrix
 //             resident in LDS, cooperative right-looking updates separated
 //             by workgroup barriers; P problems back to back.
@@ -223,71 +227,162 @@ __global__ void __launch_bounds__(512) trsv_thread(int trans, int batch, const f
 }
 
 // -------------------------------------------------------------- wave scope --
-// Row `lane` of the staged matrix, lower part only.  Rows and columns beyond
-// n are padded with an identity block, so factoring all NB columns leaves the
-// leading n x n factor unchanged (every padded pivot is exactly 1 and every
-// padded coupling exactly 0) and the column loop needs no data-dependent exit.
+// Lane i owns row i.  Rows come straight from global memory with 16-byte
+// buffer loads of only the column blocks at or left of the diagonal; rows and
+// columns beyond n are padded with an identity block, so every column loop
+// runs the full bucket width NB without a data-dependent exit and the leading
+// n x n factor is unchanged (padded pivots are 1, padded couplings 0).
 template <int NB>
-GLASS_DEV void row_load(float (&a)[NB], const float* M, int n, int s, int lane) {
-#pragma unroll
-    for (int j = 0; j < NB; ++j)
-        a[j] = (lane < n && j < n && j <= lane) ? M[lane * s + j] : (j == lane && j >= n ? 1.f : 0.f);
-}
-
-template <int NB>
-GLASS_DEV void row_store(const float (&a)[NB], float* M, int n, int s, int lane) {
-    if (lane < n) {
-#pragma unroll
-        for (int j = 0; j < NB; ++j)
-            if (j < n) M[lane * s + j] = j <= lane ? a[j] : 0.f;
-    }
-}
-
-// Right-looking wave Cholesky, lane i holding row i (identity-padded to NB by
-// row_load); returns info.
-template <int NB>
-GLASS_DEV int wave_potrf(float (&a)[NB], float* col, int lane) {
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        const float d = readlane(a[j], j);
-        if (!(d > 0.f)) return j + 1;
-        const float inv = rsq(d);
-        const float v = lane == j ? d * inv : a[j] * inv;
-        a[j] = v;
-        col[lane] = v;
-        wave_sync();
-#pragma unroll
-        for (int k = j + 1; k < NB; ++k) a[k] = fmaf(-v, col[k], a[k]);
-        wave_sync();
-    }
-    return 0;
-}
-
-// Lane-parallel substitutions for one problem whose factor L is staged in
-// LDS (M, row stride s; only the lower triangle is read) and whose
-// right-hand sides are staged in Bm ([n][nrhs], row stride sb).
-GLASS_DEV void wave_solve(const float* M, int s, float* Bm, int sb, int n, int nrhs, int lane, bool fwd,
-                          bool bwd) {
+GLASS_DEV void rows_load_lower(float (&a)[NB], const float* Ag, int n, int lane) {
+    const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(Ag, (uint32_t)(n * n) * 4u);
     const bool row = lane < n;
-    const float myinv = row ? 1.0f / M[lane * s + lane] : 0.f;
-    for (int c = 0; c < nrhs; ++c) {
-        float acc = row ? Bm[lane * sb + c] : 0.f;
-        if (fwd) {
-            for (int k = 0; k < n; ++k) {
-                const float lik = (row && k < lane) ? M[lane * s + k] : 0.f;
-                const float yk = readlane(acc * myinv, k);
-                acc = lane == k ? yk : fmaf(-lik, yk, acc);
+#pragma unroll
+    for (int t = 0; t < NB / 4; ++t) {
+        f4_t v = {0.f, 0.f, 0.f, 0.f};
+        if (row && 4 * t <= lane) {
+            if (lane * n + 4 * t + 4 <= n * n) {
+                v = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, lane * n * 4, t * 16, 0));
+            } else {  // last row, block past the end of the problem: element-wise
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (4 * t + e < n)
+                        v[e] = __builtin_bit_cast(
+                            float, __builtin_amdgcn_raw_buffer_load_b32(rs, (lane * n + 4 * t + e) * 4, 0, 0));
             }
         }
-        if (bwd) {
-            for (int k = n - 1; k >= 0; --k) {
-                const float lki = lane < k ? M[k * s + lane] : 0.f;
-                const float xk = readlane(acc * myinv, k);
-                acc = lane == k ? xk : fmaf(-lki, xk, acc);
-            }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = 4 * t + e;
+            a[j] = (row && j <= lane) ? v[e] : (j == lane ? 1.f : 0.f);
         }
-        if (row) Bm[lane * sb + c] = acc;
     }
+}
+
+// One column step of the right-looking factorization: the pivot of column J
+// comes from v_readlane, the scaled column is broadcast with DPP and each lane
+// updates the rest of its row in VGPRs (a[K] -= l_iJ * l_KJ, one v_fmac each).
+template <int NB, int J, int K>
+struct WaveUpd {
+    static GLASS_DEV void run(float (&a)[NB], const float (&R)[4], float nv) {
+        fmac_bcast<K % 16>(a[K], R[K / 16], nv);
+        WaveUpd<NB, J, K + 1>::run(a, R, nv);
+    }
+};
+template <int NB, int J>
+struct WaveUpd<NB, J, NB> {
+    static GLASS_DEV void run(float (&)[NB], const float (&)[4], float) {}
+};
+
+template <int NB, int J>
+struct WaveStep {
+    static GLASS_DEV void run(float (&a)[NB], int lane, int& info, float& myinv) {
+        const float d = readlane(a[J], J);
+        if (!(d > 0.f) && info == 0) info = J + 1;
+        const float inv = rsq(d);
+        const float v = lane == J ? d * inv : a[J] * inv;
+        myinv = lane == J ? inv : myinv;
+        a[J] = v;
+        float R[4];
+        replicate_rows<(NB + 15) / 16>(v, R);
+        WaveUpd<NB, J, J + 1>::run(a, R, -v);
+        WaveStep<NB, J + 1>::run(a, lane, info, myinv);
+    }
+};
+template <int NB>
+struct WaveStep<NB, NB> {
+    static GLASS_DEV void run(float (&)[NB], int, int&, float&) {}
+};
+
+// Factor the identity-padded rows in place; returns info, sets myinv = 1/L_ii
+// and clears the strict upper part of every row.
+template <int NB>
+GLASS_DEV int wave_potrf(float (&a)[NB], int lane, float& myinv) {
+    int info = 0;
+    myinv = 1.f;
+    WaveStep<NB, 0>::run(a, lane, info, myinv);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) a[k] = k <= lane ? a[k] : 0.f;
+    return info;
+}
+
+// Forward substitution L y = b for one right-hand side, b_i in lane i: the
+// solved unknown is broadcast with v_readlane (rows hold L_ik with a zero
+// strict upper part; padded lanes have b = 0 and L_ii = 1).
+template <int NB>
+GLASS_DEV float wave_fwd(const float (&a)[NB], float acc, float myinv, int lane) {
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const float yk = readlane(acc * myinv, k);
+        acc = lane == k ? yk : fmaf(-a[k], yk, acc);
+    }
+    return acc;
+}
+
+// Rows r0 .. r0+7 (< n) of L (strict upper +0) from the owning lanes into
+// the LDS chunk buffer, row-major with row stride n.
+template <int NB>
+GLASS_DEV void rows_to_lds(const float (&a)[NB], float* buf, int n, int r0, int lane) {
+    if (lane >= r0 && lane < r0 + 8 && lane < n) {
+        float* dst = buf + (lane - r0) * n;
+        if ((n & 3) == 0) {
+#pragma unroll
+            for (int t = 0; t < NB / 4; ++t) {
+                if (4 * t < n) {
+                    f4_t v;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] = a[4 * t + e];
+                    *reinterpret_cast<f4_t*>(dst + 4 * t) = v;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                if (j < n) dst[j] = a[j];
+        }
+    }
+}
+
+// Coalesced copy of len floats from the LDS chunk to global memory.
+GLASS_DEV void chunk_to_global(float* __restrict__ dst, const float* buf, int len, bool vec, int lane) {
+    if (vec) {
+        for (int q = lane; q < (len >> 2); q += 64)
+            reinterpret_cast<f4_t*>(dst)[q] = reinterpret_cast<const f4_t*>(buf)[q];
+    } else {
+        for (int g = lane; g < len; g += 64) dst[g] = buf[g];
+    }
+}
+
+// Backward substitution L^T x = y for the rows of the chunk in LDS (rows
+// r0 .. r1-1, descending); lane i < k reads L_ki from row k of the chunk.
+GLASS_DEV float wave_bwd_chunk(const float* buf, int n, int r0, int r1, float acc, float myinv, int lane) {
+    for (int k = r1 - 1; k >= r0; --k) {
+        const float lki = lane < k ? buf[(k - r0) * n + lane] : 0.f;
+        const float xk = readlane(acc * myinv, k);
+        acc = lane == k ? xk : fmaf(-lki, xk, acc);
+    }
+    return acc;
+}
+
+// Walk the 8-row chunks of L from the bottom up: optionally store each chunk
+// of L to global memory (coalesced) and optionally run the backward
+// substitution steps of its rows.
+template <int NB>
+GLASS_DEV float wave_chunks_desc(const float (&a)[NB], float* buf, float* Lg, bool vec, int n, int lane, bool bwd,
+                                 float acc, float myinv) {
+    for (int r0 = (n - 1) & ~7; r0 >= 0; r0 -= 8) {
+        const int r1 = min(r0 + 8, n);
+        rows_to_lds<NB>(a, buf, n, r0, lane);
+        wave_sync();
+        if (Lg) chunk_to_global(Lg + r0 * n, buf, (r1 - r0) * n, vec, lane);
+        if (bwd) acc = wave_bwd_chunk(buf, n, r0, r1, acc, myinv, lane);
+        wave_sync();
+    }
+    return acc;
+}
+
+// 1 / L_ii of lane i's row (1 beyond n), read from global memory.
+GLASS_DEV float diag_inv(const float* Lg, int n, int lane) {
+    return lane < n ? 1.0f / Lg[lane * n + lane] : 1.f;
 }
 
 template <int NB>
@@ -297,19 +392,14 @@ __global__ void __launch_bounds__(512) potrf_wave(int n, int batch, float* __res
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
-    float* M = lds + (size_t)w * region;
-    const int s = n | 1;
-    float* col = M + ((n * s + 3) & ~3);
+    float* buf = lds + (size_t)w * region;
     float* Ag = A + p * n * n;
-    const FastDiv fd = make_fastdiv(n);
-    stage_in<WaveU<NB>::v>(M, Ag, n * n, fd, s, lane, 64);
-    wave_sync();
     float a[NB];
-    row_load<NB>(a, M, n, s, lane);
-    const int inf = wave_potrf<NB>(a, col, lane);
-    row_store<NB>(a, M, n, s, lane);
-    wave_sync();
-    stage_out(Ag, M, n * n, fd, s, lane, 64);
+    rows_load_lower<NB>(a, Ag, n, lane);
+    float myinv;
+    const int inf = wave_potrf<NB>(a, lane, myinv);
+    const bool vec = (n & 3) == 0 && aligned16(A);
+    wave_chunks_desc<NB>(a, buf, Ag, vec, n, lane, false, 0.f, myinv);
     if (info && lane == 0) info[p] = inf;
 }
 
@@ -320,69 +410,66 @@ __global__ void __launch_bounds__(512) posv_wave(int n, int nrhs, int batch, flo
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
-    float* M = lds + (size_t)w * region;
-    const int s = n | 1, sb = nrhs | 1;
-    float* Bm = M + ((n * s + 3) & ~3);
-    float* col = Bm + ((n * sb + 3) & ~3);
+    float* buf = lds + (size_t)w * region;
     float* Ag = A + p * n * n;
     float* Bg = B + p * n * nrhs;
-    const FastDiv fd = make_fastdiv(n), fdb = make_fastdiv(nrhs);
-    stage_in<WaveU<NB>::v>(M, Ag, n * n, fd, s, lane, 64);
-    stage_in<2>(Bm, Bg, n * nrhs, fdb, sb, lane, 64);
-    wave_sync();
     float a[NB];
-    row_load<NB>(a, M, n, s, lane);
-    const int inf = wave_potrf<NB>(a, col, lane);
-    row_store<NB>(a, M, n, s, lane);
-    wave_sync();
-    stage_out(Ag, M, n * n, fd, s, lane, 64);
-    if (info && lane == 0) info[p] = inf;
-    if (inf == 0) {
-        wave_solve(M, s, Bm, sb, n, nrhs, lane, true, true);
-        wave_sync();
-        stage_out(Bg, Bm, n * nrhs, fdb, sb, lane, 64);
+    rows_load_lower<NB>(a, Ag, n, lane);
+    float myinv;
+    const int inf = wave_potrf<NB>(a, lane, myinv);
+    const bool vec = (n & 3) == 0 && aligned16(A);
+    if (inf != 0) {
+        wave_chunks_desc<NB>(a, buf, Ag, vec, n, lane, false, 0.f, myinv);
+    } else {
+        for (int c = 0; c < nrhs; ++c) {
+            float acc = lane < n ? Bg[lane * nrhs + c] : 0.f;
+            acc = wave_fwd<NB>(a, acc, myinv, lane);
+            acc = wave_chunks_desc<NB>(a, buf, c == 0 ? Ag : nullptr, vec, n, lane, true, acc, myinv);
+            if (lane < n) Bg[lane * nrhs + c] = acc;
+        }
     }
+    if (info && lane == 0) info[p] = inf;
 }
 
-template <int U>
+template <int NB>
 __global__ void __launch_bounds__(512) potrs_wave(int n, int nrhs, int batch, const float* __restrict__ L,
                                                   float* __restrict__ B, int region) {
     extern __shared__ float lds[];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
-    float* M = lds + (size_t)w * region;
-    const int s = n | 1, sb = nrhs | 1;
-    float* Bm = M + ((n * s + 3) & ~3);
+    float* buf = lds + (size_t)w * region;
+    const float* Lg = L + p * n * n;
     float* Bg = B + p * n * nrhs;
-    const FastDiv fdb = make_fastdiv(nrhs);
-    stage_in<U>(M, L + p * n * n, n * n, make_fastdiv(n), s, lane, 64);
-    stage_in<2>(Bm, Bg, n * nrhs, fdb, sb, lane, 64);
-    wave_sync();
-    wave_solve(M, s, Bm, sb, n, nrhs, lane, true, true);
-    wave_sync();
-    stage_out(Bg, Bm, n * nrhs, fdb, sb, lane, 64);
+    float a[NB];
+    rows_load_lower<NB>(a, Lg, n, lane);
+    const float myinv = diag_inv(Lg, n, lane);
+    for (int c = 0; c < nrhs; ++c) {
+        float acc = lane < n ? Bg[lane * nrhs + c] : 0.f;
+        acc = wave_fwd<NB>(a, acc, myinv, lane);
+        acc = wave_chunks_desc<NB>(a, buf, nullptr, false, n, lane, true, acc, myinv);
+        if (lane < n) Bg[lane * nrhs + c] = acc;
+    }
 }
 
-template <int U>
+template <int NB>
 __global__ void __launch_bounds__(512) trsv_wave(int n, int trans, int batch, const float* __restrict__ L,
                                                  float* __restrict__ x, int region) {
     extern __shared__ float lds[];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
-    float* M = lds + (size_t)w * region;
-    const int s = n | 1;
-    stage_in<U>(M, L + p * n * n, n * n, make_fastdiv(n), s, lane, 64);
-    wave_sync();
-    const bool row = lane < n;
-    float v = row ? x[p * n + lane] : 0.f;
-    float* vm = M + ((n * s + 3) & ~3);
-    if (row) vm[lane] = v;
-    wave_sync();
-    wave_solve(M, s, vm, 1, n, 1, lane, trans == 0, trans != 0);
-    wave_sync();
-    if (row) x[p * n + lane] = vm[lane];
+    float* buf = lds + (size_t)w * region;
+    const float* Lg = L + p * n * n;
+    float a[NB];
+    rows_load_lower<NB>(a, Lg, n, lane);
+    const float myinv = diag_inv(Lg, n, lane);
+    float acc = lane < n ? x[p * n + lane] : 0.f;
+    if (trans == 0)
+        acc = wave_fwd<NB>(a, acc, myinv, lane);
+    else
+        acc = wave_chunks_desc<NB>(a, buf, nullptr, false, n, lane, true, acc, myinv);
+    if (lane < n) x[p * n + lane] = acc;
 }
 
 // --------------------------------------------------------- workgroup scope --
@@ -546,9 +633,6 @@ __global__ void __launch_bounds__(256) trsv_wg(int n, int trans, int batch, int 
 
 inline int bucket8(int n) { return ((n + 7) / 8) * 8; }
 
-// U of stage_in for a wave staging an n x n problem in one chunk.
-inline int wave_u(int n) { return n * n <= 512 ? 2 : n * n <= 1024 ? 4 : n * n <= 2048 ? 8 : 16; }
-#define GLASS_WAVE_U(X) X(2) X(4) X(8) X(16)
 
 inline int finish() { return (int)hipGetLastError(); }
 
@@ -567,7 +651,7 @@ int launch_potrf(const Shape& sh, const Geometry& g, int batch, float* A, int32_
         default: return (int)hipErrorInvalidValue;
         }
     } else if (g.scope == GLASS_SCOPE_WAVE) {
-        const int region = (int)region_floats(sh);
+        const int region = (int)wave_region_floats(sh);
         switch (bucket8(n)) {
 #define X(NB) \
     case NB: hipLaunchKernelGGL(potrf_wave<NB>, grid, block, g.lds_bytes, st, n, batch, A, info, region); break;
@@ -594,7 +678,7 @@ int launch_posv(const Shape& sh, const Geometry& g, int batch, float* A, float* 
         default: return (int)hipErrorInvalidValue;
         }
     } else if (g.scope == GLASS_SCOPE_WAVE) {
-        const int region = (int)region_floats(sh);
+        const int region = (int)wave_region_floats(sh);
         switch (bucket8(n)) {
 #define X(NB) \
     case NB: hipLaunchKernelGGL(posv_wave<NB>, grid, block, g.lds_bytes, st, n, r, batch, A, B, info, region); break;
@@ -621,12 +705,13 @@ int launch_potrs(const Shape& sh, const Geometry& g, int batch, const float* L, 
         default: return (int)hipErrorInvalidValue;
         }
     } else if (g.scope == GLASS_SCOPE_WAVE) {
-        const int region = (int)region_floats(sh);
-        switch (wave_u(n)) {
-#define X(U) \
-    case U: hipLaunchKernelGGL(potrs_wave<U>, grid, block, g.lds_bytes, st, n, r, batch, L, B, region); break;
-            GLASS_WAVE_U(X)
+        const int region = (int)wave_region_floats(sh);
+        switch (bucket8(n)) {
+#define X(NB) \
+    case NB: hipLaunchKernelGGL(potrs_wave<NB>, grid, block, g.lds_bytes, st, n, r, batch, L, B, region); break;
+            GLASS_BUCKETS(X)
 #undef X
+        default: return (int)hipErrorInvalidValue;
         }
     } else {
         hipLaunchKernelGGL(potrs_wg, grid, block, g.lds_bytes, st, n, r, batch, g.pack, L, B);
@@ -647,12 +732,13 @@ int launch_trsv(const Shape& sh, const Geometry& g, int batch, const float* L, f
         default: return (int)hipErrorInvalidValue;
         }
     } else if (g.scope == GLASS_SCOPE_WAVE) {
-        const int region = (int)region_floats(sh);
-        switch (wave_u(n)) {
-#define X(U) \
-    case U: hipLaunchKernelGGL(trsv_wave<U>, grid, block, g.lds_bytes, st, n, tr, batch, L, x, region); break;
-            GLASS_WAVE_U(X)
+        const int region = (int)wave_region_floats(sh);
+        switch (bucket8(n)) {
+#define X(NB) \
+    case NB: hipLaunchKernelGGL(trsv_wave<NB>, grid, block, g.lds_bytes, st, n, tr, batch, L, x, region); break;
+            GLASS_BUCKETS(X)
 #undef X
+        default: return (int)hipErrorInvalidValue;
         }
     } else {
         hipLaunchKernelGGL(trsv_wg, grid, block, g.lds_bytes, st, n, tr, batch, g.pack, L, x);

@@ -164,4 +164,66 @@ GLASS_DEV void stage_out_beta(float* __restrict__ dst, const float* src, int len
 // Reciprocal square root of a positive pivot (v_rsq_f32, about 1 ulp).
 GLASS_DEV float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
+
+// ---------------------------------------------------------------------------
+// Wavefront broadcast without LDS.  DPP row_newbcast:c hands every lane the
+// value of lane c of its own 16-lane row, and it can be folded into the
+// v_fmac_f32 that consumes it.  To broadcast lane k = 16 r + c to the whole
+// wave, row r is first replicated into all four rows (R[r]); two
+// v_permlane32_swap / v_permlane16_swap steps build R[0..3] from one VGPR.
+
+// R[r][lane] = v[16 r + lane % 16] for r < NR (NR 16-lane rows in use).  The
+// trailing s_nop provides the two wait states between the VALU writes of R
+// and their DPP reads; it is tied to R so the compiler cannot reorder them.
+template <int NR>
+GLASS_DEV void replicate_rows(float v, float (&R)[4]) {
+    if (NR == 1) {
+        float r0 = v;
+        asm volatile("s_nop 1" : "+v"(r0));
+        R[0] = r0;
+        R[1] = R[2] = R[3] = r0;
+    } else if (NR == 2) {
+        float r0, r1;
+        asm volatile(
+            "v_mov_b32 %0, %2\n"
+            "v_mov_b32 %1, %2\n"
+            "s_nop 1\n"
+            "v_permlane16_swap_b32 %0, %1\n"
+            "s_nop 1\n"
+            : "=&v"(r0), "=&v"(r1)
+            : "v"(v));
+        R[0] = r0;
+        R[1] = r1;
+        R[2] = R[3] = r0;
+    } else {
+        float r0, r1, r2, r3;
+        asm volatile(
+            "v_mov_b32 %0, %4\n"
+            "v_mov_b32 %1, %4\n"
+            "s_nop 1\n"
+            "v_permlane32_swap_b32 %0, %1\n"
+            "v_mov_b32 %2, %0\n"
+            "v_mov_b32 %3, %1\n"
+            "s_nop 1\n"
+            "v_permlane16_swap_b32 %0, %2\n"
+            "v_permlane16_swap_b32 %1, %3\n"
+            "s_nop 1\n"
+            : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3)
+            : "v"(v));
+        // r0 = row 0, r2 = row 1 (from the first swap's low half), r1 = row 2, r3 = row 3
+        R[0] = r0;
+        R[1] = r2;
+        R[2] = r1;
+        R[3] = r3;
+    }
+}
+
+// acc += bcast_c(src) * m, where bcast_c is DPP row_newbcast:C (one VALU op).
+template <int C>
+GLASS_DEV void fmac_bcast(float& acc, float src, float m) {
+    asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                 : "+v"(acc)
+                 : "v"(src), "v"(m), "n"(C));
+}
+
 }  // namespace glass

@@ -59,7 +59,8 @@ inline bool gemm_uses_mfma(const Shape& s) {
     return mx >= 16;
 }
 
-// LDS floats of one problem region used by the wave and workgroup scopes.
+// LDS floats of one problem region of the workgroup scope (and of the wave
+// scope for GEMV and small-n GEMM): the staged, row-padded problem.
 inline size_t region_floats(const Shape& s) {
     const int n = s.n;
     switch (s.op) {
@@ -76,6 +77,23 @@ inline size_t region_floats(const Shape& s) {
         return (size_t)round4(s.m * odd_up(s.k)) + (size_t)round4(s.k * odd_up(s.n));
     default:
         return 0;
+    }
+}
+
+inline int bucket8_host(int n) { return ((n + 7) / 8) * 8; }
+
+// LDS floats of one wavefront of the wave scope.  The Cholesky family keeps
+// rows in VGPRs and needs only an 8-row chunk buffer for its coalesced
+// stores and backward substitution.
+inline size_t wave_region_floats(const Shape& s) {
+    switch (s.op) {
+    case GLASS_OP_POTRF:
+    case GLASS_OP_POTRS:
+    case GLASS_OP_POSV:
+    case GLASS_OP_TRSV:
+        return (size_t)8 * bucket8_host(s.n);
+    default:
+        return region_floats(s);
     }
 }
 
@@ -132,7 +150,7 @@ inline bool make_geometry(const Shape& s, int scope, int pack, long long batch, 
     } else if (scope == GLASS_SCOPE_WAVE) {
         out.threads = kWave * pack;
         out.problems_per_wg = pack;
-        out.lds_bytes = region_floats(s) * pack * sizeof(float);
+        out.lds_bytes = wave_region_floats(s) * pack * sizeof(float);
     } else if (scope == GLASS_SCOPE_WORKGROUP) {
         int order = s.n;
         if (s.op == GLASS_OP_GEMM || s.op == GLASS_OP_GEMV) {
