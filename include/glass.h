@@ -61,7 +61,8 @@ typedef enum {
     GLASS_OP_POSV = 4,
     GLASS_OP_TRSV = 5,
     GLASS_OP_SE3_COMPOSE = 6,
-    GLASS_OP_SE3_INVERSE = 7
+    GLASS_OP_SE3_INVERSE = 7,
+    GLASS_OP_POSV_ADJOINT = 8
 } glass_op_t;
 
 /* Execution scope (Sec. III-A). */
@@ -148,6 +149,24 @@ glass_status_t glass_trsv_batched(int n, int batch, int trans, const float* L,
 glass_status_t glass_se3_batched(glass_op_t op, int batch, const float* Ta,
                                  const float* Tb, float* Tout,
                                  const glass_placement_t* force, void* stream);
+
+/* Reverse mode of the Cholesky solve X = A^{-1} B (the differentiation
+ * part; derivatives are validated by finite differences, Sec. III-C).
+ * Given the factor L [batch][n][n] (lower triangle read, as returned by
+ * glass_posv_batched / glass_potrf_batched), the solution X [batch][n][nrhs]
+ * and the upstream gradient G = dl/dX [batch][n][nrhs] of a scalar loss l,
+ * writes
+ *   dB = A^{-1} G                      [batch][n][nrhs]
+ *   dA = -(dB X^T + X dB^T) / 2        [batch][n][n], symmetric
+ * dA is the gradient with respect to a symmetric A (the factorization reads
+ * A as symmetric).  dB may be G exactly (in place); dA must not overlap any
+ * other argument.  Scopes: thread (n <= 16) and wave; the workgroup scope is
+ * infeasible.  With force == NULL the placement is the table's POTRS entry
+ * for (n, batch) when feasible, else wave / pack 1. */
+glass_status_t glass_posv_adjoint_batched(int n, int nrhs, int batch, const float* L,
+                                          const float* X, const float* G, float* dB,
+                                          float* dA, const glass_placement_t* force,
+                                          void* stream);
 
 /* The advisor (Sec. III-A): the placement the built-in table gives for
  * (op, n, batch), written to *out (HOST pointer).  Lookup rule: n_key = the

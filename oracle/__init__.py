@@ -57,6 +57,7 @@ def _load():
             "oracle_trsv": [i, i, i, p, p],
             "oracle_se3_compose": [i, p, p, p],
             "oracle_se3_inverse": [i, p, p],
+            "oracle_posv_adjoint": [i, i, i, p, p, p, p, p],
             "oracle_num_threads": [],
             "oracle_set_num_threads": [i],
         }
@@ -160,3 +161,16 @@ def se3_inverse(Ta):
     out = np.empty((b, 4, 4))
     _load().oracle_se3_inverse(b, _ptr(Ta), _ptr(out))
     return out
+
+
+def posv_adjoint(L, X, G):
+    """(dB, dA) of the Cholesky solve X = A^{-1} B for upstream gradient G:
+    dB = A^{-1} G with A = L L^T, dA = -(dB X^T + X dB^T) / 2."""
+    L = _f64(L)
+    X = _f64(X)
+    G = _f64(G)
+    b, n, r = X.shape
+    dB = np.empty((b, n, r))
+    dA = np.empty((b, n, n))
+    _load().oracle_posv_adjoint(n, r, b, _ptr(L), _ptr(X), _ptr(G), _ptr(dB), _ptr(dA))
+    return dB, dA

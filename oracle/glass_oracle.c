@@ -236,3 +236,31 @@ void oracle_se3_inverse(int batch, const double* Ta, double* T) {
         memcpy(T + OIDX(bb, 16), o, sizeof o);
     }
 }
+
+/* ------------------------------------------------------- POSV adjoint --
+ * Reverse mode of the Cholesky solve X = A^{-1} B (A symmetric positive
+ * definite, B n x r), for a scalar loss with upstream gradient G = dl/dX:
+ *   dB = A^{-1} G               (a second solve with the same factor)
+ *   dA = -(1/2) (dB X^T + X dB^T)
+ * The symmetric form is the gradient restricted to symmetric perturbations
+ * of A (A enters only through its lower triangle, and the factorization
+ * treats it as symmetric).  L is A's Cholesky factor, X the solution.      */
+void oracle_posv_adjoint(int n, int nrhs, int batch, const double* L, const double* X,
+                         const double* G, double* dB, double* dA) {
+    long long bb;
+#pragma omp parallel for schedule(static)
+    for (bb = 0; bb < batch; ++bb) {
+        const double* l = L + OIDX(bb, n * n);
+        const double* x = X + OIDX(bb, n * nrhs);
+        double* db = dB + OIDX(bb, n * nrhs);
+        double* da = dA + OIDX(bb, n * n);
+        memcpy(db, G + OIDX(bb, n * nrhs), sizeof(double) * (size_t)n * nrhs);
+        chol_solve_one(n, nrhs, l, db);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double s = 0.0;
+                for (int c = 0; c < nrhs; ++c) s += db[i * nrhs + c] * x[j * nrhs + c] + x[i * nrhs + c] * db[j * nrhs + c];
+                da[i * n + j] = -0.5 * s;
+            }
+    }
+}

@@ -1,0 +1,164 @@
+// adjoint.hip -- reverse mode of the batched Cholesky solve X = A^{-1} B.
+//
+// Given the factor L (A = L L^T), the solution X and the upstream gradient
+// G = dl/dX of a scalar loss, one kernel returns
+//   dB = A^{-1} G                       (forward + backward substitution)
+//   dA = -(dB X^T + X dB^T) / 2         (the gradient over symmetric A)
+// The paper validates derivatives by finite differences (Sec. III-C); the
+// adjoint itself is the standard one of a linear solve, symmetrized because
+// the factorization reads A as symmetric (only its lower triangle).
+//
+//   thread  (n <= 16) one problem per lane: L in VGPRs (compile-time n),
+//           G and X staged through LDS, dA written through LDS passes as
+//           coalesced stores.
+//   wave    one problem per wavefront, the wave-scope substitutions of
+//           chol.hip; lane i accumulates row i of dA from v_readlane
+//           broadcasts of x_j and dB_j, rows leave through the 8-row LDS chunk.
+#include "device_common.hpp"
+#include "glass_internal.hpp"
+#include "chol_device.hpp"
+
+namespace glass {
+namespace {
+
+// acc + (p * q + r * s) with both products rounded and no contraction: the
+// (j, i) entry of dA forms the same two products in the other order, and
+// addition commutes, so dA comes out bit-symmetric.
+GLASS_DEV float sym_pair(float acc, float p, float q, float r, float s) {
+#pragma clang fp contract(off)
+    const float t = p * q + r * s;
+    return acc + t;
+}
+
+template <int N>
+__global__ void __launch_bounds__(512) adjoint_thread(int nrhs, int batch, const float* __restrict__ L,
+                                                      const float* __restrict__ X, const float* __restrict__ G,
+                                                      float* __restrict__ dB, float* __restrict__ dA) {
+    extern __shared__ float lds[];
+    constexpr int SZ = N * N, S = SZ | 1;
+    const int nt = blockDim.x, tid = threadIdx.x;
+    const long long p0 = (long long)blockIdx.x * nt;
+    const int cnt = (int)min((long long)nt, (long long)batch - p0);
+    const int Q = thread_stage_q_dev(nt, SZ);
+    const int SBn = N * nrhs, SB = SBn | 1;
+    float* gs = lds + Q * S;
+    float* xs = gs + nt * SB;
+    float a[N * (N + 1) / 2];
+    float dinv[N];
+    thread_load_tri<N>(a, L + p0 * SZ, lds, cnt, tid, nt);
+#pragma unroll
+    for (int i = 0; i < N; ++i) dinv[i] = 1.0f / a[TI(i, i)];
+    const FastDiv fb = make_fastdiv(SBn);
+    stage_in<2>(gs, G + p0 * SBn, cnt * SBn, fb, SB, tid, nt);
+    stage_in<2>(xs, X + p0 * SBn, cnt * SBn, fb, SB, tid, nt);
+    __syncthreads();
+    const bool active = tid < cnt;
+    if (active) {
+        float* b = gs + tid * SB;
+        for (int c = 0; c < nrhs; ++c) {
+            float y[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) y[i] = b[i * nrhs + c];
+            tri_fwd<N>(a, dinv, y);
+            tri_bwd<N>(a, dinv, y);
+#pragma unroll
+            for (int i = 0; i < N; ++i) b[i * nrhs + c] = y[i];
+        }
+    }
+    __syncthreads();
+    stage_out(dB + p0 * SBn, gs, cnt * SBn, fb, SB, tid, nt);
+    const FastDiv fa = make_fastdiv(SZ);
+    for (int s = 0; s < cnt; s += Q) {
+        const int qn = min(Q, cnt - s);
+        if (tid >= s && tid < s + qn) {
+            const float* b = gs + tid * SB;
+            const float* x = xs + tid * SB;
+            float* o = lds + (tid - s) * S;
+#pragma unroll
+            for (int i = 0; i < N; ++i)
+#pragma unroll
+                for (int j = 0; j <= i; ++j) {
+                    float v = 0.f;
+                    for (int c = 0; c < nrhs; ++c)
+                        v = sym_pair(v, b[i * nrhs + c], x[j * nrhs + c], x[i * nrhs + c], b[j * nrhs + c]);
+                    o[i * N + j] = -0.5f * v;
+                    o[j * N + i] = -0.5f * v;
+                }
+        }
+        __syncthreads();
+        stage_out(dA + (p0 + s) * SZ, lds, qn * SZ, fa, S, tid, nt);
+        __syncthreads();
+    }
+}
+
+template <int NB>
+__global__ void __launch_bounds__(512) adjoint_wave(int n, int nrhs, int batch, const float* __restrict__ L,
+                                                    const float* __restrict__ X, const float* __restrict__ G,
+                                                    float* __restrict__ dB, float* __restrict__ dA, int region) {
+    extern __shared__ float lds[];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
+    if (p >= batch) return;
+    float* buf = lds + (size_t)w * region;
+    const float* Lg = L + p * n * n;
+    const long long ob = p * n * nrhs;
+    float a[NB];
+    rows_load_lower<NB>(a, Lg, n, lane);
+    const float myinv = diag_inv(Lg, n, lane);
+    float d[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) d[j] = 0.f;
+    for (int c = 0; c < nrhs; ++c) {
+        float acc = lane < n ? G[ob + lane * nrhs + c] : 0.f;
+        acc = wave_fwd<NB>(a, acc, myinv, lane);
+        acc = wave_chunks_desc<NB>(a, buf, nullptr, false, n, lane, true, acc, myinv);
+        const float xc = lane < n ? X[ob + lane * nrhs + c] : 0.f;
+        if (lane < n) dB[ob + lane * nrhs + c] = acc;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const float xj = readlane(xc, j), bj = readlane(acc, j);
+            d[j] = sym_pair(d[j], acc, xj, xc, bj);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) d[j] *= -0.5f;
+    const bool vec = (n & 3) == 0 && aligned16(dA);
+    wave_chunks_desc<NB>(d, buf, dA + p * n * n, vec, n, lane, false, 0.f, 1.f);
+}
+
+inline int bucket8(int n) { return ((n + 7) / 8) * 8; }
+
+}  // namespace
+
+int launch_posv_adjoint(const Shape& sh, const Geometry& g, int batch, const float* L, const float* X,
+                        const float* G, float* dB, float* dA, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const int n = sh.n, r = sh.nrhs;
+    dim3 grid((unsigned)g.grid), block(g.threads);
+    if (g.scope == GLASS_SCOPE_THREAD) {
+        switch (n) {
+#define CASE(N) \
+    case N: hipLaunchKernelGGL(adjoint_thread<N>, grid, block, g.lds_bytes, st, r, batch, L, X, G, dB, dA); break;
+            CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11) CASE(12)
+            CASE(13) CASE(14) CASE(15) CASE(16)
+#undef CASE
+        default: return (int)hipErrorInvalidValue;
+        }
+    } else if (g.scope == GLASS_SCOPE_WAVE) {
+        const int region = (int)wave_region_floats(sh);
+        switch (bucket8(n)) {
+#define CASE(NB)                                                                                                 \
+    case NB:                                                                                                     \
+        hipLaunchKernelGGL(adjoint_wave<NB>, grid, block, g.lds_bytes, st, n, r, batch, L, X, G, dB, dA, region); \
+        break;
+            CASE(8) CASE(16) CASE(24) CASE(32) CASE(40) CASE(48) CASE(56) CASE(64)
+#undef CASE
+        default: return (int)hipErrorInvalidValue;
+        }
+    } else {
+        return (int)hipErrorInvalidValue;
+    }
+    return (int)hipGetLastError();
+}
+
+}  // namespace glass

@@ -37,6 +37,7 @@ int b_index(long long batch) {
 }
 
 void table_lookup(glass_op_t op, int n, long long batch, int* scope, int* pack) {
+    if (op == GLASS_OP_POSV_ADJOINT) op = GLASS_OP_POTRS;  // a POTRS plus an outer-product epilogue
     const int ni = is_se3(op) ? 0 : n_index(n);
     const int bi = b_index(batch);
     *scope = kPlace[(int)op][ni][bi][0];
@@ -175,8 +176,23 @@ glass_status_t glass_se3_batched(glass_op_t op, int batch, const float* Ta, cons
     return launched(launch_se3(s, g, batch, Ta, Tb, Tout, stream));
 }
 
+glass_status_t glass_posv_adjoint_batched(int n, int nrhs, int batch, const float* L, const float* X,
+                                          const float* G, float* dB, float* dA, const glass_placement_t* force,
+                                          void* stream) {
+    if (!valid_force(force)) return GLASS_ERR_INVALID_VALUE;
+    if (!size_ok(n) || !size_ok(nrhs)) return GLASS_ERR_UNSUPPORTED;
+    if (batch < 0) return GLASS_ERR_INVALID_VALUE;
+    if (batch == 0) return GLASS_OK;
+    if (!L || !X || !G || !dB || !dA) return GLASS_ERR_INVALID_VALUE;
+    Shape s{GLASS_OP_POSV_ADJOINT, n, n, n, nrhs, 0};
+    Geometry g;
+    glass_status_t st = resolve(s, batch, force, &g);
+    if (st != GLASS_OK) return st;
+    return launched(launch_posv_adjoint(s, g, batch, L, X, G, dB, dA, stream));
+}
+
 glass_status_t glass_query_placement(glass_op_t op, int n, int batch, glass_placement_t* out) {
-    if ((int)op < GLASS_OP_GEMM || (int)op > GLASS_OP_SE3_INVERSE) return GLASS_ERR_INVALID_VALUE;
+    if ((int)op < GLASS_OP_GEMM || (int)op > GLASS_OP_POSV_ADJOINT) return GLASS_ERR_INVALID_VALUE;
     if (!is_se3(op) && !size_ok(n)) return GLASS_ERR_UNSUPPORTED;
     if (batch < 1 || !out) return GLASS_ERR_INVALID_VALUE;
     const int order = is_se3(op) ? 4 : n;
@@ -197,7 +213,7 @@ glass_status_t glass_query_placement(glass_op_t op, int n, int batch, glass_plac
 }
 
 int glass_placement_feasible(glass_op_t op, int n, int nrhs, int scope, int pack) {
-    if ((int)op < GLASS_OP_GEMM || (int)op > GLASS_OP_SE3_INVERSE) return GLASS_ERR_INVALID_VALUE;
+    if ((int)op < GLASS_OP_GEMM || (int)op > GLASS_OP_POSV_ADJOINT) return GLASS_ERR_INVALID_VALUE;
     if (scope < GLASS_SCOPE_THREAD || scope > GLASS_SCOPE_WORKGROUP) return GLASS_ERR_INVALID_VALUE;
     if (!is_se3(op) && !size_ok(n)) return GLASS_ERR_UNSUPPORTED;
     if (!size_ok(nrhs)) return GLASS_ERR_UNSUPPORTED;

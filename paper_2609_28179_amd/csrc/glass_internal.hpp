@@ -91,6 +91,7 @@ inline size_t wave_region_floats(const Shape& s) {
     case GLASS_OP_POTRS:
     case GLASS_OP_POSV:
     case GLASS_OP_TRSV:
+    case GLASS_OP_POSV_ADJOINT:
         return (size_t)8 * bucket8_host(s.n);
     default:
         return region_floats(s);
@@ -122,6 +123,8 @@ inline size_t thread_lds_floats(const Shape& s, int t) {
         return 2 * (size_t)t * 17;
     case GLASS_OP_SE3_INVERSE:
         return (size_t)t * 17;
+    case GLASS_OP_POSV_ADJOINT:
+        return pass + 2 * (size_t)t * odd_up(n * s.nrhs);
     }
     return 0;
 }
@@ -152,6 +155,7 @@ inline bool make_geometry(const Shape& s, int scope, int pack, long long batch, 
         out.problems_per_wg = pack;
         out.lds_bytes = wave_region_floats(s) * pack * sizeof(float);
     } else if (scope == GLASS_SCOPE_WORKGROUP) {
+        if (s.op == GLASS_OP_POSV_ADJOINT) return false;
         int order = s.n;
         if (s.op == GLASS_OP_GEMM || s.op == GLASS_OP_GEMV) {
             order = s.m > order ? s.m : order;
@@ -183,5 +187,7 @@ int launch_posv(const Shape& s, const Geometry& g, int batch, float* A, float* B
 int launch_trsv(const Shape& s, const Geometry& g, int batch, const float* L, float* x, void* stream);
 int launch_se3(const Shape& s, const Geometry& g, int batch, const float* Ta, const float* Tb,
                float* Tout, void* stream);
+int launch_posv_adjoint(const Shape& s, const Geometry& g, int batch, const float* L, const float* X,
+                        const float* G, float* dB, float* dA, void* stream);
 
 }  // namespace glass

@@ -19,7 +19,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libglass.so")
 
 OK, ERR_INVALID_VALUE, ERR_UNSUPPORTED, ERR_INFEASIBLE_PLACEMENT, ERR_LAUNCH = 0, -1, -2, -3, -4
-OP_GEMM, OP_GEMV, OP_POTRF, OP_POTRS, OP_POSV, OP_TRSV, OP_SE3_COMPOSE, OP_SE3_INVERSE = range(8)
+OP_GEMM, OP_GEMV, OP_POTRF, OP_POTRS, OP_POSV, OP_TRSV, OP_SE3_COMPOSE, OP_SE3_INVERSE, OP_POSV_ADJOINT = range(9)
 SCOPE_THREAD, SCOPE_WAVE, SCOPE_WORKGROUP = 0, 1, 2
 OPS = {"gemm": OP_GEMM, "gemv": OP_GEMV, "potrf": OP_POTRF, "potrs": OP_POTRS, "posv": OP_POSV,
        "trsv": OP_TRSV, "se3_compose": OP_SE3_COMPOSE, "se3_inverse": OP_SE3_INVERSE}
@@ -56,6 +56,7 @@ _SIGS = {
     "glass_posv_batched": [_i, _i, _i, _p, _p, _p, _PP, _p],
     "glass_trsv_batched": [_i, _i, _i, _p, _p, _PP, _p],
     "glass_se3_batched": [_i, _i, _p, _p, _p, _PP, _p],
+    "glass_posv_adjoint_batched": [_i, _i, _i, _p, _p, _p, _p, _p, _PP, _p],
     "glass_query_placement": [_i, _i, _i, _PP],
     "glass_placement_feasible": [_i, _i, _i, _i, _i],
     "glass_table_provenance": [],
@@ -127,6 +128,11 @@ def glass_trsv_batched(n, batch, trans, L, x, force=None, stream=None) -> int:
 
 def glass_se3_batched(op, batch, Ta, Tb, Tout, force=None, stream=None) -> int:
     return _lib.glass_se3_batched(op, batch, _ptr(Ta), _ptr(Tb), _ptr(Tout), _force(force), _stream(stream))
+
+
+def glass_posv_adjoint_batched(n, nrhs, batch, L, X, G, dB, dA, force=None, stream=None) -> int:
+    return _lib.glass_posv_adjoint_batched(n, nrhs, batch, _ptr(L), _ptr(X), _ptr(G), _ptr(dB), _ptr(dA),
+                                           _force(force), _stream(stream))
 
 
 def glass_query_placement(op, n, batch) -> Placement:
@@ -256,3 +262,17 @@ def se3_inverse(Ta, out=None, force=None):
     _check(out, "out", (b, 4, 4))
     _raise(glass_se3_batched(OP_SE3_INVERSE, b, Ta, None, out, force), "se3_inverse")
     return out
+
+
+def posv_adjoint(L, X, G, force=None):
+    """(dB, dA) = (A^{-1} G, -(dB X^T + X dB^T) / 2) for A = L L^T."""
+    import torch
+    b, n, _ = L.shape
+    r = X.shape[2]
+    _check(L, "L", (b, n, n))
+    _check(X, "X", (b, n, r))
+    _check(G, "G", (b, n, r))
+    dB = torch.empty_like(X)
+    dA = torch.empty_like(L)
+    _raise(glass_posv_adjoint_batched(n, r, b, L, X, G, dB, dA, force), "posv_adjoint")
+    return dB, dA
