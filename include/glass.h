@@ -39,6 +39,7 @@
 #ifndef GLASS_H_
 #define GLASS_H_
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -167,6 +168,42 @@ glass_status_t glass_posv_adjoint_batched(int n, int nrhs, int batch, const floa
                                           const float* X, const float* G, float* dB,
                                           float* dA, const glass_placement_t* force,
                                           void* stream);
+
+/* Factor-and-solve of a ragged batch: `count` SPD systems of mixed order and
+ * right-hand-side count in one launch sequence (problem packing of Sec. IV-C
+ * extended to mixed sizes; no host synchronisation, so the call can be
+ * captured in a HIP graph): three small planning kernels and one solve
+ * launch with a wavefront per work item.  All arrays are DEVICE arrays:
+ *   n[count], nrhs[count]  int32, each in 1..64 (a problem outside that range
+ *                          gets info = -1 and is not touched);
+ *   offA[count], offB[count] int64 element offsets of problem i's A (n x n,
+ *                          row-major) in A and of its B (n x nrhs) in B;
+ *   A, B                   packed problems, overwritten by L (strict upper
+ *                          +0) and by the solutions, as glass_posv_batched;
+ *   info[count]            int32 as for glass_potrf_batched (required);
+ *   workspace              caller-owned device scratch of at least
+ *                          glass_posv_ragged_workspace_size(count) bytes,
+ *                          4-byte aligned; its contents on entry are ignored
+ *                          and on exit hold the class-sorted permutation of
+ *                          the problems (int32 at byte offset
+ *                          glass_posv_ragged_perm_offset(count)).
+ * Problems are grouped into eight size classes (orders 8k+1 .. 8k+8) by a
+ * deterministic stable counting sort on the device, largest class first;
+ * class_scope (HOST int32[8] or NULL) picks each class's scope: thread
+ * (class 0 only, 64 problems per wavefront; GLASS_ERR_INFEASIBLE_PLACEMENT
+ * for another class) or wave (one problem per wavefront); NULL takes each
+ * class's scope from the table's POSV entry at order 8k+8 and batch count/8.  Concurrent calls must not share a
+ * workspace. */
+glass_status_t glass_posv_ragged(int count, const int32_t* n, const int32_t* nrhs,
+                                 const int64_t* offA, const int64_t* offB, float* A,
+                                 float* B, int32_t* info, void* workspace,
+                                 size_t workspace_bytes, const int32_t* class_scope,
+                                 void* stream);
+
+/* Workspace bytes glass_posv_ragged needs for `count` problems (0 if
+ * count < 0), and the byte offset of the permutation inside it. */
+size_t glass_posv_ragged_workspace_size(int count);
+size_t glass_posv_ragged_perm_offset(int count);
 
 /* The advisor (Sec. III-A): the placement the built-in table gives for
  * (op, n, batch), written to *out (HOST pointer).  Lookup rule: n_key = the

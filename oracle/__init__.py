@@ -174,3 +174,33 @@ def posv_adjoint(L, X, G):
     dA = np.empty((b, n, n))
     _load().oracle_posv_adjoint(n, r, b, _ptr(L), _ptr(X), _ptr(G), _ptr(dB), _ptr(dA))
     return dB, dA
+
+
+def posv_ragged(n, nrhs, offA, offB, A, B):
+    """Per-problem factor-and-solve of a packed ragged batch (a loop over the
+    problems, grouped by (n, nrhs) only to call the batched routine).
+    Returns (A_out, B_out, info) with A_out / B_out packed like the inputs."""
+    n = np.asarray(n)
+    nrhs = np.asarray(nrhs)
+    A_out = _f64(A).copy()
+    B_out = _f64(B).copy()
+    info = np.zeros(len(n), dtype=np.int32)
+    for key in set(zip(n.tolist(), nrhs.tolist())):
+        idx = np.nonzero((n == key[0]) & (nrhs == key[1]))[0]
+        sa, sb = key[0] * key[0], key[0] * key[1]
+        Ab = np.stack([A_out[offA[i]:offA[i] + sa] for i in idx]).reshape(len(idx), key[0], key[0])
+        Bb = np.stack([B_out[offB[i]:offB[i] + sb] for i in idx]).reshape(len(idx), key[0], key[1])
+        L, X, inf = posv(Ab, Bb)
+        for row, i in enumerate(idx):
+            A_out[offA[i]:offA[i] + sa] = L[row].reshape(-1)
+            B_out[offB[i]:offB[i] + sb] = X[row].reshape(-1)
+            info[i] = inf[row]
+    return A_out, B_out, info
+
+
+def ragged_order(n):
+    """The problem order of a stable counting sort by size class
+    ceil(n / 8) - 1, largest class first (ties keep index order)."""
+    n = np.asarray(n, dtype=np.int64)
+    cls = np.clip((n - 1) // 8, 0, 7)
+    return np.argsort(-cls, kind="stable").astype(np.int32)

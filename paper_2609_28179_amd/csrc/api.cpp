@@ -191,6 +191,37 @@ glass_status_t glass_posv_adjoint_batched(int n, int nrhs, int batch, const floa
     return launched(launch_posv_adjoint(s, g, batch, L, X, G, dB, dA, stream));
 }
 
+size_t glass_posv_ragged_workspace_size(int count) { return count < 0 ? 0 : ragged_workspace_bytes(count); }
+
+size_t glass_posv_ragged_perm_offset(int count) {
+    if (count < 0) return 0;
+    return ragged_workspace_bytes(count) - sizeof(int32_t) * (size_t)count;
+}
+
+glass_status_t glass_posv_ragged(int count, const int32_t* n, const int32_t* nrhs, const int64_t* offA,
+                                 const int64_t* offB, float* A, float* B, int32_t* info, void* workspace,
+                                 size_t workspace_bytes, const int32_t* class_scope, void* stream) {
+    if (count < 0) return GLASS_ERR_INVALID_VALUE;
+    RaggedScopes sc{};
+    for (int k = 0; k < 8; ++k) {
+        if (class_scope) {
+            const int s = class_scope[k];
+            if (s != GLASS_SCOPE_THREAD && s != GLASS_SCOPE_WAVE) return GLASS_ERR_INVALID_VALUE;
+            if (s == GLASS_SCOPE_THREAD && k > 0) return GLASS_ERR_INFEASIBLE_PLACEMENT;
+            sc.s[k] = s;
+        } else {
+            int scope, pack;
+            table_lookup(GLASS_OP_POSV, 8 * (k + 1), count / 8 > 0 ? count / 8 : 1, &scope, &pack);
+            sc.s[k] = (scope == GLASS_SCOPE_THREAD && k == 0) ? GLASS_SCOPE_THREAD : GLASS_SCOPE_WAVE;
+        }
+    }
+    if (count == 0) return GLASS_OK;
+    if (!n || !nrhs || !offA || !offB || !A || !B || !info || !workspace) return GLASS_ERR_INVALID_VALUE;
+    if (workspace_bytes < ragged_workspace_bytes(count) || (reinterpret_cast<uintptr_t>(workspace) & 3))
+        return GLASS_ERR_INVALID_VALUE;
+    return launched(launch_posv_ragged(count, n, nrhs, offA, offB, A, B, info, workspace, sc, stream));
+}
+
 glass_status_t glass_query_placement(glass_op_t op, int n, int batch, glass_placement_t* out) {
     if ((int)op < GLASS_OP_GEMM || (int)op > GLASS_OP_POSV_ADJOINT) return GLASS_ERR_INVALID_VALUE;
     if (!is_se3(op) && !size_ok(n)) return GLASS_ERR_UNSUPPORTED;

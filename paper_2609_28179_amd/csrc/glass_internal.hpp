@@ -187,6 +187,15 @@ int launch_posv(const Shape& s, const Geometry& g, int batch, float* A, float* B
 int launch_trsv(const Shape& s, const Geometry& g, int batch, const float* L, float* x, void* stream);
 int launch_se3(const Shape& s, const Geometry& g, int batch, const float* Ta, const float* Tb,
                float* Tout, void* stream);
+// Placement (scope) of each of the eight ragged size classes (orders 8k+1 ..
+// 8k+8); thread scope is available for class 0 (n <= 8).
+struct RaggedScopes {
+    int32_t s[8];
+};
+size_t ragged_workspace_bytes(int count);
+int launch_posv_ragged(int count, const int32_t* n, const int32_t* nrhs, const int64_t* offA, const int64_t* offB,
+                       float* A, float* B, int32_t* info, void* workspace, const RaggedScopes& scopes,
+                       void* stream);
 int launch_posv_adjoint(const Shape& s, const Geometry& g, int batch, const float* L, const float* X,
                         const float* G, float* dB, float* dA, void* stream);
 

@@ -1,0 +1,261 @@
+// ragged.hip -- factor-and-solve of a ragged batch (problems of mixed order n
+// and right-hand-side count) in one launch sequence.
+//
+// Problems are grouped into eight size classes k = ceil(n/8) - 1 (orders
+// 8k+1 .. 8k+8).  Every class has one placement (Sec. III-A, Sec. IV-C),
+// thread scope (class 0 only: a wavefront takes 64 problems, one per lane) or
+// wave scope (a wavefront takes one problem); within a class a problem is
+// padded with an identity block up to the class order, so one code path
+// serves all its n.  (Thread scope stops at order 8 here because every path
+// of the persistent kernel shares one register allocation.)
+//
+// Launch sequence (all on one stream, no host synchronisation, capturable):
+//   1. ragged_count    per-chunk class histograms (each block a fixed chunk);
+//   2. ragged_scan     one block: class totals, class bases in descending
+//                      class order (largest problems first), per-chunk bases,
+//                      work-item bases;
+//   3. ragged_scatter  stable counting-sort scatter of problem indices into
+//                      perm[] (ranks from wavefront ballots, so the permutation
+//                      is deterministic: equal classes keep index order);
+//   4. ragged_solve    one wavefront per work item of the class-sorted list
+//                      (64 problems of a thread-scope class, or one problem).
+#include "device_common.hpp"
+#include "glass_internal.hpp"
+#include "chol_device.hpp"
+
+namespace glass {
+
+namespace {
+
+constexpr int kClasses = 8;
+constexpr int kChunk = 1024;        // problems per histogram / scatter block
+constexpr int kScanThreads = 256;
+
+// Size class of order n; orders outside 1..64 are clamped into a class here
+// and flagged (info = -1, problem skipped) by the solve kernel.
+GLASS_DEV int class_of(int n) {
+    const int k = (n - 1) >> 3;
+    return k < 0 ? 0 : (k > kClasses - 1 ? kClasses - 1 : k);
+}
+
+__global__ void __launch_bounds__(256) ragged_count(int count, const int32_t* __restrict__ nvec, int32_t* hist,
+                                                    int32_t* meta) {
+    __shared__ int32_t h[kClasses];
+    const int tid = threadIdx.x;
+    if (tid < kClasses) h[tid] = 0;
+    __syncthreads();
+    const int base = blockIdx.x * kChunk;
+    for (int e = base + tid; e < min(base + kChunk, count); e += blockDim.x) atomicAdd(&h[class_of(nvec[e])], 1);
+    __syncthreads();
+    if (tid < kClasses) hist[blockIdx.x * kClasses + tid] = h[tid];
+}
+
+// One block.  Classes are laid out largest first.  meta: [0..8) class count,
+// [8..16) class base in perm, [16..24) work-item base per class, [24] total
+// work items.  Every value is formed in LDS and registers of this block; the
+// per-chunk bases are derived from those, not re-read from global memory.
+__global__ void __launch_bounds__(kScanThreads) ragged_scan(int nchunks, int32_t* hist, int32_t* meta,
+                                                           RaggedScopes scopes) {
+    __shared__ int32_t tot[kClasses];
+    __shared__ int32_t cbase[kClasses];
+    const int tid = threadIdx.x;
+    if (tid < kClasses) {
+        int s = 0;
+        for (int b = 0; b < nchunks; ++b) s += hist[b * kClasses + tid];
+        tot[tid] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int base = 0, items = 0;
+        for (int k = kClasses - 1; k >= 0; --k) {
+            cbase[k] = base;
+            meta[k] = tot[k];
+            meta[kClasses + k] = base;
+            meta[2 * kClasses + k] = items;
+            base += tot[k];
+            items += scopes.s[k] == GLASS_SCOPE_THREAD ? (tot[k] + 63) / 64 : tot[k];
+        }
+        meta[3 * kClasses] = items;  // total work items
+    }
+    __syncthreads();
+    // per-chunk bases: class base + counts of that class in earlier chunks
+    if (tid < kClasses) {
+        int run = cbase[tid];
+        for (int b = 0; b < nchunks; ++b) {
+            const int c = hist[b * kClasses + tid];
+            hist[b * kClasses + tid] = run;
+            run += c;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) ragged_scatter(int count, const int32_t* __restrict__ nvec,
+                                                      const int32_t* __restrict__ hist, int32_t* __restrict__ perm) {
+    __shared__ int32_t off[kClasses];
+    __shared__ int32_t wcnt[4][kClasses];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid < kClasses) off[tid] = hist[blockIdx.x * kClasses + tid];
+    __syncthreads();
+    const int base = blockIdx.x * kChunk;
+    const int end = min(base + kChunk, count);
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int s = base; s < end; s += 256) {
+        const int e = s + tid;
+        const int k = e < end ? class_of(nvec[e]) : -1;
+        int rank = 0;
+#pragma unroll
+        for (int c = 0; c < kClasses; ++c) {
+            const uint64_t m = __ballot(k == c);
+            if (k == c) rank = __popcll(m & lt);
+            if (lane == 0) wcnt[w][c] = __popcll(m);
+        }
+        __syncthreads();
+        if (k >= 0) {
+            int before = 0;
+            for (int ww = 0; ww < w; ++ww) before += wcnt[ww][k];
+            perm[off[k] + before + rank] = e;
+        }
+        __syncthreads();
+        if (tid < kClasses) off[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- solve --
+// Thread scope: lane q solves one problem of order n <= N, padded with an
+// identity block to N; its own rows are read and written with direct loads.
+template <int N>
+GLASS_DEV void ragged_thread_one(float* __restrict__ Ag, float* __restrict__ Bg, int n, int nrhs, int32_t* info) {
+    float a[N * (N + 1) / 2];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) a[TI(i, j)] = (i < n) ? Ag[i * n + j] : (i == j ? 1.f : 0.f);
+    float dinv[N];
+    const int inf = tri_potrf<N>(a, dinv);
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        if (i < n) {
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+                if (j < n) Ag[i * n + j] = j <= i ? a[TI(i, j)] : 0.f;
+        }
+    *info = inf;
+    if (inf != 0) return;
+    for (int c = 0; c < nrhs; ++c) {
+        float y[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) y[i] = i < n ? Bg[i * nrhs + c] : 0.f;
+        tri_fwd<N>(a, dinv, y);
+        tri_bwd<N>(a, dinv, y);
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (i < n) Bg[i * nrhs + c] = y[i];
+    }
+}
+
+template <int NB>
+GLASS_DEV void ragged_wave_one(float* __restrict__ Ag, float* __restrict__ Bg, int n, int nrhs, int32_t* info,
+                               float* buf, int lane) {
+    float a[NB];
+    rows_load_lower<NB>(a, Ag, n, lane);
+    float myinv;
+    const int inf = wave_potrf<NB>(a, lane, myinv);
+    const bool vec = false;  // problem offsets are arbitrary: 4-byte stores
+    if (inf != 0) {
+        wave_chunks_desc<NB>(a, buf, Ag, vec, n, lane, false, 0.f, myinv);
+    } else {
+        for (int c = 0; c < nrhs; ++c) {
+            float acc = lane < n ? Bg[lane * nrhs + c] : 0.f;
+            acc = wave_fwd<NB>(a, acc, myinv, lane);
+            acc = wave_chunks_desc<NB>(a, buf, c == 0 ? Ag : nullptr, vec, n, lane, true, acc, myinv);
+            if (lane < n) Bg[lane * nrhs + c] = acc;
+        }
+    }
+    if (lane == 0) *info = inf;
+}
+
+// One work item per wavefront: wavefront g of the launch takes item g of the
+// class-sorted work list (largest class first) and exits; waves past the
+// list's end exit at once.  There is no work-queue loop: a loop drawing items
+// from an atomic counter in lane 0 compiled to a per-lane exit in which lanes
+// 1..63 never saw a new item and could not leave, so the launch covers the
+// list instead and hardware dispatch order provides the largest-first order.
+__global__ void __launch_bounds__(256) ragged_solve(const int32_t* __restrict__ nvec,
+                                                    const int32_t* __restrict__ rvec,
+                                                    const int64_t* __restrict__ offA,
+                                                    const int64_t* __restrict__ offB, float* A, float* B,
+                                                    int32_t* info, const int32_t* __restrict__ perm,
+                                                    const int32_t* __restrict__ meta, RaggedScopes scopes) {
+    __shared__ float chunk[4][8 * 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int item = blockIdx.x * 4 + w;
+    if (item >= meta[3 * kClasses]) return;
+    int k = kClasses - 1;
+#pragma unroll
+    for (int c = 0; c < kClasses; ++c) {
+        const int cnt = meta[c], ib = meta[2 * kClasses + c];
+        const int nit = scopes.s[c] == GLASS_SCOPE_THREAD ? (cnt + 63) / 64 : cnt;
+        if (cnt > 0 && item >= ib && item < ib + nit) k = c;
+    }
+    const int rel = item - meta[2 * kClasses + k];
+    const int cbase = meta[kClasses + k];
+    if (scopes.s[k] == GLASS_SCOPE_THREAD) {
+        const int q = rel * 64 + lane;
+        if (q < meta[k]) {
+            const int e = perm[cbase + q];
+            const int n = nvec[e], r = rvec[e];
+            if (n < 1 || n > kMaxN || r < 1 || r > kMaxN) {
+                info[e] = -1;
+            } else {
+                ragged_thread_one<8>(A + offA[e], B + offB[e], n, r, info + e);  // class 0 only
+            }
+        }
+        return;
+    }
+    const int e = perm[cbase + rel];
+    const int n = nvec[e], r = rvec[e];
+    if (n < 1 || n > kMaxN || r < 1 || r > kMaxN) {
+        if (lane == 0) info[e] = -1;
+        return;
+    }
+    float* Ag = A + offA[e];
+    float* Bg = B + offB[e];
+    float* buf = chunk[w];
+    switch (k) {
+    case 0: ragged_wave_one<8>(Ag, Bg, n, r, info + e, buf, lane); break;
+    case 1: ragged_wave_one<16>(Ag, Bg, n, r, info + e, buf, lane); break;
+    case 2: ragged_wave_one<24>(Ag, Bg, n, r, info + e, buf, lane); break;
+    case 3: ragged_wave_one<32>(Ag, Bg, n, r, info + e, buf, lane); break;
+    case 4: ragged_wave_one<40>(Ag, Bg, n, r, info + e, buf, lane); break;
+    case 5: ragged_wave_one<48>(Ag, Bg, n, r, info + e, buf, lane); break;
+    case 6: ragged_wave_one<56>(Ag, Bg, n, r, info + e, buf, lane); break;
+    default: ragged_wave_one<64>(Ag, Bg, n, r, info + e, buf, lane); break;
+    }
+}
+
+}  // namespace
+
+size_t ragged_workspace_bytes(int count) {
+    const int nchunks = (count + kChunk - 1) / kChunk;
+    return sizeof(int32_t) * ((size_t)nchunks * kClasses + 32 + (size_t)count);
+}
+
+int launch_posv_ragged(int count, const int32_t* n, const int32_t* nrhs, const int64_t* offA, const int64_t* offB,
+                       float* A, float* B, int32_t* info, void* workspace, const RaggedScopes& scopes,
+                       void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const int nchunks = (count + kChunk - 1) / kChunk;
+    int32_t* hist = reinterpret_cast<int32_t*>(workspace);
+    int32_t* meta = hist + (size_t)nchunks * kClasses;
+    int32_t* perm = meta + 32;
+    hipLaunchKernelGGL(ragged_count, dim3(nchunks), dim3(256), 0, st, count, n, hist, meta);
+    hipLaunchKernelGGL(ragged_scan, dim3(1), dim3(kScanThreads), 0, st, nchunks, hist, meta, scopes);
+    hipLaunchKernelGGL(ragged_scatter, dim3(nchunks), dim3(256), 0, st, count, n, hist, perm);
+    // work items never outnumber problems: ceil(count / 4) four-wave blocks cover the list
+    hipLaunchKernelGGL(ragged_solve, dim3((count + 3) / 4), dim3(256), 0, st, n, nrhs, offA, offB, A, B, info, perm,
+                       meta, scopes);
+    return (int)hipGetLastError();
+}
+
+}  // namespace glass

@@ -57,6 +57,9 @@ _SIGS = {
     "glass_trsv_batched": [_i, _i, _i, _p, _p, _PP, _p],
     "glass_se3_batched": [_i, _i, _p, _p, _p, _PP, _p],
     "glass_posv_adjoint_batched": [_i, _i, _i, _p, _p, _p, _p, _p, _PP, _p],
+    "glass_posv_ragged": [_i, _p, _p, _p, _p, _p, _p, _p, _p, ctypes.c_size_t, _p, _p],
+    "glass_posv_ragged_workspace_size": [_i],
+    "glass_posv_ragged_perm_offset": [_i],
     "glass_query_placement": [_i, _i, _i, _PP],
     "glass_placement_feasible": [_i, _i, _i, _i, _i],
     "glass_table_provenance": [],
@@ -66,6 +69,8 @@ for _name, _args in _SIGS.items():
     _fn = getattr(_lib, _name)
     _fn.argtypes = _args
     _fn.restype = ctypes.c_char_p if _name in ("glass_table_provenance", "glass_status_string") else ctypes.c_int
+    if _name in ("glass_posv_ragged_workspace_size", "glass_posv_ragged_perm_offset"):
+        _fn.restype = ctypes.c_size_t
 
 EXPORTED = tuple(_SIGS)
 
@@ -133,6 +138,24 @@ def glass_se3_batched(op, batch, Ta, Tb, Tout, force=None, stream=None) -> int:
 def glass_posv_adjoint_batched(n, nrhs, batch, L, X, G, dB, dA, force=None, stream=None) -> int:
     return _lib.glass_posv_adjoint_batched(n, nrhs, batch, _ptr(L), _ptr(X), _ptr(G), _ptr(dB), _ptr(dA),
                                            _force(force), _stream(stream))
+
+
+def glass_posv_ragged(count, n, nrhs, offA, offB, A, B, info, workspace, workspace_bytes, class_scope=None,
+                      stream=None) -> int:
+    cs = None
+    if class_scope is not None:
+        vals = [SCOPES[v] if isinstance(v, str) else int(v) for v in class_scope]
+        cs = (ctypes.c_int32 * 8)(*vals)
+    return _lib.glass_posv_ragged(count, _ptr(n), _ptr(nrhs), _ptr(offA), _ptr(offB), _ptr(A), _ptr(B), _ptr(info),
+                                  _ptr(workspace), workspace_bytes, cs, _stream(stream))
+
+
+def glass_posv_ragged_workspace_size(count) -> int:
+    return _lib.glass_posv_ragged_workspace_size(count)
+
+
+def glass_posv_ragged_perm_offset(count) -> int:
+    return _lib.glass_posv_ragged_perm_offset(count)
 
 
 def glass_query_placement(op, n, batch) -> Placement:
@@ -276,3 +299,25 @@ def posv_adjoint(L, X, G, force=None):
     dA = torch.empty_like(L)
     _raise(glass_posv_adjoint_batched(n, r, b, L, X, G, dB, dA, force), "posv_adjoint")
     return dB, dA
+
+
+class Ragged:
+    """A packed ragged batch on the device plus its workspace (tensors kept)."""
+
+    def __init__(self, case: dict, device="cuda:0"):
+        import torch
+        self.count = len(case["n"])
+        t = lambda a: torch.from_numpy(a).to(device)
+        self.n, self.nrhs, self.offA, self.offB = t(case["n"]), t(case["nrhs"]), t(case["offA"]), t(case["offB"])
+        self.A, self.B = t(case["A"]), t(case["B"])
+        self.info = torch.zeros(self.count, dtype=torch.int32, device=device)
+        self.ws_bytes = glass_posv_ragged_workspace_size(self.count)
+        self.ws = torch.empty((self.ws_bytes + 3) // 4, dtype=torch.int32, device=device)
+
+    def solve(self, class_scope=None, stream=None):
+        _raise(glass_posv_ragged(self.count, self.n, self.nrhs, self.offA, self.offB, self.A, self.B, self.info,
+                                 self.ws, self.ws_bytes, class_scope, stream), "posv_ragged")
+
+    def perm(self):
+        off = glass_posv_ragged_perm_offset(self.count) // 4
+        return self.ws[off:off + self.count]

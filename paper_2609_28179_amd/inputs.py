@@ -178,3 +178,28 @@ def se3_torch(g, batch: int, device):
     T[:, :3, 3] = torch.rand((batch, 3), generator=g, device=device, dtype=torch.float64) * 2.0 - 1.0
     T[:, 3, 3] = 1.0
     return T.to(torch.float32)
+
+
+# ------------------------------------------------------------ ragged batches
+RAGGED_SIZES = (6, 7, 12, 14, 18, 24, 36, 48, 64)
+
+
+def make_ragged(count: int, seed: int = 2, sizes=RAGGED_SIZES, max_rhs: int = 8) -> dict:
+    """A ragged batch: n uniform over `sizes`, nrhs uniform over 1..max_rhs,
+    A = M M^T + n I per problem (as ``spd``), B iid uniform[-1, 1]; packed
+    row-major with int64 element offsets (exclusive prefix sums)."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, OP_IDS["ragged"], count]))
+    n = rng.choice(np.asarray(sizes, dtype=np.int32), size=count).astype(np.int32)
+    nrhs = rng.integers(1, max_rhs + 1, size=count).astype(np.int32)
+    sa = n.astype(np.int64) ** 2
+    sb = n.astype(np.int64) * nrhs
+    offA = np.concatenate([[0], np.cumsum(sa)[:-1]]).astype(np.int64)
+    offB = np.concatenate([[0], np.cumsum(sb)[:-1]]).astype(np.int64)
+    A = np.empty(int(sa.sum()), dtype=np.float32)
+    B = rng.uniform(-1.0, 1.0, size=int(sb.sum())).astype(np.float32)
+    for size in np.unique(n):
+        idx = np.nonzero(n == size)[0]
+        blocks = spd(rng, len(idx), int(size)).reshape(len(idx), -1)
+        for row, i in enumerate(idx):
+            A[offA[i]:offA[i] + sa[i]] = blocks[row]
+    return {"n": n, "nrhs": nrhs, "offA": offA, "offB": offB, "A": A, "B": B}

@@ -1,0 +1,55 @@
+"""Host-side checks of the ragged batch: generator shape, the CPU reference
+permutation, workspace size and argument validation (no device calls)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_28179_amd import inputs
+
+
+def test_generator_and_reference_order():
+    case = inputs.make_ragged(1000, seed=5)
+    n, r = case["n"], case["nrhs"]
+    assert set(np.unique(n)) <= set(inputs.RAGGED_SIZES)
+    assert r.min() >= 1 and r.max() <= 8
+    assert case["offA"][0] == 0 and np.all(np.diff(case["offA"]) == n[:-1].astype(np.int64) ** 2)
+    assert case["A"].size == int((n.astype(np.int64) ** 2).sum())
+    order = oracle.ragged_order(n)
+    cls = (n[order] - 1) // 8
+    assert np.all(np.diff(cls) <= 0)                      # largest class first
+    for c in np.unique(cls):                              # stable within a class
+        idx = order[cls == c]
+        assert np.all(np.diff(idx) > 0)
+    assert sorted(order.tolist()) == list(range(1000))
+
+
+def test_oracle_ragged_matches_per_problem_solve():
+    case = inputs.make_ragged(40, seed=9)
+    A_out, B_out, info = oracle.posv_ragged(case["n"], case["nrhs"], case["offA"], case["offB"], case["A"], case["B"])
+    assert (info == 0).all()
+    for i in (0, 7, 39):
+        n, r = int(case["n"][i]), int(case["nrhs"][i])
+        A = case["A"][case["offA"][i]:case["offA"][i] + n * n].reshape(n, n).astype(np.float64)
+        b = case["B"][case["offB"][i]:case["offB"][i] + n * r].reshape(n, r).astype(np.float64)
+        x = np.linalg.solve(A, b)
+        got = B_out[case["offB"][i]:case["offB"][i] + n * r].reshape(n, r)
+        assert np.max(np.abs(got - x)) <= 1e-10
+
+
+def test_ragged_validation_without_device():
+    from paper_2609_28179_amd import glass
+    F = 0x10000
+    assert glass.glass_posv_ragged_workspace_size(0) >= 32 * 4
+    w = glass.glass_posv_ragged_workspace_size(50000)
+    assert w == 4 * ((50000 + 1023) // 1024 * 8 + 32 + 50000)
+    assert glass.glass_posv_ragged_perm_offset(50000) == w - 4 * 50000
+    assert glass.glass_posv_ragged(0, None, None, None, None, None, None, None, None, 0, stream=0) == glass.OK
+    assert glass.glass_posv_ragged(-1, F, F, F, F, F, F, F, F, w, stream=0) == glass.ERR_INVALID_VALUE
+    assert glass.glass_posv_ragged(10, F, F, F, F, F, F, None, F, w, stream=0) == glass.ERR_INVALID_VALUE
+    assert glass.glass_posv_ragged(10, F, F, F, F, F, F, F, F, 8, stream=0) == glass.ERR_INVALID_VALUE
+    bad = ["wave"] * 8
+    bad[3] = "thread"
+    assert glass.glass_posv_ragged(10, F, F, F, F, F, F, F, F, w, class_scope=bad, stream=0) == \
+        glass.ERR_INFEASIBLE_PLACEMENT
+    assert glass.glass_posv_ragged(10, F, F, F, F, F, F, F, F, w, class_scope=[7] * 8, stream=0) == \
+        glass.ERR_INVALID_VALUE
