@@ -21,7 +21,6 @@ Prints one JSON line on stdout.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -38,52 +37,41 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2609_28179_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp", ".cpp", ".inc")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
-    return h.hexdigest()[:16]
-
-
-def cpu_baseline(cells, sets, shared, sample_cap, torch):
-    """Time the FP64 oracle on up to `sample_cap` problems of every cell."""
-    import numpy as np
+def cpu_baseline(cells, sets, shared, sample_cap, min_seconds, torch):
+    """Time the FP64 oracle on up to `sample_cap` problems of every cell,
+    repeating the pass over the cells until at least `min_seconds` of oracle
+    time have accumulated."""
     import oracle
-    from paper_2609_28179_amd import timing
 
-    t_est, sampled, total = 0.0, 0, 0
+    host, sampled, total = [], 0, 0
     for (op, n, batch) in cells:
         m = min(batch, sample_cap)
         src = dict(shared[(op, n, batch)])
         src.update(sets[0].get((op, n, batch), {}))
-        h = {k: v[:m].detach().cpu().numpy() for k, v in src.items() if v.dtype == torch.float32}
-        t0 = time.perf_counter()
-        if op == "gemm":
-            oracle.gemm(h["A"], h["B"])
-        elif op == "gemv":
-            oracle.gemv(h["A"], h["x"])
-        elif op == "potrf":
-            oracle.potrf(h["A"])
-        elif op == "posv":
-            oracle.posv(h["A"], h["B"])
-        elif op == "potrs":
-            oracle.potrs(h["L"], h["B"])
-        elif op == "trsv":
-            oracle.trsv(h["L"], h["x"], 0)
-        elif op == "se3_compose":
-            oracle.se3_compose(h["Ta"], h["Tb"])
-        else:
-            oracle.se3_inverse(h["Ta"])
-        dt = time.perf_counter() - t0
-        t_est += dt * batch / m
+        host.append((op, batch, m, {k: v[:m].detach().cpu().numpy() for k, v in src.items()
+                                    if v.dtype == torch.float32}))
         sampled += m
         total += batch
+    calls = {"gemm": lambda h: oracle.gemm(h["A"], h["B"]), "gemv": lambda h: oracle.gemv(h["A"], h["x"]),
+             "potrf": lambda h: oracle.potrf(h["A"]), "posv": lambda h: oracle.posv(h["A"], h["B"]),
+             "potrs": lambda h: oracle.potrs(h["L"], h["B"]), "trsv": lambda h: oracle.trsv(h["L"], h["x"], 0),
+             "se3_compose": lambda h: oracle.se3_compose(h["Ta"], h["Tb"]),
+             "se3_inverse": lambda h: oracle.se3_inverse(h["Ta"])}
+    t_est, spent, passes = 0.0, 0.0, 0
+    while passes == 0 or spent < min_seconds:
+        for op, batch, m, h in host:
+            t0 = time.perf_counter()
+            calls[op](h)
+            dt = time.perf_counter() - t0
+            spent += dt
+            t_est += dt * batch / m
+        passes += 1
+    t_est /= passes
+    scope = "every problem of the step" if sampled == total else \
+        f"the first min(batch, {sample_cap}) problems of each cell, time scaled to the full batch"
     return {"value": total / t_est, "unit": "solves/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"FP64 C oracle (OpenMP) on the first min(batch, {sample_cap}) problems of each of the "
-                      f"{len(cells)} cells ({sampled} problems), time scaled to the full batch; "
-                      f"estimated full-step time {t_est:.2f} s"}
+            "sample": f"FP64 C oracle (OpenMP) on {scope} ({len(cells)} cells, {sampled} of {total} problems), "
+                      f"{passes} passes, {spent:.1f} s of oracle time; {t_est:.2f} s per full step"}
 
 
 def main():
@@ -93,7 +81,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fixed", action="store_true", help="skip the fixed-placement comparator")
-    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--cpu-sample", type=int, default=65536,
+                    help="problems per cell the CPU oracle runs (65536: the whole step)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="repeat the oracle pass until this much CPU time has accumulated")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the batched problems are independent and this build "
@@ -220,6 +211,7 @@ def main():
     tpath = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tpath):
         t = json.load(open(tpath))
+        from paper_2609_28179_amd.traffic import kernel_source_hash
         if t.get("source_hash") == kernel_source_hash() and tuple(t.get("cell", ())) == tuple(dom):
             traffic = t.get("bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -230,7 +222,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         t0 = time.time()
-        cpu = cpu_baseline(cells, sets, shared, args.cpu_sample, torch)
+        cpu = cpu_baseline(cells, sets, shared, args.cpu_sample, args.cpu_seconds, torch)
         log(f"cpu baseline {cpu['value']:.3e} solves/s with {cpu['cores']} threads ({time.time() - t0:.1f} s)")
 
     out = {

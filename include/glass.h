@@ -205,6 +205,45 @@ glass_status_t glass_posv_ragged(int count, const int32_t* n, const int32_t* nrh
 size_t glass_posv_ragged_workspace_size(int count);
 size_t glass_posv_ragged_perm_offset(int count);
 
+/* Diagnostics of GLASS_ERR_LAUNCH: the HIP runtime error code of the most
+ * recent failed launch made by this library on the calling thread (0 if none;
+ * never reset), and the runtime's name for an error code (static string). */
+int glass_last_launch_error(void);
+const char* glass_hip_error_name(int code);
+
+/* Placement cost model: a 3-layer perceptron d -> 64 -> 64 -> 1 (ReLU) that
+ * predicts log run time from placement features, trained by the kernels
+ * below (the paper chooses placements by measurement only, Sec. III-A /
+ * Sec. IV-A; the model proposes placements for unmeasured shapes and the
+ * measured search stays the judge and the fallback).
+ * params: FP32 flat vector of glass_mlp_num_params(d) floats laid out as
+ * W1[64][d], b1[64], W2[64][64], b2[64], w3[64], b3.  X [N][d] row-major,
+ * y / t [N].  All pointers are DEVICE pointers; 1 <= d <= 32 (else
+ * GLASS_ERR_UNSUPPORTED). */
+size_t glass_mlp_num_params(int d);
+
+/* y = w3 . relu(W2 relu(W1 x + b1) + b2) + b3 per row of X.  H1, H2 [N][64]
+ * receive the two hidden activations (needed by the backward pass) or may be
+ * NULL. */
+glass_status_t glass_mlp_forward(int N, int d, const float* X, const float* params,
+                                 float* H1, float* H2, float* y, void* stream);
+
+/* grad = dL/dparams for L = (1/N) sum (y - t)^2, from the forward pass's X,
+ * H1, H2, y.  Deterministic: per-block partial sums (in `workspace`, at least
+ * glass_mlp_backward_workspace_size(N, d) bytes, 4-byte aligned) are added in
+ * a fixed order.  N >= 1. */
+size_t glass_mlp_backward_workspace_size(int N, int d);
+glass_status_t glass_mlp_backward(int N, int d, const float* X, const float* params,
+                                  const float* H1, const float* H2, const float* y,
+                                  const float* t, float* grad, void* workspace,
+                                  size_t workspace_bytes, void* stream);
+
+/* One Adam step (step >= 1) over P parameters: m = b1 m + (1-b1) g,
+ * v = b2 v + (1-b2) g^2, p -= lr (m/(1-b1^step)) / (sqrt(v/(1-b2^step)) + eps). */
+glass_status_t glass_mlp_adam(int P, float* params, const float* grad, float* m, float* v,
+                              int step, float lr, float beta1, float beta2, float eps,
+                              void* stream);
+
 /* The advisor (Sec. III-A): the placement the built-in table gives for
  * (op, n, batch), written to *out (HOST pointer).  Lookup rule: n_key = the
  * smallest tabulated n >= n (n <= 2 maps to the smallest key); batch_key =

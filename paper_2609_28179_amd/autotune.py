@@ -3,7 +3,7 @@ on the target GPU, store the choice in an architecture-specific table;
 Sec. IV-A: paired randomized rounds, fresh inputs for destructive ops, raw
 samples kept, a 5 % dispatch margin).
 
-  python -m paper_2609_28179_amd.autotune sweep [--rounds 20] [--out FILE]
+  python -m paper_2609_28179_amd.autotune sweep [--rounds 20] [--out FILE] [--cells table|heldout]
   python -m paper_2609_28179_amd.autotune emit  [--sweep FILE] [--out INC]
   python -m paper_2609_28179_amd.autotune summary [--sweep FILE]
 
@@ -68,7 +68,7 @@ def sweep(args):
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     meta, recs = load(args.out)
     done = {(r["op"], r["n"], r["batch"]) for r in recs}
-    cells = timing.sweep_cells()
+    cells = timing.heldout_cells() if args.cells == "heldout" else timing.sweep_cells()
     if args.ops:
         cells = [c for c in cells if c[0] in args.ops.split(",")]
     if args.max_batch:
@@ -200,6 +200,9 @@ def main(argv=None):
     s.add_argument("--seed", type=int, default=0)
     s.add_argument("--ops", default="")
     s.add_argument("--max-batch", type=int, default=0)
+    s.add_argument("--cells", choices=("table", "heldout"), default="table",
+                   help="table: the 250 cells of the dispatch table; heldout: n in {5,9,20,48} x "
+                        "batch in {256,65536}, the cost model's evaluation set")
     e = sub.add_parser("emit")
     e.add_argument("--sweep", default=DEFAULT_SWEEP)
     e.add_argument("--out", default=DEFAULT_INC)

@@ -132,6 +132,7 @@ inline int bucket8(int n) { return ((n + 7) / 8) * 8; }
 
 int launch_posv_adjoint(const Shape& sh, const Geometry& g, int batch, const float* L, const float* X,
                         const float* G, float* dB, float* dA, void* stream) {
+    (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
     hipStream_t st = (hipStream_t)stream;
     const int n = sh.n, r = sh.nrhs;
     dim3 grid((unsigned)g.grid), block(g.threads);

@@ -70,7 +70,13 @@ glass_status_t resolve(const Shape& s, long long batch, const glass_placement_t*
     return GLASS_ERR_INFEASIBLE_PLACEMENT;
 }
 
-inline glass_status_t launched(int err) { return err == 0 ? GLASS_OK : GLASS_ERR_LAUNCH; }
+thread_local int t_last_launch_error = 0;
+
+inline glass_status_t launched(int err) {
+    if (err == 0) return GLASS_OK;
+    t_last_launch_error = err;
+    return GLASS_ERR_LAUNCH;
+}
 
 }  // namespace
 }  // namespace glass
@@ -220,6 +226,46 @@ glass_status_t glass_posv_ragged(int count, const int32_t* n, const int32_t* nrh
     if (workspace_bytes < ragged_workspace_bytes(count) || (reinterpret_cast<uintptr_t>(workspace) & 3))
         return GLASS_ERR_INVALID_VALUE;
     return launched(launch_posv_ragged(count, n, nrhs, offA, offB, A, B, info, workspace, sc, stream));
+}
+
+int glass_last_launch_error(void) { return t_last_launch_error; }
+
+const char* glass_hip_error_name(int code) { return hip_error_name(code); }
+
+size_t glass_mlp_num_params(int d) { return (d >= 1 && d <= 32) ? mlp_num_params(d) : 0; }
+
+size_t glass_mlp_backward_workspace_size(int N, int d) {
+    return (N >= 0 && d >= 1 && d <= 32) ? mlp_backward_workspace_bytes(N, d) : 0;
+}
+
+glass_status_t glass_mlp_forward(int N, int d, const float* X, const float* params, float* H1, float* H2, float* y,
+                                 void* stream) {
+    if (d < 1 || d > 32) return GLASS_ERR_UNSUPPORTED;
+    if (N < 0) return GLASS_ERR_INVALID_VALUE;
+    if (N == 0) return GLASS_OK;
+    if (!X || !params || !y) return GLASS_ERR_INVALID_VALUE;
+    return launched(launch_mlp_forward(N, d, X, params, H1, H2, y, stream));
+}
+
+glass_status_t glass_mlp_backward(int N, int d, const float* X, const float* params, const float* H1,
+                                  const float* H2, const float* y, const float* t, float* grad, void* workspace,
+                                  size_t workspace_bytes, void* stream) {
+    if (d < 1 || d > 32) return GLASS_ERR_UNSUPPORTED;
+    if (N < 1) return GLASS_ERR_INVALID_VALUE;
+    if (!X || !params || !H1 || !H2 || !y || !t || !grad || !workspace) return GLASS_ERR_INVALID_VALUE;
+    if (workspace_bytes < mlp_backward_workspace_bytes(N, d) || (reinterpret_cast<uintptr_t>(workspace) & 3))
+        return GLASS_ERR_INVALID_VALUE;
+    return launched(launch_mlp_backward(N, d, X, params, H1, H2, y, t, grad, workspace, stream));
+}
+
+glass_status_t glass_mlp_adam(int P, float* params, const float* grad, float* m, float* v, int step, float lr,
+                              float beta1, float beta2, float eps, void* stream) {
+    if (P < 0 || step < 1) return GLASS_ERR_INVALID_VALUE;
+    if (P == 0) return GLASS_OK;
+    if (!params || !grad || !m || !v) return GLASS_ERR_INVALID_VALUE;
+    const float bc1 = (float)(1.0 - pow((double)beta1, step));
+    const float bc2 = (float)(1.0 - pow((double)beta2, step));
+    return launched(launch_mlp_adam(P, params, grad, m, v, lr, beta1, beta2, eps, bc1, bc2, stream));
 }
 
 glass_status_t glass_query_placement(glass_op_t op, int n, int batch, glass_placement_t* out) {

@@ -352,6 +352,7 @@ inline int finish() { return (int)hipGetLastError(); }
 }  // namespace
 
 int launch_potrf(const Shape& sh, const Geometry& g, int batch, float* A, int32_t* info, void* stream) {
+    (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
     hipStream_t st = (hipStream_t)stream;
     const int n = sh.n;
     dim3 grid((unsigned)g.grid), block(g.threads);
@@ -379,6 +380,7 @@ int launch_potrf(const Shape& sh, const Geometry& g, int batch, float* A, int32_
 }
 
 int launch_posv(const Shape& sh, const Geometry& g, int batch, float* A, float* B, int32_t* info, void* stream) {
+    (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
     hipStream_t st = (hipStream_t)stream;
     const int n = sh.n, r = sh.nrhs;
     dim3 grid((unsigned)g.grid), block(g.threads);
@@ -406,6 +408,7 @@ int launch_posv(const Shape& sh, const Geometry& g, int batch, float* A, float* 
 }
 
 int launch_potrs(const Shape& sh, const Geometry& g, int batch, const float* L, float* B, void* stream) {
+    (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
     hipStream_t st = (hipStream_t)stream;
     const int n = sh.n, r = sh.nrhs;
     dim3 grid((unsigned)g.grid), block(g.threads);
@@ -433,6 +436,7 @@ int launch_potrs(const Shape& sh, const Geometry& g, int batch, const float* L, 
 }
 
 int launch_trsv(const Shape& sh, const Geometry& g, int batch, const float* L, float* x, void* stream) {
+    (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
     hipStream_t st = (hipStream_t)stream;
     const int n = sh.n, tr = sh.trans;
     dim3 grid((unsigned)g.grid), block(g.threads);

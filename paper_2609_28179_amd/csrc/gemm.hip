@@ -225,6 +225,7 @@ __global__ void __launch_bounds__(256) gemm_mfma_wg(int m, int n, int k, int bat
 
 int launch_gemm(const Shape& sh, const Geometry& g, int batch, float alpha, const float* A, const float* B,
                 float beta, float* C, void* stream) {
+    (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
     hipStream_t st = (hipStream_t)stream;
     const int m = sh.m, n = sh.n, k = sh.k;
     dim3 grid((unsigned)g.grid), block(g.threads);

@@ -196,6 +196,14 @@ size_t ragged_workspace_bytes(int count);
 int launch_posv_ragged(int count, const int32_t* n, const int32_t* nrhs, const int64_t* offA, const int64_t* offB,
                        float* A, float* B, int32_t* info, void* workspace, const RaggedScopes& scopes,
                        void* stream);
+const char* hip_error_name(int code);
+size_t mlp_num_params(int d);
+size_t mlp_backward_workspace_bytes(int N, int d);
+int launch_mlp_forward(int N, int d, const float* X, const float* P, float* H1, float* H2, float* Y, void* stream);
+int launch_mlp_backward(int N, int d, const float* X, const float* P, const float* H1, const float* H2,
+                        const float* Y, const float* T, float* grad, void* workspace, void* stream);
+int launch_mlp_adam(int P, float* p, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
+                    float bc1, float bc2, void* stream);
 int launch_posv_adjoint(const Shape& s, const Geometry& g, int batch, const float* L, const float* X,
                         const float* G, float* dB, float* dA, void* stream);
 

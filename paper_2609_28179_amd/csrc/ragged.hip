@@ -244,6 +244,7 @@ size_t ragged_workspace_bytes(int count) {
 int launch_posv_ragged(int count, const int32_t* n, const int32_t* nrhs, const int64_t* offA, const int64_t* offB,
                        float* A, float* B, int32_t* info, void* workspace, const RaggedScopes& scopes,
                        void* stream) {
+    (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
     hipStream_t st = (hipStream_t)stream;
     const int nchunks = (count + kChunk - 1) / kChunk;
     int32_t* hist = reinterpret_cast<int32_t*>(workspace);

@@ -122,6 +122,7 @@ __global__ void __launch_bounds__(64) se3_wg(int inverse, int batch, int pack, c
 
 int launch_se3(const Shape& sh, const Geometry& g, int batch, const float* Ta, const float* Tb, float* Tout,
                void* stream) {
+    (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
     hipStream_t st = (hipStream_t)stream;
     const int inv = sh.op == GLASS_OP_SE3_INVERSE;
     dim3 grid((unsigned)g.grid), block(g.threads);

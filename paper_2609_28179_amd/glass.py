@@ -9,11 +9,20 @@ outputs with torch and raise :class:`GlassError` on a nonzero status.
 
 Importing this module loads the built library and raises ImportError when it
 is missing: there is no fallback path.
+
+torch is imported before the library is loaded.  torch's HIP build asks for
+its own copy of the HIP runtime by the unversioned file name; were the
+library (which asks for ``libamdhip64.so.7``) loaded first, the process would
+hold two runtimes, and torch's streams and allocations would belong to the
+other one (launches then fail with hipErrorNoDevice).  Loaded after torch,
+the library binds to torch's runtime.
 """
 from __future__ import annotations
 
 import ctypes
 import os
+
+import torch  # noqa: F401  (must precede the CDLL below, see above)
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libglass.so")
@@ -60,6 +69,13 @@ _SIGS = {
     "glass_posv_ragged": [_i, _p, _p, _p, _p, _p, _p, _p, _p, ctypes.c_size_t, _p, _p],
     "glass_posv_ragged_workspace_size": [_i],
     "glass_posv_ragged_perm_offset": [_i],
+    "glass_last_launch_error": [],
+    "glass_hip_error_name": [_i],
+    "glass_mlp_num_params": [_i],
+    "glass_mlp_forward": [_i, _i, _p, _p, _p, _p, _p, _p],
+    "glass_mlp_backward_workspace_size": [_i, _i],
+    "glass_mlp_backward": [_i, _i, _p, _p, _p, _p, _p, _p, _p, _p, ctypes.c_size_t, _p],
+    "glass_mlp_adam": [_i, _p, _p, _p, _p, _i, _f, _f, _f, _f, _p],
     "glass_query_placement": [_i, _i, _i, _PP],
     "glass_placement_feasible": [_i, _i, _i, _i, _i],
     "glass_table_provenance": [],
@@ -68,8 +84,10 @@ _SIGS = {
 for _name, _args in _SIGS.items():
     _fn = getattr(_lib, _name)
     _fn.argtypes = _args
-    _fn.restype = ctypes.c_char_p if _name in ("glass_table_provenance", "glass_status_string") else ctypes.c_int
-    if _name in ("glass_posv_ragged_workspace_size", "glass_posv_ragged_perm_offset"):
+    _fn.restype = ctypes.c_char_p if _name in ("glass_table_provenance", "glass_status_string",
+                                               "glass_hip_error_name") else ctypes.c_int
+    if _name in ("glass_posv_ragged_workspace_size", "glass_posv_ragged_perm_offset", "glass_mlp_num_params",
+                 "glass_mlp_backward_workspace_size"):
         _fn.restype = ctypes.c_size_t
 
 EXPORTED = tuple(_SIGS)
@@ -158,6 +176,36 @@ def glass_posv_ragged_perm_offset(count) -> int:
     return _lib.glass_posv_ragged_perm_offset(count)
 
 
+def glass_last_launch_error() -> int:
+    return _lib.glass_last_launch_error()
+
+
+def glass_hip_error_name(code) -> str:
+    return _lib.glass_hip_error_name(code).decode()
+
+
+def glass_mlp_num_params(d) -> int:
+    return _lib.glass_mlp_num_params(d)
+
+
+def glass_mlp_forward(N, d, X, params, H1, H2, y, stream=None) -> int:
+    return _lib.glass_mlp_forward(N, d, _ptr(X), _ptr(params), _ptr(H1), _ptr(H2), _ptr(y), _stream(stream))
+
+
+def glass_mlp_backward_workspace_size(N, d) -> int:
+    return _lib.glass_mlp_backward_workspace_size(N, d)
+
+
+def glass_mlp_backward(N, d, X, params, H1, H2, y, t, grad, workspace, workspace_bytes, stream=None) -> int:
+    return _lib.glass_mlp_backward(N, d, _ptr(X), _ptr(params), _ptr(H1), _ptr(H2), _ptr(y), _ptr(t), _ptr(grad),
+                                   _ptr(workspace), workspace_bytes, _stream(stream))
+
+
+def glass_mlp_adam(P, params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None) -> int:
+    return _lib.glass_mlp_adam(P, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), step, lr, beta1, beta2, eps,
+                               _stream(stream))
+
+
 def glass_query_placement(op, n, batch) -> Placement:
     out = Placement()
     st = _lib.glass_query_placement(op, n, batch, ctypes.byref(out))
@@ -195,6 +243,9 @@ def _check(t, name, shape=None, dtype=None):
 
 
 def _raise(st, what):
+    if st == ERR_LAUNCH:
+        code = _lib.glass_last_launch_error()
+        raise GlassError(st, f"{what} [HIP {_lib.glass_hip_error_name(code).decode()} ({code})]")
     if st != OK:
         raise GlassError(st, what)
 

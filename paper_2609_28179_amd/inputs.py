@@ -180,6 +180,18 @@ def se3_torch(g, batch: int, device):
     return T.to(torch.float32)
 
 
+# ----------------------------------------------------- cost-model initial weights
+def mlp_init(d: int, seed: int, hidden: int = 64) -> np.ndarray:
+    """He-normal initial weights of the d -> 64 -> 64 -> 1 cost model (std
+    sqrt(2 / fan_in), zero biases) as one flat float64 vector in the order
+    W1 [64][d], b1, W2 [64][64], b2, w3, b3."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, d, hidden]))
+    W1 = rng.standard_normal((hidden, d)) * np.sqrt(2.0 / d)
+    W2 = rng.standard_normal((hidden, hidden)) * np.sqrt(2.0 / hidden)
+    w3 = rng.standard_normal(hidden) * np.sqrt(2.0 / hidden)
+    return np.concatenate([W1.ravel(), np.zeros(hidden), W2.ravel(), np.zeros(hidden), w3, [0.0]])
+
+
 # ------------------------------------------------------------ ragged batches
 RAGGED_SIZES = (6, 7, 12, 14, 18, 24, 36, 48, 64)
 

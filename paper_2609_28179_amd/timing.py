@@ -31,6 +31,8 @@ SE3_OPS = ("se3_compose", "se3_inverse")
 SWEEP_N = (3, 4, 6, 7, 12, 16, 32, 64)
 SWEEP_B = (1, 16, 256, 4096, 65536)
 PACKS = (1, 2, 4, 8)
+HELDOUT_N = (5, 9, 20, 48)          # orders the table does not hold (cost-model evaluation)
+HELDOUT_B = (256, 65536)
 GIB = 1 << 30
 
 
@@ -65,6 +67,10 @@ def sweep_cells():
     cells = [(op, n, b) for op in SWEEP_OPS for n in SWEEP_N for b in SWEEP_B]
     cells += [(op, 4, b) for op in SE3_OPS for b in SWEEP_B]
     return cells
+
+
+def heldout_cells():
+    return [(op, n, b) for op in SWEEP_OPS for n in HELDOUT_N for b in HELDOUT_B]
 
 
 def feasible_placements(glass, op: str, n: int, nrhs: int = 1):

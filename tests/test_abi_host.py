@@ -69,6 +69,29 @@ def test_validation_paths(glass):
         assert g.status_string(s).startswith("GLASS_")
 
 
+def test_mlp_validation_paths(glass):
+    g = glass
+    S = 0
+    assert g.glass_mlp_num_params(14) == 5185 and g.glass_mlp_num_params(0) == 0 and g.glass_mlp_num_params(33) == 0
+    assert g.glass_mlp_backward_workspace_size(64, 14) == 2 * 5185 * 4
+    assert g.glass_mlp_backward_workspace_size(65, 14) == 3 * 5185 * 4
+    assert g.glass_mlp_forward(4, 0, FAKE, FAKE, None, None, FAKE, stream=S) == g.ERR_UNSUPPORTED
+    assert g.glass_mlp_forward(4, 33, FAKE, FAKE, None, None, FAKE, stream=S) == g.ERR_UNSUPPORTED
+    assert g.glass_mlp_forward(-1, 14, FAKE, FAKE, None, None, FAKE, stream=S) == g.ERR_INVALID_VALUE
+    assert g.glass_mlp_forward(0, 14, None, None, None, None, None, stream=S) == g.OK
+    assert g.glass_mlp_forward(4, 14, FAKE, None, None, None, FAKE, stream=S) == g.ERR_INVALID_VALUE
+    ws = g.glass_mlp_backward_workspace_size(4, 14)
+    assert g.glass_mlp_backward(0, 14, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, ws, stream=S) \
+        == g.ERR_INVALID_VALUE
+    assert g.glass_mlp_backward(4, 14, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, ws - 4, stream=S) \
+        == g.ERR_INVALID_VALUE
+    assert g.glass_mlp_backward(4, 14, FAKE, FAKE, None, FAKE, FAKE, FAKE, FAKE, FAKE, ws, stream=S) \
+        == g.ERR_INVALID_VALUE
+    assert g.glass_mlp_adam(0, None, None, None, None, 1, 1e-3, stream=S) == g.OK
+    assert g.glass_mlp_adam(8, FAKE, FAKE, FAKE, FAKE, 0, 1e-3, stream=S) == g.ERR_INVALID_VALUE
+    assert g.glass_mlp_adam(8, FAKE, FAKE, None, FAKE, 1, 1e-3, stream=S) == g.ERR_INVALID_VALUE
+
+
 def test_query_placement_matches_reference_lookup(glass):
     table = pref.load_table(os.path.join(ROOT, "paper_2609_28179_amd", "csrc", "glass_table_gfx950.inc"))
     batches = [1, 2, 3, 4, 5, 8, 15, 16, 17, 63, 64, 65, 255, 256, 257, 1000, 1024, 1025, 4095, 4096,
@@ -119,3 +142,18 @@ def test_feasibility_rule_shape(glass):
                 for pack in (1, 2, 4, 8):
                     if n > 1 and g.glass_placement_feasible(op, n, 1, scope, pack) == 1:
                         assert g.glass_placement_feasible(op, n - 1, 1, scope, pack) == 1
+
+
+def test_single_hip_runtime_in_process():
+    """Importing the binding first must still leave one HIP runtime mapped:
+    the library has to share torch's runtime (streams, allocations)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2609_28179_amd import glass\n"
+            "import torch\n"
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    libs = eval(out.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1, libs
