@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fixed", action="store_true", help="skip the fixed-placement comparator")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the small-POSV, ragged and adjoint workload timings")
     ap.add_argument("--cpu-sample", type=int, default=65536,
                     help="problems per cell the CPU oracle runs (65536: the whole step)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -219,6 +221,15 @@ def main():
                 "kernel": f"{op} n={n} batch={batch} at {glass.SCOPE_NAMES[pl.scope]}/P={pl.pack}",
                 "alg_bytes_per_launch": dom_bytes, "avg_launch_us": round(dom_us, 2)}
 
+    extras = None
+    if not args.no_extras:
+        from paper_2609_28179_amd import workloads
+        t0 = time.time()
+        extras = {"posv_small": workloads.posv_small(glass, torch),
+                  "ragged": workloads.ragged(glass, torch),
+                  "adjoint": workloads.adjoint(glass, torch)}
+        log(f"workloads ({time.time() - t0:.1f} s): " + json.dumps(extras))
+
     cpu = None
     if not args.no_cpu:
         t0 = time.time()
@@ -237,6 +248,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fixed_placement": fixed,
+        "workloads": extras,
     }
     print(json.dumps(out), flush=True)
     return 0

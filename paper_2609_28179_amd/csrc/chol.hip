@@ -116,7 +116,9 @@ __global__ void __launch_bounds__(512) potrf_wave(int n, int batch, float* __res
     if (info && lane == 0) info[p] = inf;
 }
 
-template <int NB>
+// MULTI: several right-hand sides are solved in column groups; the nrhs = 1
+// instance keeps only the single-column path and its register budget.
+template <int NB, bool MULTI>
 __global__ void __launch_bounds__(512) posv_wave(int n, int nrhs, int batch, float* __restrict__ A,
                                                  float* __restrict__ B, int* __restrict__ info, int region) {
     extern __shared__ float lds[];
@@ -133,18 +135,18 @@ __global__ void __launch_bounds__(512) posv_wave(int n, int nrhs, int batch, flo
     const bool vec = (n & 3) == 0 && aligned16(A);
     if (inf != 0) {
         wave_chunks_desc<NB>(a, buf, Ag, vec, n, lane, false, 0.f, myinv);
+    } else if (MULTI) {
+        wave_solve_all<NB>(a, buf, Ag, vec, Bg, n, nrhs, myinv, lane);
     } else {
-        for (int c = 0; c < nrhs; ++c) {
-            float acc = lane < n ? Bg[lane * nrhs + c] : 0.f;
-            acc = wave_fwd<NB>(a, acc, myinv, lane);
-            acc = wave_chunks_desc<NB>(a, buf, c == 0 ? Ag : nullptr, vec, n, lane, true, acc, myinv);
-            if (lane < n) Bg[lane * nrhs + c] = acc;
-        }
+        float acc = lane < n ? Bg[lane] : 0.f;
+        acc = wave_fwd<NB>(a, acc, myinv, lane);
+        acc = wave_chunks_desc<NB>(a, buf, Ag, vec, n, lane, true, acc, myinv);
+        if (lane < n) Bg[lane] = acc;
     }
     if (info && lane == 0) info[p] = inf;
 }
 
-template <int NB>
+template <int NB, bool MULTI>
 __global__ void __launch_bounds__(512) potrs_wave(int n, int nrhs, int batch, const float* __restrict__ L,
                                                   float* __restrict__ B, int region) {
     extern __shared__ float lds[];
@@ -157,11 +159,13 @@ __global__ void __launch_bounds__(512) potrs_wave(int n, int nrhs, int batch, co
     float a[NB];
     rows_load_lower<NB>(a, Lg, n, lane);
     const float myinv = diag_inv(Lg, n, lane);
-    for (int c = 0; c < nrhs; ++c) {
-        float acc = lane < n ? Bg[lane * nrhs + c] : 0.f;
+    if (MULTI) {
+        wave_solve_all<NB>(a, buf, nullptr, false, Bg, n, nrhs, myinv, lane);
+    } else {
+        float acc = lane < n ? Bg[lane] : 0.f;
         acc = wave_fwd<NB>(a, acc, myinv, lane);
         acc = wave_chunks_desc<NB>(a, buf, nullptr, false, n, lane, true, acc, myinv);
-        if (lane < n) Bg[lane * nrhs + c] = acc;
+        if (lane < n) Bg[lane] = acc;
     }
 }
 
@@ -396,7 +400,12 @@ int launch_posv(const Shape& sh, const Geometry& g, int batch, float* A, float* 
         const int region = (int)wave_region_floats(sh);
         switch (bucket8(n)) {
 #define X(NB) \
-    case NB: hipLaunchKernelGGL(posv_wave<NB>, grid, block, g.lds_bytes, st, n, r, batch, A, B, info, region); break;
+    case NB:                                                                                                  \
+        if (r == 1)                                                                                           \
+            hipLaunchKernelGGL((posv_wave<NB, false>), grid, block, g.lds_bytes, st, n, r, batch, A, B, info, region); \
+        else                                                                                                  \
+            hipLaunchKernelGGL((posv_wave<NB, true>), grid, block, g.lds_bytes, st, n, r, batch, A, B, info, region);  \
+        break;
             GLASS_BUCKETS(X)
 #undef X
         default: return (int)hipErrorInvalidValue;
@@ -424,7 +433,12 @@ int launch_potrs(const Shape& sh, const Geometry& g, int batch, const float* L, 
         const int region = (int)wave_region_floats(sh);
         switch (bucket8(n)) {
 #define X(NB) \
-    case NB: hipLaunchKernelGGL(potrs_wave<NB>, grid, block, g.lds_bytes, st, n, r, batch, L, B, region); break;
+    case NB:                                                                                                  \
+        if (r == 1)                                                                                           \
+            hipLaunchKernelGGL((potrs_wave<NB, false>), grid, block, g.lds_bytes, st, n, r, batch, L, B, region); \
+        else                                                                                                  \
+            hipLaunchKernelGGL((potrs_wave<NB, true>), grid, block, g.lds_bytes, st, n, r, batch, L, B, region);  \
+        break;
             GLASS_BUCKETS(X)
 #undef X
         default: return (int)hipErrorInvalidValue;

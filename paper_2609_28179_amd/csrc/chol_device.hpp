@@ -296,6 +296,77 @@ GLASS_DEV float wave_chunks_desc(const float (&a)[NB], float* buf, float* Lg, bo
     return acc;
 }
 
+// ------------------------------------------- several right-hand sides at once
+// The substitutions for RG columns run in one sweep: each step broadcasts RG
+// unknowns (independent v_readlane) and updates RG accumulators, so the
+// dependent chain is n steps for the whole group instead of n per column.
+template <int NB, int RG>
+GLASS_DEV void wave_fwd_rg(const float (&a)[NB], float (&acc)[RG], float myinv, int lane) {
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        float yk[RG];
+#pragma unroll
+        for (int c = 0; c < RG; ++c) yk[c] = readlane(acc[c] * myinv, k);
+#pragma unroll
+        for (int c = 0; c < RG; ++c) acc[c] = lane == k ? yk[c] : fmaf(-a[k], yk[c], acc[c]);
+    }
+}
+
+template <int RG>
+GLASS_DEV void wave_bwd_chunk_rg(const float* buf, int n, int r0, int r1, float (&acc)[RG], float myinv, int lane) {
+    for (int k = r1 - 1; k >= r0; --k) {
+        const float lki = lane < k ? buf[(k - r0) * n + lane] : 0.f;
+        float xk[RG];
+#pragma unroll
+        for (int c = 0; c < RG; ++c) xk[c] = readlane(acc[c] * myinv, k);
+#pragma unroll
+        for (int c = 0; c < RG; ++c) acc[c] = lane == k ? xk[c] : fmaf(-lki, xk[c], acc[c]);
+    }
+}
+
+// Columns c0 .. c0+RG-1 of the row-major [n][nrhs] block Bg (columns past
+// nrhs are zero padding and are not stored); the backward sweep walks the
+// 8-row chunks of L bottom-up and, when Lg is given, also stores L.
+template <int NB, int RG>
+GLASS_DEV void wave_solve_cols(const float (&a)[NB], float* buf, float* Lg, bool vec, float* Bg, int n, int nrhs,
+                               int c0, float myinv, int lane) {
+    float acc[RG];
+#pragma unroll
+    for (int c = 0; c < RG; ++c) acc[c] = (lane < n && c0 + c < nrhs) ? Bg[lane * nrhs + c0 + c] : 0.f;
+    wave_fwd_rg<NB, RG>(a, acc, myinv, lane);
+    for (int r0 = (n - 1) & ~7; r0 >= 0; r0 -= 8) {
+        const int r1 = min(r0 + 8, n);
+        rows_to_lds<NB>(a, buf, n, r0, lane);
+        wave_sync();
+        if (Lg) chunk_to_global(Lg + r0 * n, buf, (r1 - r0) * n, vec, lane);
+        wave_bwd_chunk_rg<RG>(buf, n, r0, r1, acc, myinv, lane);
+        wave_sync();
+    }
+#pragma unroll
+    for (int c = 0; c < RG; ++c)
+        if (lane < n && c0 + c < nrhs) Bg[lane * nrhs + c0 + c] = acc[c];
+}
+
+// All nrhs columns in groups of 8, 4 or 1 (L stored during the first group).
+template <int NB>
+GLASS_DEV void wave_solve_all(const float (&a)[NB], float* buf, float* Lg, bool vec, float* Bg, int n, int nrhs,
+                              float myinv, int lane) {
+    for (int c0 = 0; c0 < nrhs;) {
+        float* L = c0 == 0 ? Lg : nullptr;
+        const int left = nrhs - c0;
+        if (left >= 5) {
+            wave_solve_cols<NB, 8>(a, buf, L, vec, Bg, n, nrhs, c0, myinv, lane);
+            c0 += 8;
+        } else if (left >= 2) {
+            wave_solve_cols<NB, 4>(a, buf, L, vec, Bg, n, nrhs, c0, myinv, lane);
+            c0 += 4;
+        } else {
+            wave_solve_cols<NB, 1>(a, buf, L, vec, Bg, n, nrhs, c0, myinv, lane);
+            c0 += 1;
+        }
+    }
+}
+
 // 1 / L_ii of lane i's row (1 beyond n), read from global memory.
 GLASS_DEV float diag_inv(const float* Lg, int n, int lane) {
     return lane < n ? 1.0f / Lg[lane * n + lane] : 1.f;

@@ -165,12 +165,7 @@ GLASS_DEV void ragged_wave_one(float* __restrict__ Ag, float* __restrict__ Bg, i
     if (inf != 0) {
         wave_chunks_desc<NB>(a, buf, Ag, vec, n, lane, false, 0.f, myinv);
     } else {
-        for (int c = 0; c < nrhs; ++c) {
-            float acc = lane < n ? Bg[lane * nrhs + c] : 0.f;
-            acc = wave_fwd<NB>(a, acc, myinv, lane);
-            acc = wave_chunks_desc<NB>(a, buf, c == 0 ? Ag : nullptr, vec, n, lane, true, acc, myinv);
-            if (lane < n) Bg[lane * nrhs + c] = acc;
-        }
+        wave_solve_all<NB>(a, buf, Ag, vec, Bg, n, nrhs, myinv, lane);
     }
     if (lane == 0) *info = inf;
 }

@@ -1,0 +1,146 @@
+"""Timings of the workloads beside the placement-sweep step: the plain small
+POSV, the ragged batch against per-size launches, and the Cholesky-solve
+adjoint.  Each returns a small dict for the benchmark's JSON line.
+
+All timings are device-side: HIP graphs replayed between two events, inputs
+resident in HBM, destructive inputs restored from a pristine copy outside the
+events.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import inputs, timing
+
+
+def _median_us(samples):
+    return float(np.median(samples))
+
+
+def posv_small(glass, torch, n=6, batch=1024, rounds=20):
+    """POSV n x n, one right-hand side, `batch` systems: microseconds per
+    launch at the fixed wavefront placement (one system per 64-lane
+    workgroup) and at the table's placement."""
+    dev = torch.device("cuda:0")
+    table = glass.glass_query_placement(glass.OP_POSV, n, batch)
+    pls = [(glass.SCOPE_WAVE, 1)]
+    if (table.scope, table.pack) != pls[0]:
+        pls.append((table.scope, table.pack))
+    cell = timing.Cell(torch, "posv", n, batch, dev, seed=0)
+    s = timing.time_cell(glass, torch, cell, pls, rounds=rounds)
+    fixed = _median_us(s[pls[0]])
+    tuned = _median_us(s[(table.scope, table.pack)])
+    return {"workload": f"posv n={n} nrhs=1 batch={batch}",
+            "fixed_wave_p1_us": round(fixed, 3), "fixed_solves_per_s": round(batch / (fixed * 1e-6), 1),
+            "table": f"{glass.SCOPE_NAMES[table.scope]}/P={table.pack}", "table_us": round(tuned, 3),
+            "table_solves_per_s": round(batch / (tuned * 1e-6), 1),
+            "alg_bytes": timing.alg_bytes("posv", n) * batch, "sets": cell.nsets}
+
+
+def ragged(glass, torch, count=50000, seed=2, rounds=20):
+    """The ragged POSV batch (n over {6,...,64}, 1-8 right-hand sides) solved
+    by the one-sequence ragged pipeline versus one batched POSV launch per
+    (n, nrhs) group on pre-grouped contiguous copies (the grouping itself is
+    not timed, which favours the comparator)."""
+    dev = torch.device("cuda:0")
+    case = inputs.make_ragged(count, seed=seed)
+    rg = glass.Ragged(case, device=dev)
+    A0, B0 = rg.A.clone(), rg.B.clone()
+    n, r = case["n"], case["nrhs"]
+    groups = []
+    for (gn, gr) in sorted(set(zip(n.tolist(), r.tolist()))):
+        idx = np.nonzero((n == gn) & (r == gr))[0]
+        A = np.concatenate([case["A"][case["offA"][i]:case["offA"][i] + gn * gn] for i in idx])
+        B = np.concatenate([case["B"][case["offB"][i]:case["offB"][i] + gn * gr] for i in idx])
+        At = torch.from_numpy(A.reshape(len(idx), gn, gn)).to(dev)
+        Bt = torch.from_numpy(B.reshape(len(idx), gn, gr)).to(dev)
+        groups.append({"n": gn, "r": gr, "batch": len(idx), "A": At, "B": Bt, "A0": At.clone(), "B0": Bt.clone(),
+                       "info": torch.zeros(len(idx), dtype=torch.int32, device=dev)})
+    alg = int(sum(timing.alg_bytes("posv", int(a), int(b)) for a, b in zip(n, r)))
+
+    def run_ragged():
+        rg.solve()
+
+    def run_groups():
+        for g in groups:
+            st = glass.glass_posv_batched(g["n"], g["r"], g["batch"], g["A"], g["B"], g["info"], None)
+            if st != 0:
+                raise RuntimeError(f"posv n={g['n']} nrhs={g['r']}: {glass.status_string(st)}")
+
+    def restore():
+        rg.A.copy_(A0)
+        rg.B.copy_(B0)
+        for g in groups:
+            g["A"].copy_(g["A0"])
+            g["B"].copy_(g["B0"])
+
+    run_ragged()
+    run_groups()
+    torch.cuda.synchronize()
+    restore()
+    graphs = {}
+    for name, fn in (("ragged", run_ragged), ("per_group", run_groups)):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        graphs[name] = g
+    torch.cuda.synchronize()
+    samples = {k: [] for k in graphs}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for it in range(3 + rounds):
+        for name in (("ragged", "per_group") if it % 2 == 0 else ("per_group", "ragged")):
+            restore()
+            e0.record()
+            graphs[name].replay()
+            e1.record()
+            e1.synchronize()
+            if it >= 3:
+                samples[name].append(e0.elapsed_time(e1) * 1e3)
+    restore()
+    torch.cuda.synchronize()
+    tr, tg = _median_us(samples["ragged"]), _median_us(samples["per_group"])
+    return {"workload": f"ragged posv: {count} systems, n uniform over {sorted(set(n.tolist()))}, nrhs 1-8",
+            "ragged_us": round(tr, 2), "per_group_us": round(tg, 2), "groups": len(groups),
+            "ragged_speedup": round(tg / tr, 3), "alg_bytes": alg,
+            "ragged_gbps": round(alg / (tr * 1e-6) / 1e9, 1), "ragged_solves_per_s": round(count / (tr * 1e-6), 1)}
+
+
+def adjoint(glass, torch, n=12, batch=16384, nrhs=1, rounds=20):
+    """Backward of the batched Cholesky solve at n=12, 16,384 systems:
+    microseconds per adjoint launch over rotating buffer sets >= 1 GiB."""
+    dev = torch.device("cuda:0")
+    gen = inputs.torch_generator(dev, 3)
+    L = inputs.lower_factor_torch(gen, batch, n, dev)
+    X = inputs.uniform_torch(gen, (batch, n, nrhs), dev)
+    G = inputs.uniform_torch(gen, (batch, n, nrhs), dev)
+    per_set = 4 * (L.numel() + 3 * X.numel() + L.numel())
+    sets = max(2, min(64, -(-timing.GIB // per_set)))
+    bufs = [{"L": L.clone(), "X": X.clone(), "G": G.clone(), "dB": torch.empty_like(X), "dA": torch.empty_like(L)}
+            for _ in range(sets)]
+    table = glass.glass_query_placement(glass.OP_POSV_ADJOINT, n, batch)
+
+    def launch(b):
+        st = glass.glass_posv_adjoint_batched(n, nrhs, batch, b["L"], b["X"], b["G"], b["dB"], b["dA"], None)
+        if st != 0:
+            raise RuntimeError(f"adjoint: {glass.status_string(st)}")
+
+    launch(bufs[0])
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for b in bufs:
+            launch(b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    samples = []
+    for it in range(3 + rounds):
+        e0.record()
+        g.replay()
+        e1.record()
+        e1.synchronize()
+        if it >= 3:
+            samples.append(e0.elapsed_time(e1) * 1e3 / sets)
+    us = _median_us(samples)
+    alg = 4 * (n * (n + 1) // 2 + 3 * n * nrhs + n * n) * batch
+    return {"workload": f"posv adjoint n={n} nrhs={nrhs} batch={batch}",
+            "placement": f"{glass.SCOPE_NAMES[table.scope]}/P={table.pack}", "us": round(us, 3),
+            "alg_bytes": alg, "gbps": round(alg / (us * 1e-6) / 1e9, 1), "sets": sets}

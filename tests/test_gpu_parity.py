@@ -91,7 +91,8 @@ def test_parity_se3(env, op, scope):
 
 
 @pytest.mark.parametrize("scope", ["wave", "workgroup", "thread"])
-@pytest.mark.parametrize("op,nrhs", [("posv", 3), ("posv", 8), ("potrs", 5), ("potrs", 64), ("posv", 64)])
+@pytest.mark.parametrize("op,nrhs", [("posv", 2), ("posv", 3), ("posv", 4), ("posv", 8), ("posv", 9), ("posv", 12),
+                                     ("potrs", 5), ("potrs", 12), ("potrs", 64), ("posv", 64)])
 def test_parity_multi_rhs(env, op, nrhs, scope):
     glass, torch = env
     fails = []
