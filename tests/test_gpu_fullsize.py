@@ -1,0 +1,73 @@
+"""GPU parity at the benchmark's full sizes and launch configuration: every
+cell of the placement-sweep grid at batch 4096 and 65536 (plus SE(3)), called
+exactly as the benchmark calls it (built-in table placement, inputs drawn on
+the device by the same recipes), checked against the FP64 oracle on sampled
+problems; the structural outputs (info, the +0 strict upper triangle of L,
+SE(3) row 3) are checked bit-exactly over the whole batch."""
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import TOL, normwise
+from paper_2609_28179_amd import timing
+
+pytestmark = pytest.mark.gpu
+
+SAMPLES = 192
+CELLS = [c for c in timing.sweep_cells() if c[2] >= 4096]
+
+
+def sample_index(batch, seed):
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(batch, size=min(batch, SAMPLES - 3), replace=False)
+    return np.unique(np.concatenate([[0, batch // 2, batch - 1], idx]))
+
+
+@pytest.mark.parametrize("op,n,batch", CELLS, ids=[f"{o}-{n}-{b}" for o, n, b in CELLS])
+def test_fullsize_table_placement(op, n, batch):
+    import torch
+    from paper_2609_28179_amd import glass
+    dev = torch.device("cuda:0")
+    pl = glass.glass_query_placement(glass.OPS[op], n, batch)
+    print(f"{op} n={n} batch={batch} table {glass.SCOPE_NAMES[pl.scope]}/P={pl.pack}", flush=True)
+    bufs = timing.make_set(torch, op, n, batch, dev, seed=50_000 + timing.sweep_cells().index((op, n, batch)))
+    before = {k: v.clone() for k, v in bufs.items() if k in timing.DESTRUCTIVE.get(op, ())}
+    if "info" in bufs:
+        bufs["info"].fill_(-7)
+    assert timing.launch(glass, op, n, batch, bufs, None) == 0
+    torch.cuda.synchronize()
+    idx = sample_index(batch, zlib.crc32(f"{op}-{n}-{batch}".encode()))
+    ti = torch.from_numpy(idx).to(dev)
+    h = lambda t: t.index_select(0, ti).cpu().numpy()
+    if op == "gemm":
+        err = normwise(h(bufs["C"]), oracle.gemm(h(bufs["A"]), h(bufs["B"])))
+    elif op == "gemv":
+        err = normwise(h(bufs["y"]), oracle.gemv(h(bufs["A"]), h(bufs["x"])))
+    elif op in ("potrf", "posv"):
+        A0 = h(before["A"])
+        L = h(bufs["A"])
+        if op == "potrf":
+            L_ref, info_ref = oracle.potrf(A0)
+            err = normwise(np.tril(L), L_ref)
+        else:
+            L_ref, X_ref, info_ref = oracle.posv(A0, h(before["B"]))
+            err = np.maximum(normwise(np.tril(L), L_ref), normwise(h(bufs["B"]), X_ref))
+        assert (info_ref == 0).all()
+        assert int(bufs["info"].abs().max()) == 0, "info must be 0 for every problem"
+        up = torch.triu(bufs["A"], 1)
+        assert int(torch.count_nonzero(up)) == 0 and not bool(torch.signbit(up).any()), "strict upper must be +0"
+    elif op == "potrs":
+        err = normwise(h(bufs["B"]), oracle.potrs(h(bufs["L"]), h(before["B"])))
+    elif op == "trsv":
+        err = normwise(h(bufs["x"]), oracle.trsv(h(bufs["L"]), h(before["x"]), 0))
+    elif op == "se3_compose":
+        err = normwise(h(bufs["T"]), oracle.se3_compose(h(bufs["Ta"]), h(bufs["Tb"])))
+    else:
+        err = normwise(h(bufs["T"]), oracle.se3_inverse(h(bufs["Ta"])))
+    if op.startswith("se3"):
+        row3 = bufs["T"][:, 3, :]
+        want = torch.tensor([0.0, 0.0, 0.0, 1.0], device=dev).expand_as(row3)
+        assert torch.equal(row3, want) and not bool(torch.signbit(row3).any()), "row 3 must be exactly (0,0,0,1)"
+    assert err.max() <= TOL, f"max normwise error {err.max():.3e}"
