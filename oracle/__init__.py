@@ -58,6 +58,8 @@ def _load():
             "oracle_se3_compose": [i, p, p, p],
             "oracle_se3_inverse": [i, p, p],
             "oracle_posv_adjoint": [i, i, i, p, p, p, p, p],
+            "oracle_gemm_t": [i, i, i, i, i, i, d, p, p, d, p],
+            "oracle_riccati_gain": [i, i, i, p, p, p, p, p, p],
             "oracle_num_threads": [],
             "oracle_set_num_threads": [i],
         }
@@ -174,6 +176,30 @@ def posv_adjoint(L, X, G):
     dA = np.empty((b, n, n))
     _load().oracle_posv_adjoint(n, r, b, _ptr(L), _ptr(X), _ptr(G), _ptr(dB), _ptr(dA))
     return dB, dA
+
+
+def gemm_t(A, B, transa=0, transb=0, alpha=1.0, beta=0.0, C=None):
+    """alpha op(A) op(B) + beta C with op = transpose where the flag is set."""
+    A = _f64(A)
+    B = _f64(B)
+    b = A.shape[0]
+    m = A.shape[2] if transa else A.shape[1]
+    k = A.shape[1] if transa else A.shape[2]
+    n = B.shape[1] if transb else B.shape[2]
+    out = np.zeros((b, m, n)) if C is None else _f64(C).copy()
+    _load().oracle_gemm_t(int(transa), int(transb), m, n, k, b, float(alpha), _ptr(A), _ptr(B), float(beta),
+                          _ptr(out))
+    return out
+
+
+def riccati_gain(A, B, P, R):
+    """K = (R + B^T P B)^{-1} B^T P A per problem; returns (K, info)."""
+    A, B, P, R = _f64(A), _f64(B), _f64(P), _f64(R)
+    b, nx, nu = B.shape
+    K = np.zeros((b, nu, nx))
+    info = np.zeros(b, dtype=np.int32)
+    _load().oracle_riccati_gain(nx, nu, b, _ptr(A), _ptr(B), _ptr(P), _ptr(R), _ptr(K), _ptr(info))
+    return K, info
 
 
 def posv_ragged(n, nrhs, offA, offB, A, B):

@@ -264,3 +264,82 @@ void oracle_posv_adjoint(int n, int nrhs, int batch, const double* L, const doub
             }
     }
 }
+
+/* ------------------------------------------------------- GEMM, transposed --
+ * C = alpha op(A) op(B) + beta C with op(X) = X or X^T (BLAS convention).
+ * op(A) is m x k, op(B) is k x n; A is stored m x k (transa = 0) or k x m
+ * (transa = 1), B k x n or n x k.  beta == 0: C is not read.             */
+void oracle_gemm_t(int transa, int transb, int m, int n, int k, int batch, double alpha,
+                   const double* A, const double* B, double beta, double* C) {
+    long long bb;
+#pragma omp parallel for schedule(static)
+    for (bb = 0; bb < batch; ++bb) {
+        const double* a = A + OIDX(bb, m * k);
+        const double* b = B + OIDX(bb, k * n);
+        double* c = C + OIDX(bb, m * n);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < n; ++j) {
+                double s = 0.0;
+                for (int p = 0; p < k; ++p) {
+                    const double av = transa ? a[p * m + i] : a[i * k + p];
+                    const double bv = transb ? b[j * k + p] : b[p * n + j];
+                    s += av * bv;
+                }
+                c[i * n + j] = beta == 0.0 ? alpha * s : alpha * s + beta * c[i * n + j];
+            }
+    }
+}
+
+/* ------------------------------------------------------------- LQR gain --
+ * Sec. III-B / Sec. IV-E: the feedback gain K = (R + B^T P B)^{-1} B^T P A
+ * of one Riccati step, A nx x nx, B nx x nu, P nx x nx, R nu x nu,
+ * K nu x nx.  Written out as its definition: S = R + B^T (P B) and
+ * T = B^T (P A) by plain sums, then K = S^{-1} T by Cholesky of S (S is
+ * symmetric positive definite when R is and P is semidefinite) and
+ * forward / backward substitution for every column of T.  info is the
+ * Cholesky info of S (K unspecified where it is nonzero).                 */
+void oracle_riccati_gain(int nx, int nu, int batch, const double* A, const double* B,
+                         const double* P, const double* R, double* K, int32_t* info) {
+    long long bb;
+#pragma omp parallel for schedule(static)
+    for (bb = 0; bb < batch; ++bb) {
+        const double* a = A + OIDX(bb, nx * nx);
+        const double* b = B + OIDX(bb, nx * nu);
+        const double* p = P + OIDX(bb, nx * nx);
+        const double* r = R + OIDX(bb, nu * nu);
+        double* kk = K + OIDX(bb, nu * nx);
+        double* pb = (double*)malloc(sizeof(double) * (size_t)nx * nu);
+        double* pa = (double*)malloc(sizeof(double) * (size_t)nx * nx);
+        double* s = (double*)malloc(sizeof(double) * (size_t)nu * nu);
+        for (int i = 0; i < nx; ++i) {
+            for (int j = 0; j < nu; ++j) {
+                double t = 0.0;
+                for (int q = 0; q < nx; ++q) t += p[i * nx + q] * b[q * nu + j];
+                pb[i * nu + j] = t;
+            }
+            for (int j = 0; j < nx; ++j) {
+                double t = 0.0;
+                for (int q = 0; q < nx; ++q) t += p[i * nx + q] * a[q * nx + j];
+                pa[i * nx + j] = t;
+            }
+        }
+        for (int i = 0; i < nu; ++i) {
+            for (int j = 0; j < nu; ++j) {
+                double t = 0.0;
+                for (int q = 0; q < nx; ++q) t += b[q * nu + i] * pb[q * nu + j];
+                s[i * nu + j] = r[i * nu + j] + t;
+            }
+            for (int j = 0; j < nx; ++j) {
+                double t = 0.0;
+                for (int q = 0; q < nx; ++q) t += b[q * nu + i] * pa[q * nx + j];
+                kk[i * nx + j] = t;
+            }
+        }
+        const int inf = chol_one(nu, s);
+        if (info) info[bb] = inf;
+        if (inf == 0) chol_solve_one(nu, nx, s, kk);
+        free(pb);
+        free(pa);
+        free(s);
+    }
+}

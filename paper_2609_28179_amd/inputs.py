@@ -180,6 +180,47 @@ def se3_torch(g, batch: int, device):
     return T.to(torch.float32)
 
 
+# ------------------------------------------------------------------ LQR gain
+def riccati64(rng: np.random.Generator, batch: int, nx: int, nu: int):
+    """Float64 inputs of K = (R + B^T P B)^{-1} B^T P A, before rounding:
+    A = I + 0.1 U[-1,1] (a discretised dynamics matrix), B = 0.5 U[-1,1],
+    P = M M^T / nx + I and R = N N^T / nu + I (symmetric positive definite,
+    lower triangle mirrored), M, N iid uniform[-1, 1]."""
+    A = np.eye(nx)[None] + 0.1 * rng.uniform(-1.0, 1.0, size=(batch, nx, nx))
+    B = 0.5 * rng.uniform(-1.0, 1.0, size=(batch, nx, nu))
+    M = rng.uniform(-1.0, 1.0, size=(batch, nx, nx))
+    P = np.matmul(M, np.swapaxes(M, 1, 2)) / nx + np.eye(nx)[None]
+    N = rng.uniform(-1.0, 1.0, size=(batch, nu, nu))
+    R = np.matmul(N, np.swapaxes(N, 1, 2)) / nu + np.eye(nu)[None]
+    for S in (P, R):
+        il = np.tril_indices(S.shape[1], -1)
+        S[:, il[1], il[0]] = S[:, il[0], il[1]]
+    return A, B, P, R
+
+
+def make_riccati(batch: int, nx: int, nu: int, seed: int = 4) -> dict:
+    rng = np.random.default_rng(np.random.SeedSequence([seed, OP_IDS["riccati"], nx, nu, batch]))
+    A, B, P, R = riccati64(rng, batch, nx, nu)
+    return {"A": A.astype(np.float32), "B": B.astype(np.float32), "P": P.astype(np.float32),
+            "R": R.astype(np.float32)}
+
+
+def riccati_torch(g, batch: int, nx: int, nu: int, device):
+    """The same recipe drawn on the device (float64, rounded to float32)."""
+    torch = _torch()
+    f64 = torch.float64
+    u = lambda shape: torch.rand(shape, generator=g, device=device, dtype=f64) * 2.0 - 1.0
+    A = torch.eye(nx, dtype=f64, device=device) + 0.1 * u((batch, nx, nx))
+    B = 0.5 * u((batch, nx, nu))
+    M = u((batch, nx, nx))
+    P = torch.matmul(M, M.transpose(1, 2).contiguous()) / nx + torch.eye(nx, dtype=f64, device=device)
+    N = u((batch, nu, nu))
+    R = torch.matmul(N, N.transpose(1, 2).contiguous()) / nu + torch.eye(nu, dtype=f64, device=device)
+    P = torch.tril(P) + torch.tril(P, -1).transpose(1, 2)
+    R = torch.tril(R) + torch.tril(R, -1).transpose(1, 2)
+    return {k: v.to(torch.float32).contiguous() for k, v in (("A", A), ("B", B), ("P", P), ("R", R))}
+
+
 # ----------------------------------------------------- cost-model initial weights
 def mlp_init(d: int, seed: int, hidden: int = 64) -> np.ndarray:
     """He-normal initial weights of the d -> 64 -> 64 -> 1 cost model (std
