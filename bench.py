@@ -227,7 +227,8 @@ def main():
         t0 = time.time()
         extras = {"posv_small": workloads.posv_small(glass, torch),
                   "ragged": workloads.ragged(glass, torch),
-                  "adjoint": workloads.adjoint(glass, torch)}
+                  "adjoint": workloads.adjoint(glass, torch),
+                  "riccati_gain": workloads.riccati_gain(glass, torch)}
         log(f"workloads ({time.time() - t0:.1f} s): " + json.dumps(extras))
 
     cpu = None

@@ -98,6 +98,18 @@ glass_status_t glass_gemm_batched(int m, int n, int k, int batch, float alpha,
                                   float* C, const glass_placement_t* force,
                                   void* stream);
 
+/* C = alpha op(A) op(B) + beta C with op(X) = X (trans 0) or X^T (trans 1),
+ * the BLAS form (Sec. III-B, BLAS L3).  op(A) is m x k, op(B) is k x n, C is
+ * m x n; A is stored row-major m x k (transa = 0) or k x m (transa = 1), B
+ * k x n or n x k.  Same ranges, ownership and errors as glass_gemm_batched
+ * (which is this call with both flags 0); a flag other than 0 / 1 is
+ * GLASS_ERR_INVALID_VALUE.  Transposed operands run at wavefront or
+ * workgroup scope (a forced thread placement is GLASS_ERR_INFEASIBLE_PLACEMENT;
+ * a table entry naming thread scope falls back to wavefront scope). */
+glass_status_t glass_gemm_batched_ex(int transa, int transb, int m, int n, int k, int batch,
+                                     float alpha, const float* A, const float* B, float beta,
+                                     float* C, const glass_placement_t* force, void* stream);
+
 /* y = alpha * A x + beta * y  (Sec. III-B, BLAS L2).
  * A [batch][m][n], x [batch][n], y [batch][m]; beta == 0: y is not read.
  * y must not overlap A or x.  Thread scope requires m == n <= 16. */
@@ -204,6 +216,28 @@ glass_status_t glass_posv_ragged(int count, const int32_t* n, const int32_t* nrh
  * count < 0), and the byte offset of the permutation inside it. */
 size_t glass_posv_ragged_workspace_size(int count);
 size_t glass_posv_ragged_perm_offset(int count);
+
+/* Fused LQR feedback gain K = (R + B^T P B)^{-1} B^T P A, one Riccati step
+ * (Sec. III-B: a fused composition of GEMM and solve primitives; Sec. IV-E
+ * measures it against the chain of separate launches).  Per problem, all
+ * row-major and batch-contiguous: A [nx][nx], B [nx][nu], P [nx][nx]
+ * (symmetric, read whole), R [nu][nu] (symmetric positive definite, read
+ * whole), K [nu][nx] out; info [batch] (int32, may be NULL) receives the
+ * Cholesky info of S = R + B^T P B (0, or the 1-based failing pivot; K is
+ * unspecified and not written where it is nonzero).  Device pointers owned
+ * by the caller; inputs are not modified.  Sizes: 1 <= nu <= 16,
+ * 1 <= nx <= 56, nx + nu <= 64 and nx <= 48 when nu > 8, else
+ * GLASS_ERR_UNSUPPORTED.  Wavefront scope only (one problem per 64-lane
+ * wavefront, every intermediate in VGPRs / LDS); force->pack sets the
+ * problems per workgroup, another scope is GLASS_ERR_INFEASIBLE_PLACEMENT. */
+glass_status_t glass_riccati_gain_batched(int nx, int nu, int batch, const float* A,
+                                          const float* B, const float* P, const float* R,
+                                          float* K, int32_t* info,
+                                          const glass_placement_t* force, void* stream);
+
+/* 1 if the fused LQR gain can run nx, nu with `pack` problems per workgroup
+ * within the LDS budget, 0 if not, or a negative status for bad arguments. */
+int glass_riccati_feasible(int nx, int nu, int pack);
 
 /* Diagnostics of GLASS_ERR_LAUNCH: the HIP runtime error code of the most
  * recent failed launch made by this library on the calling thread (0 if none;

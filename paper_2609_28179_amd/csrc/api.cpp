@@ -72,6 +72,8 @@ glass_status_t resolve(const Shape& s, long long batch, const glass_placement_t*
 
 thread_local int t_last_launch_error = 0;
 
+constexpr int kRiccatiDefaultPack = 1;  // problems (wavefronts) per workgroup of the fused LQR gain
+
 inline glass_status_t launched(int err) {
     if (err == 0) return GLASS_OK;
     t_last_launch_error = err;
@@ -87,12 +89,19 @@ extern "C" {
 
 glass_status_t glass_gemm_batched(int m, int n, int k, int batch, float alpha, const float* A, const float* B,
                                   float beta, float* C, const glass_placement_t* force, void* stream) {
+    return glass_gemm_batched_ex(0, 0, m, n, k, batch, alpha, A, B, beta, C, force, stream);
+}
+
+glass_status_t glass_gemm_batched_ex(int transa, int transb, int m, int n, int k, int batch, float alpha,
+                                     const float* A, const float* B, float beta, float* C,
+                                     const glass_placement_t* force, void* stream) {
     if (!valid_force(force)) return GLASS_ERR_INVALID_VALUE;
+    if ((transa != 0 && transa != 1) || (transb != 0 && transb != 1)) return GLASS_ERR_INVALID_VALUE;
     if (!size_ok(m) || !size_ok(n) || !size_ok(k)) return GLASS_ERR_UNSUPPORTED;
     if (batch < 0) return GLASS_ERR_INVALID_VALUE;
     if (batch == 0) return GLASS_OK;
     if (!A || !B || !C) return GLASS_ERR_INVALID_VALUE;
-    Shape s{GLASS_OP_GEMM, m, n, k, 1, 0};
+    Shape s{GLASS_OP_GEMM, m, n, k, 1, transa | (transb << 1)};
     Geometry g;
     glass_status_t st = resolve(s, batch, force, &g);
     if (st != GLASS_OK) return st;
@@ -226,6 +235,32 @@ glass_status_t glass_posv_ragged(int count, const int32_t* n, const int32_t* nrh
     if (workspace_bytes < ragged_workspace_bytes(count) || (reinterpret_cast<uintptr_t>(workspace) & 3))
         return GLASS_ERR_INVALID_VALUE;
     return launched(launch_posv_ragged(count, n, nrhs, offA, offB, A, B, info, workspace, sc, stream));
+}
+
+glass_status_t glass_riccati_gain_batched(int nx, int nu, int batch, const float* A, const float* B, const float* P,
+                                          const float* R, float* K, int32_t* info, const glass_placement_t* force,
+                                          void* stream) {
+    if (!valid_force(force)) return GLASS_ERR_INVALID_VALUE;
+    if (!riccati_size_ok(nx, nu)) return GLASS_ERR_UNSUPPORTED;
+    if (batch < 0) return GLASS_ERR_INVALID_VALUE;
+    if (batch == 0) return GLASS_OK;
+    if (!A || !B || !P || !R || !K) return GLASS_ERR_INVALID_VALUE;
+    int pack = kRiccatiDefaultPack;
+    if (force) {
+        if (force->scope != GLASS_SCOPE_WAVE) return GLASS_ERR_INFEASIBLE_PLACEMENT;
+        pack = force->pack;
+    }
+    if (riccati_region_floats(nx, nu) * sizeof(float) * pack > kLdsBudgetBytes) {
+        if (force) return GLASS_ERR_INFEASIBLE_PLACEMENT;
+        pack = 1;
+    }
+    return launched(launch_riccati(nx, nu, batch, pack, A, B, P, R, K, info, stream));
+}
+
+int glass_riccati_feasible(int nx, int nu, int pack) {
+    if (!riccati_size_ok(nx, nu)) return GLASS_ERR_UNSUPPORTED;
+    if (pack != 1 && pack != 2 && pack != 4 && pack != 8) return GLASS_ERR_INVALID_VALUE;
+    return riccati_region_floats(nx, nu) * sizeof(float) * pack <= kLdsBudgetBytes ? 1 : 0;
 }
 
 int glass_last_launch_error(void) { return t_last_launch_error; }

@@ -76,25 +76,35 @@ __global__ void __launch_bounds__(512) gemm_thread(int batch, float alpha, const
 }
 
 // ------------------------------------------------- small n, wave / wg scope --
+// TA / TBT: op(A) = A^T (A stored k x m) / op(B) = B^T (B stored n x k).
+// Operands are staged as stored (rows padded to an odd stride).
+template <bool TA, bool TBT>
 GLASS_DEV void gemm_small_problem(int m, int n, int k, float alpha, const float* __restrict__ Ag,
                                   const float* __restrict__ Bg, float beta, float* __restrict__ Cg, float* As,
                                   int tid, int nt, bool wave) {
-    const int sk = k | 1, sn = n | 1;
-    float* Bs = As + ((m * sk + 3) & ~3);
-    stage_in<2>(As, Ag, m * k, make_fastdiv(k), sk, tid, nt);
-    stage_in<2>(Bs, Bg, k * n, make_fastdiv(n), sn, tid, nt);
+    const int arows = TA ? k : m, acols = TA ? m : k;
+    const int brows = TBT ? n : k, bcols = TBT ? k : n;
+    const int sa = acols | 1, sb = bcols | 1;
+    float* Bs = As + ((arows * sa + 3) & ~3);
+    stage_in<2>(As, Ag, arows * acols, make_fastdiv(acols), sa, tid, nt);
+    stage_in<2>(Bs, Bg, brows * bcols, make_fastdiv(bcols), sb, tid, nt);
     if (wave) wave_sync(); else __syncthreads();
     const FastDiv fn = make_fastdiv(n);
     for (int e = tid; e < m * n; e += nt) {
         const int i = (int)fdiv((uint32_t)e, fn), j = e - i * n;
         float c = 0.f;
-        for (int p = 0; p < k; ++p) c = fmaf(As[i * sk + p], Bs[p * sn + j], c);
+        for (int p = 0; p < k; ++p) {
+            const float av = TA ? As[p * sa + i] : As[i * sa + p];
+            const float bv = TBT ? Bs[j * sb + p] : Bs[p * sb + j];
+            c = fmaf(av, bv, c);
+        }
         float out = alpha * c;
         if (beta != 0.f) out = fmaf(beta, Cg[e], out);
         Cg[e] = out;
     }
 }
 
+template <bool TA, bool TBT>
 __global__ void __launch_bounds__(512) gemm_small_wave(int m, int n, int k, int batch, float alpha,
                                                        const float* __restrict__ A, const float* __restrict__ B,
                                                        float beta, float* __restrict__ C, int region) {
@@ -102,10 +112,11 @@ __global__ void __launch_bounds__(512) gemm_small_wave(int m, int n, int k, int 
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
-    gemm_small_problem(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lds + (size_t)w * region,
+    gemm_small_problem<TA, TBT>(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lds + (size_t)w * region,
                        lane, 64, true);
 }
 
+template <bool TA, bool TBT>
 __global__ void __launch_bounds__(256) gemm_small_wg(int m, int n, int k, int batch, int pack, float alpha,
                                                      const float* __restrict__ A, const float* __restrict__ B,
                                                      float beta, float* __restrict__ C) {
@@ -113,7 +124,7 @@ __global__ void __launch_bounds__(256) gemm_small_wg(int m, int n, int k, int ba
     for (int q = 0; q < pack; ++q) {
         const long long p = (long long)blockIdx.x * pack + q;
         if (p >= batch) break;
-        gemm_small_problem(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lds, threadIdx.x,
+        gemm_small_problem<TA, TBT>(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lds, threadIdx.x,
                            blockDim.x, false);
         __syncthreads();
     }
@@ -126,7 +137,10 @@ __global__ void __launch_bounds__(256) gemm_small_wg(int m, int n, int k, int ba
 // all of a problem's loads are in flight together.  JJ bounds the number of
 // column tiles one wave owns (TB at wave scope, 1 at workgroup scope where
 // the T(n)/64 waves split the ceil(n/16) <= T(n)/64 column tiles).
-template <int TB, bool VEC, int JJ>
+// TA / TBT select transposed operands (A stored k x m, B stored n x k); the
+// transposed A fragment is read element-wise (consecutive lanes take
+// consecutive rows i, so the loads stay coalesced).
+template <int TB, bool VEC, int JJ, bool TA = false, bool TBT = false>
 GLASS_DEV void mfma_problem(int m, int n, int k, float alpha, const float* __restrict__ Ag,
                             const float* __restrict__ Bg, float beta, float* __restrict__ Cg, int lane, int jt0,
                             int jstep) {
@@ -140,7 +154,10 @@ GLASS_DEV void mfma_problem(int m, int n, int k, float alpha, const float* __res
         for (int kb = 0; kb < TB; ++kb) {
             const int k0 = kb * 16 + 4 * q;
             const bool in = it < MT && kb < KT && i < m;
-            if (VEC) {
+            if (TA) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) af[it][kb][c] = (in && k0 + c < k) ? Ag[(k0 + c) * m + i] : 0.f;
+            } else if (VEC) {
                 floatx4 v = {0.f, 0.f, 0.f, 0.f};
                 if (in && k0 < k) v = *reinterpret_cast<const floatx4*>(Ag + i * k + k0);
 #pragma unroll
@@ -160,7 +177,7 @@ GLASS_DEV void mfma_problem(int m, int n, int k, float alpha, const float* __res
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int kk = kb * 16 + 4 * q + c;
-                bf[jj][kb][c] = (kb < KT && kk < k && j < n) ? Bg[kk * n + j] : 0.f;
+                bf[jj][kb][c] = (kb < KT && kk < k && j < n) ? (TBT ? Bg[j * k + kk] : Bg[kk * n + j]) : 0.f;
             }
     }
 #pragma unroll
@@ -197,17 +214,18 @@ GLASS_DEV void mfma_problem(int m, int n, int k, float alpha, const float* __res
     }
 }
 
-template <int TB, bool VEC>
+template <int TB, bool VEC, bool TA = false, bool TBT = false>
 __global__ void __launch_bounds__(512) gemm_mfma_wave(int m, int n, int k, int batch, float alpha,
                                                       const float* __restrict__ A, const float* __restrict__ B,
                                                       float beta, float* __restrict__ C) {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
-    mfma_problem<TB, VEC, TB>(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lane, 0, 1);
+    mfma_problem<TB, VEC, TB, TA, TBT>(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lane, 0,
+                                       1);
 }
 
-template <int TB, bool VEC>
+template <int TB, bool VEC, bool TA = false, bool TBT = false>
 __global__ void __launch_bounds__(256) gemm_mfma_wg(int m, int n, int k, int batch, int pack, float alpha,
                                                     const float* __restrict__ A, const float* __restrict__ B,
                                                     float beta, float* __restrict__ C) {
@@ -215,52 +233,41 @@ __global__ void __launch_bounds__(256) gemm_mfma_wg(int m, int n, int k, int bat
     for (int q = 0; q < pack; ++q) {
         const long long p = (long long)blockIdx.x * pack + q;
         if (p >= batch) break;
-        mfma_problem<TB, VEC, 1>(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lane, w, nw);
+        mfma_problem<TB, VEC, 1, TA, TBT>(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lane,
+                                          w, nw);
     }
 }
 
 #define GLASS_CASES_1_12(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
 
-}  // namespace
-
-int launch_gemm(const Shape& sh, const Geometry& g, int batch, float alpha, const float* A, const float* B,
-                float beta, float* C, void* stream) {
-    (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
-    hipStream_t st = (hipStream_t)stream;
+// Launch one GEMM kernel: TA / TBT are the transpose flags of the shape.
+template <bool TA, bool TBT>
+int launch_gemm_t(const Shape& sh, const Geometry& g, int batch, float alpha, const float* A, const float* B,
+                  float beta, float* C, hipStream_t st) {
     const int m = sh.m, n = sh.n, k = sh.k;
     dim3 grid((unsigned)g.grid), block(g.threads);
-    if (g.scope == GLASS_SCOPE_THREAD) {
-        switch (n) {
-#define X(N) \
-    case N: hipLaunchKernelGGL(gemm_thread<N>, grid, block, g.lds_bytes, st, batch, alpha, A, B, beta, C); break;
-            GLASS_CASES_1_12(X)
-#undef X
-        default: return (int)hipErrorInvalidValue;
-        }
-        return (int)hipGetLastError();
-    }
     if (!gemm_uses_mfma(sh)) {
         if (g.scope == GLASS_SCOPE_WAVE)
-            hipLaunchKernelGGL(gemm_small_wave, grid, block, g.lds_bytes, st, m, n, k, batch, alpha, A, B, beta, C,
-                               (int)region_floats(sh));
+            hipLaunchKernelGGL((gemm_small_wave<TA, TBT>), grid, block, g.lds_bytes, st, m, n, k, batch, alpha, A, B,
+                               beta, C, (int)region_floats(sh));
         else
-            hipLaunchKernelGGL(gemm_small_wg, grid, block, g.lds_bytes, st, m, n, k, batch, g.pack, alpha, A, B,
-                               beta, C);
+            hipLaunchKernelGGL((gemm_small_wg<TA, TBT>), grid, block, g.lds_bytes, st, m, n, k, batch, g.pack,
+                               alpha, A, B, beta, C);
         return (int)hipGetLastError();
     }
     int mx = m > n ? m : n;
     mx = mx > k ? mx : k;
     const int tb = (mx + 15) / 16;
-    const bool vec = (k % 4 == 0) && ((uintptr_t)A % 16 == 0);
+    const bool vec = !TA && (k % 4 == 0) && ((uintptr_t)A % 16 == 0);
     if (g.scope == GLASS_SCOPE_WAVE) {
-#define X(TB)                                                                                              \
-    case TB:                                                                                               \
-        if (vec)                                                                                           \
-            hipLaunchKernelGGL((gemm_mfma_wave<TB, true>), grid, block, 0, st, m, n, k, batch, alpha, A, B, \
-                               beta, C);                                                                   \
-        else                                                                                               \
-            hipLaunchKernelGGL((gemm_mfma_wave<TB, false>), grid, block, 0, st, m, n, k, batch, alpha, A,  \
-                               B, beta, C);                                                                \
+#define X(TB)                                                                                                  \
+    case TB:                                                                                                   \
+        if (vec)                                                                                               \
+            hipLaunchKernelGGL((gemm_mfma_wave<TB, true, TA, TBT>), grid, block, 0, st, m, n, k, batch, alpha, \
+                               A, B, beta, C);                                                                 \
+        else                                                                                                   \
+            hipLaunchKernelGGL((gemm_mfma_wave<TB, false, TA, TBT>), grid, block, 0, st, m, n, k, batch,       \
+                               alpha, A, B, beta, C);                                                          \
         break;
         switch (tb) {
             X(1) X(2) X(3) X(4)
@@ -268,14 +275,14 @@ int launch_gemm(const Shape& sh, const Geometry& g, int batch, float alpha, cons
         }
 #undef X
     } else {
-#define X(TB)                                                                                                 \
-    case TB:                                                                                                  \
-        if (vec)                                                                                              \
-            hipLaunchKernelGGL((gemm_mfma_wg<TB, true>), grid, block, 0, st, m, n, k, batch, g.pack, alpha, A, \
-                               B, beta, C);                                                                   \
-        else                                                                                                  \
-            hipLaunchKernelGGL((gemm_mfma_wg<TB, false>), grid, block, 0, st, m, n, k, batch, g.pack, alpha,  \
-                               A, B, beta, C);                                                                \
+#define X(TB)                                                                                                  \
+    case TB:                                                                                                   \
+        if (vec)                                                                                               \
+            hipLaunchKernelGGL((gemm_mfma_wg<TB, true, TA, TBT>), grid, block, 0, st, m, n, k, batch, g.pack,  \
+                               alpha, A, B, beta, C);                                                          \
+        else                                                                                                   \
+            hipLaunchKernelGGL((gemm_mfma_wg<TB, false, TA, TBT>), grid, block, 0, st, m, n, k, batch, g.pack, \
+                               alpha, A, B, beta, C);                                                          \
         break;
         switch (tb) {
             X(1) X(2) X(3) X(4)
@@ -284,6 +291,31 @@ int launch_gemm(const Shape& sh, const Geometry& g, int batch, float alpha, cons
 #undef X
     }
     return (int)hipGetLastError();
+}
+
+}  // namespace
+
+int launch_gemm(const Shape& sh, const Geometry& g, int batch, float alpha, const float* A, const float* B,
+                float beta, float* C, void* stream) {
+    (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
+    hipStream_t st = (hipStream_t)stream;
+    if (g.scope == GLASS_SCOPE_THREAD) {  // square, no transposes (make_geometry)
+        dim3 grid((unsigned)g.grid), block(g.threads);
+        switch (sh.n) {
+#define X(N) \
+    case N: hipLaunchKernelGGL(gemm_thread<N>, grid, block, g.lds_bytes, st, batch, alpha, A, B, beta, C); break;
+            GLASS_CASES_1_12(X)
+#undef X
+        default: return (int)hipErrorInvalidValue;
+        }
+        return (int)hipGetLastError();
+    }
+    switch (sh.trans & 3) {
+    case 0: return launch_gemm_t<false, false>(sh, g, batch, alpha, A, B, beta, C, st);
+    case 1: return launch_gemm_t<true, false>(sh, g, batch, alpha, A, B, beta, C, st);
+    case 2: return launch_gemm_t<false, true>(sh, g, batch, alpha, A, B, beta, C, st);
+    default: return launch_gemm_t<true, true>(sh, g, batch, alpha, A, B, beta, C, st);
+    }
 }
 
 }  // namespace glass

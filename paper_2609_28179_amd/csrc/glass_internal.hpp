@@ -42,7 +42,7 @@ struct Shape {
     glass_op_t op;
     int m, n, k;     // GEMM: C m x n, inner k. GEMV: A m x n. square ops: m=n=k=order
     int nrhs;        // POTRS / POSV
-    int trans;       // TRSV
+    int trans;       // TRSV: 0 / 1.  GEMM: bit 0 op(A) = A^T, bit 1 op(B) = B^T
 };
 
 struct Geometry {
@@ -72,9 +72,13 @@ inline size_t region_floats(const Shape& s) {
         return (size_t)round4(n * odd_up(n)) + (size_t)round4(n * odd_up(s.nrhs)) + kWave;
     case GLASS_OP_GEMV:
         return (size_t)round4(s.m * odd_up(n)) + (size_t)round4(n) + 4 * kWave;  // + partial sums
-    case GLASS_OP_GEMM:
+    case GLASS_OP_GEMM: {
         if (gemm_uses_mfma(s)) return 0;
-        return (size_t)round4(s.m * odd_up(s.k)) + (size_t)round4(s.k * odd_up(s.n));
+        // A staged as stored: m x k, or k x m when transposed; B likewise
+        const size_t a = (s.trans & 1) ? (size_t)round4(s.k * odd_up(s.m)) : (size_t)round4(s.m * odd_up(s.k));
+        const size_t b = (s.trans & 2) ? (size_t)round4(s.n * odd_up(s.k)) : (size_t)round4(s.k * odd_up(s.n));
+        return a + b;
+    }
     default:
         return 0;
     }
@@ -140,7 +144,7 @@ inline bool make_geometry(const Shape& s, int scope, int pack, long long batch, 
     if (scope == GLASS_SCOPE_THREAD) {
         if (!se3) {
             if (s.op == GLASS_OP_GEMM) {
-                if (!(s.m == s.n && s.n == s.k) || s.n > kThreadGemmMaxN) return false;
+                if (!(s.m == s.n && s.n == s.k) || s.n > kThreadGemmMaxN || s.trans != 0) return false;
             } else if (s.op == GLASS_OP_GEMV) {
                 if (s.m != s.n || s.n > kThreadMaxN) return false;
             } else if (s.n > kThreadMaxN) {
@@ -196,6 +200,14 @@ size_t ragged_workspace_bytes(int count);
 int launch_posv_ragged(int count, const int32_t* n, const int32_t* nrhs, const int64_t* offA, const int64_t* offB,
                        float* A, float* B, int32_t* info, void* workspace, const RaggedScopes& scopes,
                        void* stream);
+// Fused LQR gain (wave scope only): 1 <= nu <= 16, 1 <= nx <= 56, nx + nu <= 64,
+// nx <= 48 when nu > 8.  LDS floats of one wavefront.
+inline bool riccati_size_ok(int nx, int nu) {
+    return nx >= 1 && nu >= 1 && nu <= 16 && nx <= 56 && nx + nu <= 64 && (nu <= 8 || nx <= 48);
+}
+size_t riccati_region_floats(int nx, int nu);
+int launch_riccati(int nx, int nu, int batch, int pack, const float* A, const float* B, const float* P,
+                   const float* R, float* K, int32_t* info, void* stream);
 const char* hip_error_name(int code);
 size_t mlp_num_params(int d);
 size_t mlp_backward_workspace_bytes(int N, int d);

@@ -59,6 +59,7 @@ _i, _f, _p = ctypes.c_int, ctypes.c_float, ctypes.c_void_p
 _PP = ctypes.POINTER(Placement)
 _SIGS = {
     "glass_gemm_batched": [_i, _i, _i, _i, _f, _p, _p, _f, _p, _PP, _p],
+    "glass_gemm_batched_ex": [_i, _i, _i, _i, _i, _i, _f, _p, _p, _f, _p, _PP, _p],
     "glass_gemv_batched": [_i, _i, _i, _f, _p, _p, _f, _p, _PP, _p],
     "glass_potrf_batched": [_i, _i, _p, _p, _PP, _p],
     "glass_potrs_batched": [_i, _i, _i, _p, _p, _PP, _p],
@@ -69,6 +70,8 @@ _SIGS = {
     "glass_posv_ragged": [_i, _p, _p, _p, _p, _p, _p, _p, _p, ctypes.c_size_t, _p, _p],
     "glass_posv_ragged_workspace_size": [_i],
     "glass_posv_ragged_perm_offset": [_i],
+    "glass_riccati_gain_batched": [_i, _i, _i, _p, _p, _p, _p, _p, _p, _PP, _p],
+    "glass_riccati_feasible": [_i, _i, _i],
     "glass_last_launch_error": [],
     "glass_hip_error_name": [_i],
     "glass_mlp_num_params": [_i],
@@ -128,6 +131,11 @@ def glass_gemm_batched(m, n, k, batch, alpha, A, B, beta, C, force=None, stream=
                                    _stream(stream))
 
 
+def glass_gemm_batched_ex(transa, transb, m, n, k, batch, alpha, A, B, beta, C, force=None, stream=None) -> int:
+    return _lib.glass_gemm_batched_ex(transa, transb, m, n, k, batch, alpha, _ptr(A), _ptr(B), beta, _ptr(C),
+                                      _force(force), _stream(stream))
+
+
 def glass_gemv_batched(m, n, batch, alpha, A, x, beta, y, force=None, stream=None) -> int:
     return _lib.glass_gemv_batched(m, n, batch, alpha, _ptr(A), _ptr(x), beta, _ptr(y), _force(force),
                                    _stream(stream))
@@ -174,6 +182,15 @@ def glass_posv_ragged_workspace_size(count) -> int:
 
 def glass_posv_ragged_perm_offset(count) -> int:
     return _lib.glass_posv_ragged_perm_offset(count)
+
+
+def glass_riccati_gain_batched(nx, nu, batch, A, B, P, R, K, info=None, force=None, stream=None) -> int:
+    return _lib.glass_riccati_gain_batched(nx, nu, batch, _ptr(A), _ptr(B), _ptr(P), _ptr(R), _ptr(K), _ptr(info),
+                                           _force(force), _stream(stream))
+
+
+def glass_riccati_feasible(nx, nu, pack) -> int:
+    return _lib.glass_riccati_feasible(nx, nu, pack)
 
 
 def glass_last_launch_error() -> int:

@@ -69,6 +69,31 @@ def test_validation_paths(glass):
         assert g.status_string(s).startswith("GLASS_")
 
 
+def test_riccati_and_gemm_ex_validation_paths(glass):
+    g = glass
+    S = 0
+    assert g.glass_gemm_batched_ex(2, 0, 4, 4, 4, 3, 1.0, FAKE, FAKE, 0.0, FAKE, stream=S) == g.ERR_INVALID_VALUE
+    assert g.glass_gemm_batched_ex(0, -1, 4, 4, 4, 3, 1.0, FAKE, FAKE, 0.0, FAKE, stream=S) == g.ERR_INVALID_VALUE
+    assert g.glass_gemm_batched_ex(1, 0, 4, 65, 4, 3, 1.0, FAKE, FAKE, 0.0, FAKE, stream=S) == g.ERR_UNSUPPORTED
+    assert g.glass_gemm_batched_ex(1, 0, 4, 4, 4, 3, 1.0, FAKE, FAKE, 0.0, FAKE, force=("thread", 1), stream=S) \
+        == g.ERR_INFEASIBLE_PLACEMENT
+    assert g.glass_gemm_batched_ex(1, 1, 4, 4, 4, 0, 1.0, None, None, 0.0, None, stream=S) == g.OK
+    for nx, nu in ((0, 1), (1, 0), (57, 1), (8, 17), (49, 9), (50, 15)):
+        assert g.glass_riccati_gain_batched(nx, nu, 3, FAKE, FAKE, FAKE, FAKE, FAKE, stream=S) == g.ERR_UNSUPPORTED
+        assert g.glass_riccati_feasible(nx, nu, 1) == g.ERR_UNSUPPORTED
+    assert g.glass_riccati_gain_batched(12, 4, -1, FAKE, FAKE, FAKE, FAKE, FAKE, stream=S) == g.ERR_INVALID_VALUE
+    assert g.glass_riccati_gain_batched(12, 4, 0, None, None, None, None, None, stream=S) == g.OK
+    assert g.glass_riccati_gain_batched(12, 4, 3, FAKE, FAKE, None, FAKE, FAKE, stream=S) == g.ERR_INVALID_VALUE
+    assert g.glass_riccati_gain_batched(12, 4, 3, FAKE, FAKE, FAKE, FAKE, FAKE, force=("workgroup", 1),
+                                        stream=S) == g.ERR_INFEASIBLE_PLACEMENT
+    assert g.glass_riccati_feasible(12, 4, 3) == g.ERR_INVALID_VALUE
+    assert g.glass_riccati_feasible(12, 4, 8) == 1
+    # (48, 16): 3344 floats a wavefront, so four fit the 64 KiB budget and eight do not
+    assert g.glass_riccati_feasible(48, 16, 4) == 1 and g.glass_riccati_feasible(48, 16, 8) == 0
+    assert g.glass_riccati_gain_batched(48, 16, 3, FAKE, FAKE, FAKE, FAKE, FAKE, force=("wave", 8), stream=S) \
+        == g.ERR_INFEASIBLE_PLACEMENT
+
+
 def test_mlp_validation_paths(glass):
     g = glass
     S = 0
