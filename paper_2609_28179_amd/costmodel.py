@@ -16,9 +16,11 @@ glass_mlp_adam.  Features (d = 14): one-hot op over the eight table ops, ln n
 pack; each column standardised with the training set's mean and standard
 deviation (columns with zero spread are left centred).  Target: ln of the
 median microseconds per launch.  Loss: mean squared error over the whole
-training set every step (full batch); Adam with lr 1e-3, beta (0.9, 0.999),
+training set every step (full batch); Adam with lr 3e-3 (picked by
+leave-one-order-out cross-validation on the sweep), beta (0.9, 0.999),
 eps 1e-8; He-normal initial weights from a fixed seed.
 
+  python -m paper_2609_28179_amd.costmodel cv       [--sweep FILE] [--configs STEPS:LR,...]
   python -m paper_2609_28179_amd.costmodel train    [--sweep FILE] [--out PREFIX]
   python -m paper_2609_28179_amd.costmodel evaluate [--heldout FILE] [--model PREFIX] [--out JSON]
 """
@@ -46,7 +48,7 @@ D = 14
 HIDDEN = 64
 TOP_K = 3
 STEPS = 5000
-LR = 1e-3
+LR = 3e-3   # chosen by leave-one-order-out cross-validation on the training sweep
 SEED = 0
 
 
@@ -235,6 +237,53 @@ def evaluate(model_ranks: dict, table_picks: dict, heldout_recs, k=TOP_K):
     return rows, summary
 
 
+def cross_validate(recs, configs, log=print):
+    """Leave-one-order-out cross-validation on the training sweep only: for
+    every tabulated n, train on the other orders and score the held-back
+    cells by the best measured time among the model's top-k placements over
+    the measured best.  Returns {(steps, lr): (frac within 10 %, geomean, max)}."""
+    orders = sorted({r["n"] for r in recs if not r["op"].startswith("se3")})
+    out = {}
+    for steps, lr in configs:
+        ratios = []
+        for hold in orders:
+            train_recs = [r for r in recs if r["n"] != hold or r["op"].startswith("se3")]
+            model = CostModel.train(train_recs, steps=steps, lr=lr, log=None)
+            cells = {}
+            for r in recs:
+                if r["n"] == hold and not r["op"].startswith("se3"):
+                    cells.setdefault((r["op"], r["n"], r["batch"]), {})[(r["scope"], r["pack"])] = r["median_us"]
+            rows = [(c, pl) for c, meds in cells.items() for pl in meds]
+            pred = model.predict_log_us([(c[0], c[1], c[2], pl[0], pl[1]) for c, pl in rows])
+            by = {}
+            for (c, pl), y in zip(rows, pred):
+                by.setdefault(c, []).append((float(y), pl))
+            for c, lst in by.items():
+                top = [pl for _, pl in sorted(lst)[:TOP_K]]
+                meds = cells[c]
+                ratios.append(min(meds[pl] for pl in top) / min(meds.values()))
+        r = np.array(ratios)
+        out[(steps, lr)] = (float(np.mean(r <= 1.10)), float(np.exp(np.mean(np.log(r)))), float(r.max()))
+        if log:
+            log(f"steps={steps} lr={lr}: top-{TOP_K} within 10 % {out[(steps, lr)][0]:.3f}, geomean "
+                f"{out[(steps, lr)][1]:.4f}, max {out[(steps, lr)][2]:.3f} over {len(r)} cells")
+    return out
+
+
+def _cmd_cv(args):
+    recs = load_records(args.sweep)
+    configs = [(int(c.split(":")[0]), float(c.split(":")[1])) for c in args.configs.split(",")]
+    res = cross_validate(recs, configs)
+    best = max(res, key=lambda k: (res[k][0], -res[k][1]))
+    print(f"chosen: steps={best[0]} lr={best[1]}")
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump({"sweep_sha256": _sha256(args.sweep), "k": TOP_K,
+                       "results": [{"steps": k[0], "lr": k[1], "within_10pct": v[0], "geomean": v[1], "max": v[2]}
+                                   for k, v in res.items()],
+                       "chosen": {"steps": best[0], "lr": best[1]}}, f, indent=1)
+
+
 def _cmd_train(args):
     recs = load_records(args.sweep)
     model = CostModel.train(recs, steps=args.steps, lr=args.lr, seed=args.seed)
@@ -279,12 +328,16 @@ def main(argv=None):
     t.add_argument("--steps", type=int, default=STEPS)
     t.add_argument("--lr", type=float, default=LR)
     t.add_argument("--seed", type=int, default=SEED)
+    c = sub.add_parser("cv")
+    c.add_argument("--sweep", default=DEFAULT_SWEEP)
+    c.add_argument("--configs", default="2000:1e-3,5000:1e-3,10000:1e-3,5000:3e-3")
+    c.add_argument("--out", default="")
     e = sub.add_parser("evaluate")
     e.add_argument("--heldout", default=DEFAULT_HELDOUT)
     e.add_argument("--model", default=DEFAULT_MODEL)
     e.add_argument("--out", default=DEFAULT_EVAL)
     args = ap.parse_args(argv)
-    {"train": _cmd_train, "evaluate": _cmd_evaluate}[args.cmd](args)
+    {"cv": _cmd_cv, "train": _cmd_train, "evaluate": _cmd_evaluate}[args.cmd](args)
 
 
 if __name__ == "__main__":

@@ -96,14 +96,14 @@ __global__ void __launch_bounds__(512) adjoint_wave(int n, int nrhs, int batch, 
                                                     const float* __restrict__ X, const float* __restrict__ G,
                                                     float* __restrict__ dB, float* __restrict__ dA, int region) {
     extern __shared__ float lds[];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = wave_index(), lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
     float* buf = lds + (size_t)w * region;
     const float* Lg = L + p * n * n;
     const long long ob = p * n * nrhs;
     float a[NB];
-    rows_load_lower<NB>(a, Lg, n, lane);
+    rows_load_lower<NB, true>(a, Lg, n, lane);
     const float myinv = diag_inv(Lg, n, lane);
     float d[NB];
 #pragma unroll

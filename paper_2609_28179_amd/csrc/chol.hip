@@ -102,13 +102,13 @@ template <int NB>
 __global__ void __launch_bounds__(512) potrf_wave(int n, int batch, float* __restrict__ A, int* __restrict__ info,
                                                   int region) {
     extern __shared__ float lds[];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = wave_index(), lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
     float* buf = lds + (size_t)w * region;
     float* Ag = A + p * n * n;
     float a[NB];
-    rows_load_lower<NB>(a, Ag, n, lane);
+    rows_load_lower<NB, false>(a, Ag, n, lane);
     float myinv;
     const int inf = wave_potrf<NB>(a, lane, myinv);
     const bool vec = (n & 3) == 0 && aligned16(A);
@@ -122,14 +122,14 @@ template <int NB, bool MULTI>
 __global__ void __launch_bounds__(512) posv_wave(int n, int nrhs, int batch, float* __restrict__ A,
                                                  float* __restrict__ B, int* __restrict__ info, int region) {
     extern __shared__ float lds[];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = wave_index(), lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
     float* buf = lds + (size_t)w * region;
     float* Ag = A + p * n * n;
     float* Bg = B + p * n * nrhs;
     float a[NB];
-    rows_load_lower<NB>(a, Ag, n, lane);
+    rows_load_lower<NB, false>(a, Ag, n, lane);
     float myinv;
     const int inf = wave_potrf<NB>(a, lane, myinv);
     const bool vec = (n & 3) == 0 && aligned16(A);
@@ -150,14 +150,14 @@ template <int NB, bool MULTI>
 __global__ void __launch_bounds__(512) potrs_wave(int n, int nrhs, int batch, const float* __restrict__ L,
                                                   float* __restrict__ B, int region) {
     extern __shared__ float lds[];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = wave_index(), lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
     float* buf = lds + (size_t)w * region;
     const float* Lg = L + p * n * n;
     float* Bg = B + p * n * nrhs;
     float a[NB];
-    rows_load_lower<NB>(a, Lg, n, lane);
+    rows_load_lower<NB, true>(a, Lg, n, lane);
     const float myinv = diag_inv(Lg, n, lane);
     if (MULTI) {
         wave_solve_all<NB>(a, buf, nullptr, false, Bg, n, nrhs, myinv, lane);
@@ -173,13 +173,13 @@ template <int NB>
 __global__ void __launch_bounds__(512) trsv_wave(int n, int trans, int batch, const float* __restrict__ L,
                                                  float* __restrict__ x, int region) {
     extern __shared__ float lds[];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = wave_index(), lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
     float* buf = lds + (size_t)w * region;
     const float* Lg = L + p * n * n;
     float a[NB];
-    rows_load_lower<NB>(a, Lg, n, lane);
+    rows_load_lower<NB, true>(a, Lg, n, lane);
     const float myinv = diag_inv(Lg, n, lane);
     float acc = lane < n ? x[p * n + lane] : 0.f;
     if (trans == 0)

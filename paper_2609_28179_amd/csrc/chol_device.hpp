@@ -144,11 +144,19 @@ GLASS_DEV void thread_solve_rhs(const float (&a)[N * (N + 1) / 2], const float (
 
 // -------------------------------------------------------------- wave scope --
 // Lane i owns row i.  Rows come straight from global memory with 16-byte
-// buffer loads of only the column blocks at or left of the diagonal; rows and
-// columns beyond n are padded with an identity block, so every column loop
-// runs the full bucket width NB without a data-dependent exit and the leading
-// n x n factor is unchanged (padded pivots are 1, padded couplings 0).
-template <int NB>
+// buffer loads of only the column blocks at or left of the diagonal; blocks
+// right of the diagonal block are zero.
+//   MASK (L used as stored: POTRS, TRSV, the adjoint): the diagonal block is
+//     cut at the diagonal and rows past n are zero.
+//   !MASK (a factorization): the diagonal block keeps whatever the row holds
+//     past the diagonal -- it stays in the upper part (an update of row i
+//     writes only columns past the current step, and those of row i's lower
+//     part use only lower entries) and wave_potrf clears it at the end -- and
+//     rows past n are identity rows, so their steps take a unit pivot and
+//     leave every other row unchanged.  The identity is built from the lane's
+//     own 4-wide block and element (no compare per column, which would stay
+//     live across the unrolled factorization).
+template <int NB, bool MASK>
 GLASS_DEV void rows_load_lower(float (&a)[NB], const float* Ag, int n, int lane) {
     const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(Ag, (uint32_t)(n * n) * 4u);
     const bool row = lane < n;
@@ -166,12 +174,38 @@ GLASS_DEV void rows_load_lower(float (&a)[NB], const float* Ag, int n, int lane)
                             float, __builtin_amdgcn_raw_buffer_load_b32(rs, (lane * n + 4 * t + e) * 4, 0, 0));
             }
         }
+        if (MASK) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int j = 4 * t + e;
-            a[j] = (row && j <= lane) ? v[e] : (j == lane ? 1.f : 0.f);
+            for (int e = 0; e < 4; ++e) a[4 * t + e] = (4 * t + e <= lane) ? v[e] : 0.f;
+        } else {
+            const bool dblk = !row && t == (lane >> 2);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) a[4 * t + e] = (dblk && e == (lane & 3)) ? 1.f : v[e];
         }
     }
+}
+
+// v in the lane whose bit is set in the constant mask 1 << J, `other` in the
+// rest: one v_cndmask on a scalar literal mask (a lane compare per step would
+// keep 64 compare results alive across the unrolled factorization).  The
+// compiler does not insert wait states for operands read inside inline asm:
+// v comes straight from v_rsq (a transcendental result needs one wait state
+// before a VALU reads it), so the block starts with s_nop 1.
+template <int J>
+GLASS_DEV float lane_select(float other, float v) {
+    float r;
+    asm("s_nop 1\n\tv_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(other), "v"(v), "s"(1ull << J));
+    return r;
+}
+
+// The scalar v written into lane K of `old` (immediate lane select).  v is
+// the SGPR a v_readlane has just written; a VALU read of an SGPR written by a
+// VALU needs wait states the compiler does not insert for inline asm, so the
+// block starts with s_nop 4 (five wait states, above every such requirement).
+template <int K>
+GLASS_DEV float writelane(float v, float old) {
+    asm("s_nop 4\n\tv_writelane_b32 %0, %1, %2" : "+v"(old) : "s"(v), "i"(K));
+    return old;
 }
 
 // One column step of the right-looking factorization: the pivot of column J
@@ -195,8 +229,8 @@ struct WaveStep {
         const float d = readlane(a[J], J);
         if (!(d > 0.f) && info == 0) info = J + 1;
         const float inv = rsq(d);
-        const float v = lane == J ? d * inv : a[J] * inv;
-        myinv = lane == J ? inv : myinv;
+        const float v = a[J] * inv;  // in lane J, a[J] is the pivot itself: v = sqrt(d)
+        myinv = lane_select<J>(myinv, inv);
         a[J] = v;
         float R[4];
         replicate_rows<(NB + 15) / 16>(v, R);
@@ -209,8 +243,8 @@ struct WaveStep<NB, NB> {
     static GLASS_DEV void run(float (&)[NB], int, int&, float&) {}
 };
 
-// Factor the identity-padded rows in place; returns info, sets myinv = 1/L_ii
-// and clears the strict upper part of every row.
+// Factor the rows in place (identity rows past the order); returns info, sets
+// myinv = 1 / L_ii and clears the strict upper part of every row.
 template <int NB>
 GLASS_DEV int wave_potrf(float (&a)[NB], int lane, float& myinv) {
     int info = 0;
@@ -224,55 +258,79 @@ GLASS_DEV int wave_potrf(float (&a)[NB], int lane, float& myinv) {
 // Forward substitution L y = b for one right-hand side, b_i in lane i: the
 // solved unknown is broadcast with v_readlane (rows hold L_ik with a zero
 // strict upper part; padded lanes have b = 0 and L_ii = 1).
+// Each solved unknown is written into its lane with v_writelane; the update
+// runs in every lane (lane k's own accumulator is not used again).
+template <int NB, int K, int RG>
+struct FwdStep {
+    static GLASS_DEV void run(const float (&a)[NB], float (&acc)[RG], float (&y)[RG], float myinv) {
+        float yk[RG];
+#pragma unroll
+        for (int c = 0; c < RG; ++c) yk[c] = readlane(acc[c] * myinv, K);
+#pragma unroll
+        for (int c = 0; c < RG; ++c) {
+            acc[c] = fmaf(-a[K], yk[c], acc[c]);
+            y[c] = writelane<K>(yk[c], y[c]);
+        }
+        FwdStep<NB, K + 1, RG>::run(a, acc, y, myinv);
+    }
+};
+template <int NB, int RG>
+struct FwdStep<NB, NB, RG> {
+    static GLASS_DEV void run(const float (&)[NB], float (&)[RG], float (&)[RG], float) {}
+};
+
 template <int NB>
 GLASS_DEV float wave_fwd(const float (&a)[NB], float acc, float myinv, int lane) {
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        const float yk = readlane(acc * myinv, k);
-        acc = lane == k ? yk : fmaf(-a[k], yk, acc);
-    }
-    return acc;
+    float accv[1] = {acc}, y[1] = {0.f};
+    FwdStep<NB, 0, 1>::run(a, accv, y, myinv);
+    return y[0];
 }
 
-// Rows r0 .. r0+7 (< n) of L (strict upper +0) from the owning lanes into
-// the LDS chunk buffer, row-major with row stride n.
+// Rows r0 .. r0+7 of L (strict upper +0, identity padding past n) from the
+// owning lanes into the LDS chunk buffer, row stride NB: every lane of the
+// chunk writes its whole padded row with 16-byte stores and no per-element
+// predicate (a predicate per column of a runtime n spilled scalar registers).
 template <int NB>
-GLASS_DEV void rows_to_lds(const float (&a)[NB], float* buf, int n, int r0, int lane) {
-    if (lane >= r0 && lane < r0 + 8 && lane < n) {
-        float* dst = buf + (lane - r0) * n;
-        if ((n & 3) == 0) {
+GLASS_DEV void rows_to_lds(const float (&a)[NB], float* buf, int r0, int lane) {
+    if (lane >= r0 && lane < r0 + 8) {
+        float* dst = buf + (lane - r0) * NB;
 #pragma unroll
-            for (int t = 0; t < NB / 4; ++t) {
-                if (4 * t < n) {
-                    f4_t v;
+        for (int t = 0; t < NB / 4; ++t) {
+            f4_t v;
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) v[e] = a[4 * t + e];
-                    *reinterpret_cast<f4_t*>(dst + 4 * t) = v;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < NB; ++j)
-                if (j < n) dst[j] = a[j];
+            for (int e = 0; e < 4; ++e) v[e] = a[4 * t + e];
+            *reinterpret_cast<f4_t*>(dst + 4 * t) = v;
         }
     }
 }
 
-// Coalesced copy of len floats from the LDS chunk to global memory.
-GLASS_DEV void chunk_to_global(float* __restrict__ dst, const float* buf, int len, bool vec, int lane) {
+// Coalesced copy of `rows` rows of n floats from the LDS chunk (row stride
+// NB) to contiguous global memory (row stride n).  vec: n % 4 == 0 and dst
+// 16-byte aligned.
+template <int NB>
+GLASS_DEV void chunk_to_global(float* __restrict__ dst, const float* buf, int rows, int n, bool vec, int lane) {
     if (vec) {
-        for (int q = lane; q < (len >> 2); q += 64)
-            reinterpret_cast<f4_t*>(dst)[q] = reinterpret_cast<const f4_t*>(buf)[q];
+        const int n4 = n >> 2;
+        const FastDiv f4 = make_fastdiv((uint32_t)n4);
+        for (int q = lane; q < rows * n4; q += 64) {
+            const int rr = (int)fdiv((uint32_t)q, f4), c4 = q - rr * n4;
+            reinterpret_cast<f4_t*>(dst)[q] = *reinterpret_cast<const f4_t*>(buf + rr * NB + 4 * c4);
+        }
     } else {
-        for (int g = lane; g < len; g += 64) dst[g] = buf[g];
+        const FastDiv fn = make_fastdiv((uint32_t)n);
+        for (int g = lane; g < rows * n; g += 64) {
+            const int rr = (int)fdiv((uint32_t)g, fn), cc = g - rr * n;
+            dst[g] = buf[rr * NB + cc];
+        }
     }
 }
 
 // Backward substitution L^T x = y for the rows of the chunk in LDS (rows
-// r0 .. r1-1, descending); lane i < k reads L_ki from row k of the chunk.
-GLASS_DEV float wave_bwd_chunk(const float* buf, int n, int r0, int r1, float acc, float myinv, int lane) {
+// r0 .. r1-1, descending, row stride NB); lane i < k reads L_ki from row k.
+template <int NB>
+GLASS_DEV float wave_bwd_chunk(const float* buf, int r0, int r1, float acc, float myinv, int lane) {
     for (int k = r1 - 1; k >= r0; --k) {
-        const float lki = lane < k ? buf[(k - r0) * n + lane] : 0.f;
+        const float lki = lane < k ? buf[(k - r0) * NB + lane] : 0.f;
         const float xk = readlane(acc * myinv, k);
         acc = lane == k ? xk : fmaf(-lki, xk, acc);
     }
@@ -287,10 +345,10 @@ GLASS_DEV float wave_chunks_desc(const float (&a)[NB], float* buf, float* Lg, bo
                                  float acc, float myinv) {
     for (int r0 = (n - 1) & ~7; r0 >= 0; r0 -= 8) {
         const int r1 = min(r0 + 8, n);
-        rows_to_lds<NB>(a, buf, n, r0, lane);
+        rows_to_lds<NB>(a, buf, r0, lane);
         wave_sync();
-        if (Lg) chunk_to_global(Lg + r0 * n, buf, (r1 - r0) * n, vec, lane);
-        if (bwd) acc = wave_bwd_chunk(buf, n, r0, r1, acc, myinv, lane);
+        if (Lg) chunk_to_global<NB>(Lg + r0 * n, buf, r1 - r0, n, vec, lane);
+        if (bwd) acc = wave_bwd_chunk<NB>(buf, r0, r1, acc, myinv, lane);
         wave_sync();
     }
     return acc;
@@ -301,21 +359,16 @@ GLASS_DEV float wave_chunks_desc(const float (&a)[NB], float* buf, float* Lg, bo
 // unknowns (independent v_readlane) and updates RG accumulators, so the
 // dependent chain is n steps for the whole group instead of n per column.
 template <int NB, int RG>
-GLASS_DEV void wave_fwd_rg(const float (&a)[NB], float (&acc)[RG], float myinv, int lane) {
+GLASS_DEV void wave_fwd_rg(const float (&a)[NB], float (&acc)[RG], float (&y)[RG], float myinv, int lane) {
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        float yk[RG];
-#pragma unroll
-        for (int c = 0; c < RG; ++c) yk[c] = readlane(acc[c] * myinv, k);
-#pragma unroll
-        for (int c = 0; c < RG; ++c) acc[c] = lane == k ? yk[c] : fmaf(-a[k], yk[c], acc[c]);
-    }
+    for (int c = 0; c < RG; ++c) y[c] = 0.f;
+    FwdStep<NB, 0, RG>::run(a, acc, y, myinv);
 }
 
-template <int RG>
-GLASS_DEV void wave_bwd_chunk_rg(const float* buf, int n, int r0, int r1, float (&acc)[RG], float myinv, int lane) {
+template <int NB, int RG>
+GLASS_DEV void wave_bwd_chunk_rg(const float* buf, int r0, int r1, float (&acc)[RG], float myinv, int lane) {
     for (int k = r1 - 1; k >= r0; --k) {
-        const float lki = lane < k ? buf[(k - r0) * n + lane] : 0.f;
+        const float lki = lane < k ? buf[(k - r0) * NB + lane] : 0.f;
         float xk[RG];
 #pragma unroll
         for (int c = 0; c < RG; ++c) xk[c] = readlane(acc[c] * myinv, k);
@@ -330,21 +383,21 @@ GLASS_DEV void wave_bwd_chunk_rg(const float* buf, int n, int r0, int r1, float 
 template <int NB, int RG>
 GLASS_DEV void wave_solve_cols(const float (&a)[NB], float* buf, float* Lg, bool vec, float* Bg, int n, int nrhs,
                                int c0, float myinv, int lane) {
-    float acc[RG];
+    float acc[RG], y[RG];
 #pragma unroll
     for (int c = 0; c < RG; ++c) acc[c] = (lane < n && c0 + c < nrhs) ? Bg[lane * nrhs + c0 + c] : 0.f;
-    wave_fwd_rg<NB, RG>(a, acc, myinv, lane);
+    wave_fwd_rg<NB, RG>(a, acc, y, myinv, lane);
     for (int r0 = (n - 1) & ~7; r0 >= 0; r0 -= 8) {
         const int r1 = min(r0 + 8, n);
-        rows_to_lds<NB>(a, buf, n, r0, lane);
+        rows_to_lds<NB>(a, buf, r0, lane);
         wave_sync();
-        if (Lg) chunk_to_global(Lg + r0 * n, buf, (r1 - r0) * n, vec, lane);
-        wave_bwd_chunk_rg<RG>(buf, n, r0, r1, acc, myinv, lane);
+        if (Lg) chunk_to_global<NB>(Lg + r0 * n, buf, r1 - r0, n, vec, lane);
+        wave_bwd_chunk_rg<NB, RG>(buf, r0, r1, y, myinv, lane);
         wave_sync();
     }
 #pragma unroll
     for (int c = 0; c < RG; ++c)
-        if (lane < n && c0 + c < nrhs) Bg[lane * nrhs + c0 + c] = acc[c];
+        if (lane < n && c0 + c < nrhs) Bg[lane * nrhs + c0 + c] = y[c];
 }
 
 // All nrhs columns in groups of 8, 4 or 1 (L stored during the first group).

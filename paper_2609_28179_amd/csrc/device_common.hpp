@@ -37,6 +37,20 @@ GLASS_DEV void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Index of this thread's wavefront within its workgroup as a wave-uniform
+// (scalar) value.  Addresses and buffer descriptors derived from it then live
+// in SGPRs; derived from threadIdx.x directly they are per-lane values to the
+// compiler, which wraps every buffer load in a readfirstlane loop.
+GLASS_DEV int wave_index() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// A value the caller knows to be equal in every active lane, as a scalar.
+GLASS_DEV int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+GLASS_DEV long long uniform_i64(long long v) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v & 0xffffffffll));
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((unsigned long long)v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
 GLASS_DEV float readlane(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }

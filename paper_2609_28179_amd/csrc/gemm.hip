@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(512) gemm_small_wave(int m, int n, int k, int 
                                                        const float* __restrict__ A, const float* __restrict__ B,
                                                        float beta, float* __restrict__ C, int region) {
     extern __shared__ float lds[];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = wave_index(), lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
     gemm_small_problem<TA, TBT>(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lds + (size_t)w * region,
@@ -218,7 +218,7 @@ template <int TB, bool VEC, bool TA = false, bool TBT = false>
 __global__ void __launch_bounds__(512) gemm_mfma_wave(int m, int n, int k, int batch, float alpha,
                                                       const float* __restrict__ A, const float* __restrict__ B,
                                                       float beta, float* __restrict__ C) {
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = wave_index(), lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
     mfma_problem<TB, VEC, TB, TA, TBT>(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lane, 0,
@@ -229,7 +229,7 @@ template <int TB, bool VEC, bool TA = false, bool TBT = false>
 __global__ void __launch_bounds__(256) gemm_mfma_wg(int m, int n, int k, int batch, int pack, float alpha,
                                                     const float* __restrict__ A, const float* __restrict__ B,
                                                     float beta, float* __restrict__ C) {
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int w = wave_index(), lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     for (int q = 0; q < pack; ++q) {
         const long long p = (long long)blockIdx.x * pack + q;
         if (p >= batch) break;

@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(512) gemv_wave(int m, int n, int batch, float 
                                                  const float* __restrict__ x, float beta, float* __restrict__ y,
                                                  int region) {
     extern __shared__ float lds[];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = wave_index(), lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
     float* As = lds + (size_t)w * region;

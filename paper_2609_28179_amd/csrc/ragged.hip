@@ -158,7 +158,7 @@ template <int NB>
 GLASS_DEV void ragged_wave_one(float* __restrict__ Ag, float* __restrict__ Bg, int n, int nrhs, int32_t* info,
                                float* buf, int lane) {
     float a[NB];
-    rows_load_lower<NB>(a, Ag, n, lane);
+    rows_load_lower<NB, false>(a, Ag, n, lane);
     float myinv;
     const int inf = wave_potrf<NB>(a, lane, myinv);
     const bool vec = false;  // problem offsets are arbitrary: 4-byte stores
@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(256) ragged_solve(const int32_t* __restrict__ 
                                                     int32_t* info, const int32_t* __restrict__ perm,
                                                     const int32_t* __restrict__ meta, RaggedScopes scopes) {
     __shared__ float chunk[4][8 * 64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = wave_index();
     const int item = blockIdx.x * 4 + w;
     if (item >= meta[3 * kClasses]) return;
     int k = kClasses - 1;
@@ -208,14 +208,15 @@ __global__ void __launch_bounds__(256) ragged_solve(const int32_t* __restrict__ 
         }
         return;
     }
-    const int e = perm[cbase + rel];
-    const int n = nvec[e], r = rvec[e];
+    // one problem per wavefront: its index, sizes and offsets are wave-uniform
+    const int e = uniform_i32(perm[cbase + rel]);
+    const int n = uniform_i32(nvec[e]), r = uniform_i32(rvec[e]);
     if (n < 1 || n > kMaxN || r < 1 || r > kMaxN) {
         if (lane == 0) info[e] = -1;
         return;
     }
-    float* Ag = A + offA[e];
-    float* Bg = B + offB[e];
+    float* Ag = A + uniform_i64(offA[e]);
+    float* Bg = B + uniform_i64(offB[e]);
     float* buf = chunk[w];
     switch (k) {
     case 0: ragged_wave_one<8>(Ag, Bg, n, r, info + e, buf, lane); break;

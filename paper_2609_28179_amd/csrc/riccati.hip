@@ -30,7 +30,7 @@ __global__ void __launch_bounds__(512) riccati_wave(int nx, int nu, int batch, c
                                                     const float* __restrict__ R, float* __restrict__ K,
                                                     int32_t* __restrict__ info, int region) {
     extern __shared__ float lds[];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = wave_index(), lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
     float* Ps = lds + (size_t)w * region;  // [NX8][NX8]

@@ -95,7 +95,7 @@ GLASS_DEV float se3_entry(int inverse, const float* a, const float* b, int e) {
 
 __global__ void __launch_bounds__(512) se3_wave(int inverse, int batch, const float* Ta,
                                                 const float* Tb, float* Tout) {
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = wave_index(), lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
     float v = 0.f;
