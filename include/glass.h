@@ -70,7 +70,9 @@ typedef enum {
 typedef enum {
     GLASS_SCOPE_THREAD = 0,    /* one problem per lane                       */
     GLASS_SCOPE_WAVE = 1,      /* one problem per 64-lane wavefront          */
-    GLASS_SCOPE_WORKGROUP = 2  /* one problem per workgroup at a time        */
+    GLASS_SCOPE_WORKGROUP = 2, /* one problem per workgroup at a time        */
+    GLASS_SCOPE_SUBWAVE = 3    /* ragged batches only: four problems per
+                                  wavefront, one per 16-lane row (n <= 16)  */
 } glass_scope_t;
 
 /* A placement (Sec. III-A, Sec. IV-C).  `pack` P in {1,2,4,8} counts the
@@ -202,15 +204,20 @@ glass_status_t glass_posv_adjoint_batched(int n, int nrhs, int batch, const floa
  * Problems are grouped into eight size classes (orders 8k+1 .. 8k+8) by a
  * deterministic stable counting sort on the device, largest class first;
  * class_scope (HOST int32[8] or NULL) picks each class's scope: thread
- * (class 0 only, 64 problems per wavefront; GLASS_ERR_INFEASIBLE_PLACEMENT
- * for another class) or wave (one problem per wavefront); NULL takes each
- * class's scope from the table's POSV entry at order 8k+8 and batch count/8.  Concurrent calls must not share a
- * workspace. */
+ * (class 0 only, 64 problems per wavefront), sub-wave (classes 0 and 1, four
+ * problems per wavefront, one per 16-lane row) or wave (one problem per
+ * wavefront); a scope a class cannot take is GLASS_ERR_INFEASIBLE_PLACEMENT,
+ * another value GLASS_ERR_INVALID_VALUE.  NULL takes the measured per-class
+ * choice of the built-in ragged table (glass_ragged_table_provenance()).
+ * Concurrent calls must not share a workspace. */
 glass_status_t glass_posv_ragged(int count, const int32_t* n, const int32_t* nrhs,
                                  const int64_t* offA, const int64_t* offB, float* A,
                                  float* B, int32_t* info, void* workspace,
                                  size_t workspace_bytes, const int32_t* class_scope,
                                  void* stream);
+
+/* Provenance of the built-in per-class ragged placement table. */
+const char* glass_ragged_table_provenance(void);
 
 /* Workspace bytes glass_posv_ragged needs for `count` problems (0 if
  * count < 0), and the byte offset of the permutation inside it. */

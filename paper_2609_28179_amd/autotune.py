@@ -6,6 +6,8 @@ samples kept, a 5 % dispatch margin).
   python -m paper_2609_28179_amd.autotune sweep [--rounds 20] [--out FILE] [--cells table|heldout]
   python -m paper_2609_28179_amd.autotune emit  [--sweep FILE] [--out INC]
   python -m paper_2609_28179_amd.autotune summary [--sweep FILE]
+  python -m paper_2609_28179_amd.autotune ragged [--out FILE]   (per-class ragged placement)
+  python -m paper_2609_28179_amd.autotune emit-ragged [--sweep FILE] [--out INC]
 
 The sweep covers the 250 cells {GEMM, GEMV, POTRF, POTRS, POSV, TRSV} x
 n in {3,4,6,7,12,16,32,64} x batch in {1,16,256,4096,65536} plus SE(3)
@@ -190,6 +192,101 @@ def summary(args):
     print(text)
 
 
+DEFAULT_RAGGED = os.path.join(PKG, "tuning", "ragged_gfx950.jsonl")
+DEFAULT_RAGGED_INC = os.path.join(PKG, "csrc", "glass_ragged_gfx950.inc")
+RAGGED_PER_SIZE = 5556   # problems per order: the density of the 50,000-system workload over nine orders
+
+
+def ragged_options(k):
+    """Placements a size class k (orders 8k+1 .. 8k+8) can take."""
+    return ["wave"] + (["thread"] if k == 0 else []) + (["subwave"] if k <= 1 else [])
+
+
+def ragged_class_sizes(k):
+    from . import inputs
+    sizes = [s for s in inputs.RAGGED_SIZES if (s - 1) // 8 == k]
+    return sizes or [8 * k + 8]
+
+
+def ragged_sweep(args):
+    """Per size class: a ragged batch of that class's orders (nrhs 1-8), solved
+    under every placement the class can take, in paired shuffled rounds of
+    graph replays with the inputs restored between them."""
+    import torch
+    from . import glass, inputs
+    rng = random.Random(args.seed)
+    dev = torch.device("cuda:0")
+    os.makedirs(os.path.dirname(args.out), exist_ok=True)
+    with open(args.out, "w") as f:
+        p = torch.cuda.get_device_properties(0)
+        f.write(json.dumps({"kind": "meta", "gpu": p.name, "arch": p.gcnArchName, "git": _git_hash(),
+                            "date": datetime.datetime.utcnow().isoformat(timespec="seconds"),
+                            "per_size": RAGGED_PER_SIZE, "rounds": args.rounds}) + "\n")
+        for k in range(8):
+            sizes = ragged_class_sizes(k)
+            case = inputs.make_ragged(RAGGED_PER_SIZE * len(sizes), seed=100 + k, sizes=sizes)
+            rg = glass.Ragged(case, device=dev)
+            A0, B0 = rg.A.clone(), rg.B.clone()
+            graphs = {}
+            for opt in ragged_options(k):
+                scopes = ["wave"] * 8
+                scopes[k] = opt
+                rg.solve(class_scope=scopes)
+                torch.cuda.synchronize()
+                rg.A.copy_(A0)
+                rg.B.copy_(B0)
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g):
+                    rg.solve(class_scope=scopes)
+                graphs[opt] = g
+            samples = {o: [] for o in graphs}
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            order = list(graphs)
+            for r in range(3 + args.rounds):
+                rng.shuffle(order)
+                for o in order:
+                    rg.A.copy_(A0)
+                    rg.B.copy_(B0)
+                    e0.record()
+                    graphs[o].replay()
+                    e1.record()
+                    e1.synchronize()
+                    if r >= 3:
+                        samples[o].append(e0.elapsed_time(e1) * 1e3)
+            for o, v in samples.items():
+                f.write(json.dumps({"class": k, "sizes": sizes, "count": len(case["n"]), "scope": o,
+                                    "median_us": float(np.median(v)), "samples_us": [round(x, 3) for x in v]}) + "\n")
+            f.flush()
+            best = min(samples, key=lambda o: (np.median(samples[o]), ragged_options(k).index(o)))
+            print(f"class {k} sizes {sizes}: " + ", ".join(f"{o} {np.median(v):.1f} us" for o, v in samples.items())
+                  + f" -> {best}", flush=True)
+            del graphs, rg
+            torch.cuda.empty_cache()
+
+
+def emit_ragged(args):
+    from . import glass
+    meta, recs = load(args.sweep)
+    codes = {"thread": glass.SCOPE_THREAD, "wave": glass.SCOPE_WAVE, "subwave": glass.SCOPE_SUBWAVE}
+    win = []
+    for k in range(8):
+        cell = [r for r in recs if r["class"] == k]
+        best = min(cell, key=lambda r: (r["median_us"], ragged_options(k).index(r["scope"])))
+        win.append(codes[best["scope"]])
+    prov = (f"gfx950 / {meta.get('gpu', '?')} / git {meta.get('git', '?')} / ragged sweep {meta.get('date', '?')}"
+            if meta else "gfx950 / no sweep")
+    text = ("// glass_ragged_gfx950.inc -- measured per-class placement of ragged batches on\n"
+            "// gfx950, generated by paper_2609_28179_amd/autotune.py emit-ragged from\n"
+            "// paper_2609_28179_amd/tuning/ragged_gfx950.jsonl.  Do not edit by hand.\n"
+            "// kRaggedScope[k]: scope of size class k (orders 8k+1 .. 8k+8); 0 thread,\n"
+            "// 1 wave, 3 sub-wave.\n"
+            f"static const char kRaggedProvenance[] = \"{prov}\";\n"
+            f"static const int kRaggedScope[8] = {{{', '.join(map(str, win))}}};\n")
+    with open(args.out, "w") as f:
+        f.write(text)
+    print(f"wrote {args.out}: {win}")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -209,8 +306,16 @@ def main(argv=None):
     m = sub.add_parser("summary")
     m.add_argument("--sweep", default=DEFAULT_SWEEP)
     m.add_argument("--out", default="")
+    rs = sub.add_parser("ragged")
+    rs.add_argument("--out", default=DEFAULT_RAGGED)
+    rs.add_argument("--rounds", type=int, default=20)
+    rs.add_argument("--seed", type=int, default=0)
+    re_ = sub.add_parser("emit-ragged")
+    re_.add_argument("--sweep", default=DEFAULT_RAGGED)
+    re_.add_argument("--out", default=DEFAULT_RAGGED_INC)
     args = ap.parse_args(argv)
-    {"sweep": sweep, "emit": emit, "summary": summary}[args.cmd](args)
+    {"sweep": sweep, "emit": emit, "summary": summary, "ragged": ragged_sweep,
+     "emit-ragged": emit_ragged}[args.cmd](args)
 
 
 if __name__ == "__main__":

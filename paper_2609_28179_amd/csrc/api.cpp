@@ -10,6 +10,7 @@ namespace glass {
 namespace {
 
 #include "glass_table_gfx950.inc"
+#include "glass_ragged_gfx950.inc"
 
 constexpr int kNumN = sizeof(kTableN) / sizeof(kTableN[0]);
 constexpr int kNumB = sizeof(kTableB) / sizeof(kTableB[0]);
@@ -219,16 +220,12 @@ glass_status_t glass_posv_ragged(int count, const int32_t* n, const int32_t* nrh
     if (count < 0) return GLASS_ERR_INVALID_VALUE;
     RaggedScopes sc{};
     for (int k = 0; k < 8; ++k) {
-        if (class_scope) {
-            const int s = class_scope[k];
-            if (s != GLASS_SCOPE_THREAD && s != GLASS_SCOPE_WAVE) return GLASS_ERR_INVALID_VALUE;
-            if (s == GLASS_SCOPE_THREAD && k > 0) return GLASS_ERR_INFEASIBLE_PLACEMENT;
-            sc.s[k] = s;
-        } else {
-            int scope, pack;
-            table_lookup(GLASS_OP_POSV, 8 * (k + 1), count / 8 > 0 ? count / 8 : 1, &scope, &pack);
-            sc.s[k] = (scope == GLASS_SCOPE_THREAD && k == 0) ? GLASS_SCOPE_THREAD : GLASS_SCOPE_WAVE;
-        }
+        const int s = class_scope ? class_scope[k] : kRaggedScope[k];
+        if (s != GLASS_SCOPE_THREAD && s != GLASS_SCOPE_WAVE && s != GLASS_SCOPE_SUBWAVE)
+            return GLASS_ERR_INVALID_VALUE;
+        if ((s == GLASS_SCOPE_THREAD && k > 0) || (s == GLASS_SCOPE_SUBWAVE && k > 1))
+            return GLASS_ERR_INFEASIBLE_PLACEMENT;
+        sc.s[k] = s;
     }
     if (count == 0) return GLASS_OK;
     if (!n || !nrhs || !offA || !offB || !A || !B || !info || !workspace) return GLASS_ERR_INVALID_VALUE;
@@ -262,6 +259,8 @@ int glass_riccati_feasible(int nx, int nu, int pack) {
     if (pack != 1 && pack != 2 && pack != 4 && pack != 8) return GLASS_ERR_INVALID_VALUE;
     return riccati_region_floats(nx, nu) * sizeof(float) * pack <= kLdsBudgetBytes ? 1 : 0;
 }
+
+const char* glass_ragged_table_provenance(void) { return kRaggedProvenance; }
 
 int glass_last_launch_error(void) { return t_last_launch_error; }
 

@@ -192,7 +192,9 @@ int launch_trsv(const Shape& s, const Geometry& g, int batch, const float* L, fl
 int launch_se3(const Shape& s, const Geometry& g, int batch, const float* Ta, const float* Tb,
                float* Tout, void* stream);
 // Placement (scope) of each of the eight ragged size classes (orders 8k+1 ..
-// 8k+8); thread scope is available for class 0 (n <= 8).
+// 8k+8); thread scope is available for class 0 (n <= 8), sub-wave scope
+// (GLASS_SCOPE_SUBWAVE, four problems per wavefront) for classes 0 and 1.
+constexpr int kScopeSubwave = GLASS_SCOPE_SUBWAVE;
 struct RaggedScopes {
     int32_t s[8];
 };

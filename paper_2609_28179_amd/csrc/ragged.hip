@@ -31,6 +31,12 @@ constexpr int kClasses = 8;
 constexpr int kChunk = 1024;        // problems per histogram / scatter block
 constexpr int kScanThreads = 256;
 
+// Work items of a class of `cnt` problems: 64 problems per item at thread
+// scope, 4 at sub-wave scope, 1 at wave scope.
+GLASS_DEV int items_of(int scope, int cnt) {
+    return scope == GLASS_SCOPE_THREAD ? (cnt + 63) / 64 : (scope == kScopeSubwave ? (cnt + 3) / 4 : cnt);
+}
+
 // Size class of order n; orders outside 1..64 are clamped into a class here
 // and flagged (info = -1, problem skipped) by the solve kernel.
 GLASS_DEV int class_of(int n) {
@@ -73,7 +79,7 @@ __global__ void __launch_bounds__(kScanThreads) ragged_scan(int nchunks, int32_t
             meta[kClasses + k] = base;
             meta[2 * kClasses + k] = items;
             base += tot[k];
-            items += scopes.s[k] == GLASS_SCOPE_THREAD ? (tot[k] + 63) / 64 : tot[k];
+            items += items_of(scopes.s[k], tot[k]);
         }
         meta[3 * kClasses] = items;  // total work items
     }
@@ -170,6 +176,167 @@ GLASS_DEV void ragged_wave_one(float* __restrict__ Ag, float* __restrict__ Bg, i
     if (lane == 0) *info = inf;
 }
 
+// Sub-wave scope (classes 0 and 1, orders <= 16): four problems per
+// wavefront, one per 16-lane row; lane 16s + i owns row i of problem s.
+// Pivots and solved unknowns reach the other lanes of their row with DPP
+// row_newbcast, so the four problems never mix; rows past n are identity.
+// Inline asm operands get no compiler wait states, so each block starts with
+// the ones its inputs need (a VALU result read through DPP: two).
+template <int C>
+GLASS_DEV float row_bcast(float v) {
+    float r;
+    asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
+                 : "=v"(r)
+                 : "v"(v), "n"(C));
+    return r;
+}
+
+// v in lane J of every 16-lane row, `other` elsewhere (literal lane mask).
+template <int J>
+GLASS_DEV float rows_select(float other, float v) {
+    float r;
+    asm("s_nop 1\n\tv_cndmask_b32_e64 %0, %1, %2, %3"
+        : "=v"(r)
+        : "v"(other), "v"(v), "s"(0x0001000100010001ull << J));
+    return r;
+}
+
+template <int J, int K>
+struct SubUpd {
+    static GLASS_DEV void run(float (&a)[16], float R, float nv) {
+        fmac_bcast<K>(a[K], R, nv);
+        SubUpd<J, K + 1>::run(a, R, nv);
+    }
+};
+template <int J>
+struct SubUpd<J, 16> {
+    static GLASS_DEV void run(float (&)[16], float, float) {}
+};
+
+template <int J>
+struct SubStep {
+    static GLASS_DEV void run(float (&a)[16], int& info, float& myinv) {
+        const float d = row_bcast<J>(a[J]);
+        if (!(d > 0.f) && info == 0) info = J + 1;
+        const float inv = rsq(d);
+        const float v = a[J] * inv;  // in lane J of the row, a[J] is the pivot itself
+        myinv = rows_select<J>(myinv, inv);
+        a[J] = v;
+        float R[4];
+        replicate_rows<1>(v, R);  // wait states before the DPP reads of v
+        SubUpd<J, J + 1>::run(a, R[0], -v);
+        SubStep<J + 1>::run(a, info, myinv);
+    }
+};
+template <>
+struct SubStep<16> {
+    static GLASS_DEV void run(float (&)[16], int&, float&) {}
+};
+
+template <int K, int RG>
+struct SubFwd {
+    static GLASS_DEV void run(const float (&a)[16], float (&acc)[RG], float (&y)[RG], float myinv) {
+#pragma unroll
+        for (int c = 0; c < RG; ++c) {
+            const float yk = row_bcast<K>(acc[c] * myinv);
+            acc[c] = fmaf(-a[K], yk, acc[c]);
+            y[c] = rows_select<K>(y[c], yk);
+        }
+        SubFwd<K + 1, RG>::run(a, acc, y, myinv);
+    }
+};
+template <int RG>
+struct SubFwd<16, RG> {
+    static GLASS_DEV void run(const float (&)[16], float (&)[RG], float (&)[RG], float) {}
+};
+
+// Backward substitution L^T x = y; row K of the problem's L is read from its
+// 16 x 16 LDS block (lane i takes L_Ki).
+template <int K, int RG>
+struct SubBwd {
+    static GLASS_DEV void run(const float* sb, int i, float (&acc)[RG], float myinv) {
+        const float lki = i < K ? sb[K * 16 + i] : 0.f;
+#pragma unroll
+        for (int c = 0; c < RG; ++c) {
+            const float xk = row_bcast<K>(acc[c] * myinv);
+            acc[c] = rows_select<K>(fmaf(-lki, xk, acc[c]), xk);
+        }
+        SubBwd<K - 1, RG>::run(sb, i, acc, myinv);
+    }
+};
+template <int RG>
+struct SubBwd<-1, RG> {
+    static GLASS_DEV void run(const float*, int, float (&)[RG], float) {}
+};
+
+template <int RG>
+GLASS_DEV void sub_solve_cols(const float (&a)[16], const float* sb, float* Bg, int n, int r, int c0, int i,
+                              float myinv) {
+    float acc[RG], y[RG];
+#pragma unroll
+    for (int c = 0; c < RG; ++c) {
+        acc[c] = (i < n && c0 + c < r) ? Bg[i * r + c0 + c] : 0.f;
+        y[c] = 0.f;
+    }
+    SubFwd<0, RG>::run(a, acc, y, myinv);
+    SubBwd<15, RG>::run(sb, i, y, myinv);
+#pragma unroll
+    for (int c = 0; c < RG; ++c)
+        if (i < n && c0 + c < r) Bg[i * r + c0 + c] = y[c];
+}
+
+// Row s of the wavefront solves problem e (e < 0: an empty row, all identity).
+GLASS_DEV void ragged_subwave(float* A, float* B, const int64_t* offA, const int64_t* offB, int e, int n, int r,
+                              int32_t* info, float* sbuf, int lane) {
+    const int seg = lane >> 4, i = lane & 15;
+    const bool act = e >= 0;
+    const int nn = act ? n : 0;
+    float* Ag = act ? A + offA[e] : A;
+    float* Bg = act ? B + offB[e] : B;
+    float a[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) a[j] = (i < nn && j <= i) ? Ag[i * nn + j] : (j == i ? 1.f : 0.f);
+    int inf = 0;
+    float myinv = 1.f;
+    SubStep<0>::run(a, inf, myinv);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) a[j] = j <= i ? a[j] : 0.f;
+    float* sb = sbuf + seg * 256;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        f4_t v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = a[4 * t + q];
+        *reinterpret_cast<f4_t*>(sb + i * 16 + 4 * t) = v;
+    }
+    wave_sync();
+    if (i < nn) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (j < nn) Ag[i * nn + j] = a[j];
+    }
+    if (act && i == 0) info[e] = inf;
+    // column groups up to the largest right-hand-side count of the four rows
+    // (uniform, so every DPP step runs in all lanes); a failed or empty row
+    // solves zero columns and stores nothing
+    const int reff = (act && inf == 0) ? r : 0;
+    int rmax = max(max(__builtin_amdgcn_readlane(reff, 0), __builtin_amdgcn_readlane(reff, 16)),
+                   max(__builtin_amdgcn_readlane(reff, 32), __builtin_amdgcn_readlane(reff, 48)));
+    for (int c0 = 0; c0 < rmax;) {
+        const int left = rmax - c0;
+        if (left >= 5) {
+            sub_solve_cols<8>(a, sb, Bg, nn, reff, c0, i, myinv);
+            c0 += 8;
+        } else if (left >= 2) {
+            sub_solve_cols<4>(a, sb, Bg, nn, reff, c0, i, myinv);
+            c0 += 4;
+        } else {
+            sub_solve_cols<1>(a, sb, Bg, nn, reff, c0, i, myinv);
+            c0 += 1;
+        }
+    }
+}
+
 // One work item per wavefront: wavefront g of the launch takes item g of the
 // class-sorted work list (largest class first) and exits; waves past the
 // list's end exit at once.  There is no work-queue loop: a loop drawing items
@@ -182,7 +349,7 @@ __global__ void __launch_bounds__(256) ragged_solve(const int32_t* __restrict__ 
                                                     const int64_t* __restrict__ offB, float* A, float* B,
                                                     int32_t* info, const int32_t* __restrict__ perm,
                                                     const int32_t* __restrict__ meta, RaggedScopes scopes) {
-    __shared__ float chunk[4][8 * 64];
+    __shared__ float chunk[4][1024];  // per wavefront: 8 rows of 64 (wave) or four 16 x 16 blocks (sub-wave)
     const int lane = threadIdx.x & 63, w = wave_index();
     const int item = blockIdx.x * 4 + w;
     if (item >= meta[3 * kClasses]) return;
@@ -190,11 +357,26 @@ __global__ void __launch_bounds__(256) ragged_solve(const int32_t* __restrict__ 
 #pragma unroll
     for (int c = 0; c < kClasses; ++c) {
         const int cnt = meta[c], ib = meta[2 * kClasses + c];
-        const int nit = scopes.s[c] == GLASS_SCOPE_THREAD ? (cnt + 63) / 64 : cnt;
+        const int nit = items_of(scopes.s[c], cnt);
         if (cnt > 0 && item >= ib && item < ib + nit) k = c;
     }
     const int rel = item - meta[2 * kClasses + k];
     const int cbase = meta[kClasses + k];
+    if (scopes.s[k] == kScopeSubwave) {  // classes 0 and 1 only (checked by the caller)
+        const int q = rel * 4 + (lane >> 4);
+        int e = -1, n = 0, r = 0;
+        if (q < meta[k]) {
+            e = perm[cbase + q];
+            n = nvec[e];
+            r = rvec[e];
+            if (n < 1 || n > 16 || r < 1 || r > kMaxN) {
+                if ((lane & 15) == 0) info[e] = -1;
+                e = -1;
+            }
+        }
+        ragged_subwave(A, B, offA, offB, e, n, r, info, chunk[w], lane);
+        return;
+    }
     if (scopes.s[k] == GLASS_SCOPE_THREAD) {
         const int q = rel * 64 + lane;
         if (q < meta[k]) {

@@ -29,11 +29,12 @@ LIB_PATH = os.path.join(_PKG, "libglass.so")
 
 OK, ERR_INVALID_VALUE, ERR_UNSUPPORTED, ERR_INFEASIBLE_PLACEMENT, ERR_LAUNCH = 0, -1, -2, -3, -4
 OP_GEMM, OP_GEMV, OP_POTRF, OP_POTRS, OP_POSV, OP_TRSV, OP_SE3_COMPOSE, OP_SE3_INVERSE, OP_POSV_ADJOINT = range(9)
-SCOPE_THREAD, SCOPE_WAVE, SCOPE_WORKGROUP = 0, 1, 2
+SCOPE_THREAD, SCOPE_WAVE, SCOPE_WORKGROUP, SCOPE_SUBWAVE = 0, 1, 2, 3
 OPS = {"gemm": OP_GEMM, "gemv": OP_GEMV, "potrf": OP_POTRF, "potrs": OP_POTRS, "posv": OP_POSV,
        "trsv": OP_TRSV, "se3_compose": OP_SE3_COMPOSE, "se3_inverse": OP_SE3_INVERSE}
 SCOPES = {"thread": SCOPE_THREAD, "wave": SCOPE_WAVE, "workgroup": SCOPE_WORKGROUP}
 SCOPE_NAMES = {v: k for k, v in SCOPES.items()}
+RAGGED_SCOPES = dict(SCOPES, subwave=SCOPE_SUBWAVE)
 
 
 class Placement(ctypes.Structure):
@@ -72,6 +73,7 @@ _SIGS = {
     "glass_posv_ragged_perm_offset": [_i],
     "glass_riccati_gain_batched": [_i, _i, _i, _p, _p, _p, _p, _p, _p, _PP, _p],
     "glass_riccati_feasible": [_i, _i, _i],
+    "glass_ragged_table_provenance": [],
     "glass_last_launch_error": [],
     "glass_hip_error_name": [_i],
     "glass_mlp_num_params": [_i],
@@ -88,7 +90,8 @@ for _name, _args in _SIGS.items():
     _fn = getattr(_lib, _name)
     _fn.argtypes = _args
     _fn.restype = ctypes.c_char_p if _name in ("glass_table_provenance", "glass_status_string",
-                                               "glass_hip_error_name") else ctypes.c_int
+                                               "glass_hip_error_name", "glass_ragged_table_provenance") \
+        else ctypes.c_int
     if _name in ("glass_posv_ragged_workspace_size", "glass_posv_ragged_perm_offset", "glass_mlp_num_params",
                  "glass_mlp_backward_workspace_size"):
         _fn.restype = ctypes.c_size_t
@@ -170,7 +173,7 @@ def glass_posv_ragged(count, n, nrhs, offA, offB, A, B, info, workspace, workspa
                       stream=None) -> int:
     cs = None
     if class_scope is not None:
-        vals = [SCOPES[v] if isinstance(v, str) else int(v) for v in class_scope]
+        vals = [RAGGED_SCOPES[v] if isinstance(v, str) else int(v) for v in class_scope]
         cs = (ctypes.c_int32 * 8)(*vals)
     return _lib.glass_posv_ragged(count, _ptr(n), _ptr(nrhs), _ptr(offA), _ptr(offB), _ptr(A), _ptr(B), _ptr(info),
                                   _ptr(workspace), workspace_bytes, cs, _stream(stream))
@@ -191,6 +194,10 @@ def glass_riccati_gain_batched(nx, nu, batch, A, B, P, R, K, info=None, force=No
 
 def glass_riccati_feasible(nx, nu, pack) -> int:
     return _lib.glass_riccati_feasible(nx, nu, pack)
+
+
+def glass_ragged_table_provenance() -> str:
+    return _lib.glass_ragged_table_provenance().decode()
 
 
 def glass_last_launch_error() -> int:

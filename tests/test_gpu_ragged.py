@@ -22,7 +22,8 @@ def per_problem_err(case, B_gpu, B_ref, idx):
     return worst
 
 
-@pytest.mark.parametrize("scopes", [None, ["wave"] * 8, ["thread"] + ["wave"] * 7])
+@pytest.mark.parametrize("scopes", [None, ["wave"] * 8, ["thread"] + ["wave"] * 7,
+                                    ["subwave", "subwave"] + ["wave"] * 6, ["thread", "subwave"] + ["wave"] * 6])
 @pytest.mark.parametrize("count,seed", [(1, 3), (77, 4), (2500, 5)])
 def test_ragged_parity(scopes, count, seed):
     import torch

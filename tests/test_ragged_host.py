@@ -53,3 +53,8 @@ def test_ragged_validation_without_device():
         glass.ERR_INFEASIBLE_PLACEMENT
     assert glass.glass_posv_ragged(10, F, F, F, F, F, F, F, F, w, class_scope=[7] * 8, stream=0) == \
         glass.ERR_INVALID_VALUE
+    bad = ["wave"] * 8
+    bad[2] = "subwave"   # sub-wave rows hold orders up to 16 (classes 0 and 1)
+    assert glass.glass_posv_ragged(10, F, F, F, F, F, F, F, F, w, class_scope=bad, stream=0) == \
+        glass.ERR_INFEASIBLE_PLACEMENT
+    assert glass.glass_ragged_table_provenance().startswith("gfx950")
