@@ -140,10 +140,38 @@ __global__ void __launch_bounds__(256) gemm_small_wg(int m, int n, int k, int ba
 // TA / TBT select transposed operands (A stored k x m, B stored n x k); the
 // transposed A fragment is read element-wise (consecutive lanes take
 // consecutive rows i, so the loads stay coalesced).
-template <int TB, bool VEC, int JJ, bool TA = false, bool TBT = false>
+// Wave scope with a staged output (STG: n % 4 == 0, C 16-byte aligned): all
+// column tiles of one 16-row block are accumulated, written to LDS in the
+// MFMA output layout and stored back as whole rows with 16-byte stores (the
+// output layout alone writes 64-byte half lines).
+template <int TB, bool TA, bool TBT>
+GLASS_DEV void mfma_store_block(int m, int n, float alpha, float beta, float* __restrict__ Cg, const float* stg,
+                                int it, int lane) {
+    const int n4 = n >> 2;
+    const int rows = min(16, m - it * 16);
+    for (int g = lane; g < 16 * n4; g += 64) {
+        const int rr = g / n4, c4 = g - rr * n4;
+        if (rr < rows) {
+            const f4_t v = *reinterpret_cast<const f4_t*>(stg + rr * kGemmStageStride + 4 * c4);
+            f4_t* dst = reinterpret_cast<f4_t*>(Cg + (size_t)(it * 16 + rr) * n) + c4;
+            f4_t out;
+            if (beta != 0.f) {
+                const f4_t c0 = *dst;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) out[e] = fmaf(beta, c0[e], alpha * v[e]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) out[e] = alpha * v[e];
+            }
+            *dst = out;
+        }
+    }
+}
+
+template <int TB, bool VEC, int JJ, bool TA = false, bool TBT = false, bool STG = false>
 GLASS_DEV void mfma_problem(int m, int n, int k, float alpha, const float* __restrict__ Ag,
                             const float* __restrict__ Bg, float beta, float* __restrict__ Cg, int lane, int jt0,
-                            int jstep) {
+                            int jstep, float* stg = nullptr) {
     const int q = lane >> 4, r = lane & 15;
     const int MT = (m + 15) >> 4, NT = (n + 15) >> 4, KT = (k + 15) >> 4;
     float af[TB][TB][4];
@@ -180,6 +208,37 @@ GLASS_DEV void mfma_problem(int m, int n, int k, float alpha, const float* __res
                 bf[jj][kb][c] = (kb < KT && kk < k && j < n) ? (TBT ? Bg[j * k + kk] : Bg[kk * n + j]) : 0.f;
             }
     }
+    if (STG) {
+#pragma unroll
+        for (int it = 0; it < TB; ++it) {
+            if (it < MT) {
+                floatx4 acc[JJ];
+#pragma unroll
+                for (int jj = 0; jj < JJ; ++jj) {
+                    acc[jj] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int kb = 0; kb < TB; ++kb) {
+                        if (kb < KT) {
+#pragma unroll
+                            for (int c = 0; c < 4; ++c)
+                                acc[jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[it][kb][c], bf[jj][kb][c], acc[jj],
+                                                                               0, 0, 0);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int jj = 0; jj < JJ; ++jj)
+                    if (jj < NT) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) stg[(4 * q + e) * kGemmStageStride + jj * 16 + r] = acc[jj][e];
+                    }
+                wave_sync();
+                mfma_store_block<TB, TA, TBT>(m, n, alpha, beta, Cg, stg, it, lane);
+                wave_sync();
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int jj = 0; jj < JJ; ++jj) {
         const int jt = jt0 + jj * jstep;
@@ -214,15 +273,16 @@ GLASS_DEV void mfma_problem(int m, int n, int k, float alpha, const float* __res
     }
 }
 
-template <int TB, bool VEC, bool TA = false, bool TBT = false>
+template <int TB, bool VEC, bool TA = false, bool TBT = false, bool STG = false>
 __global__ void __launch_bounds__(512) gemm_mfma_wave(int m, int n, int k, int batch, float alpha,
                                                       const float* __restrict__ A, const float* __restrict__ B,
                                                       float beta, float* __restrict__ C) {
+    extern __shared__ float lds[];
     const int w = wave_index(), lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
-    mfma_problem<TB, VEC, TB, TA, TBT>(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lane, 0,
-                                       1);
+    mfma_problem<TB, VEC, TB, TA, TBT, STG>(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lane,
+                                            0, 1, lds + (size_t)w * 16 * kGemmStageStride);
 }
 
 template <int TB, bool VEC, bool TA = false, bool TBT = false>
@@ -260,14 +320,22 @@ int launch_gemm_t(const Shape& sh, const Geometry& g, int batch, float alpha, co
     const int tb = (mx + 15) / 16;
     const bool vec = !TA && (k % 4 == 0) && ((uintptr_t)A % 16 == 0);
     if (g.scope == GLASS_SCOPE_WAVE) {
-#define X(TB)                                                                                                  \
-    case TB:                                                                                                   \
-        if (vec)                                                                                               \
-            hipLaunchKernelGGL((gemm_mfma_wave<TB, true, TA, TBT>), grid, block, 0, st, m, n, k, batch, alpha, \
-                               A, B, beta, C);                                                                 \
-        else                                                                                                   \
-            hipLaunchKernelGGL((gemm_mfma_wave<TB, false, TA, TBT>), grid, block, 0, st, m, n, k, batch,       \
-                               alpha, A, B, beta, C);                                                          \
+        // staged full-row stores when C rows are whole 16-byte units
+        const bool stg = (n % 4 == 0) && ((uintptr_t)C % 16 == 0);
+#define X(TB)                                                                                                   \
+    case TB:                                                                                                    \
+        if (vec && stg)                                                                                         \
+            hipLaunchKernelGGL((gemm_mfma_wave<TB, true, TA, TBT, true>), grid, block, g.lds_bytes, st, m, n, k, \
+                               batch, alpha, A, B, beta, C);                                                    \
+        else if (stg)                                                                                           \
+            hipLaunchKernelGGL((gemm_mfma_wave<TB, false, TA, TBT, true>), grid, block, g.lds_bytes, st, m, n,  \
+                               k, batch, alpha, A, B, beta, C);                                                 \
+        else if (vec)                                                                                           \
+            hipLaunchKernelGGL((gemm_mfma_wave<TB, true, TA, TBT>), grid, block, g.lds_bytes, st, m, n, k,      \
+                               batch, alpha, A, B, beta, C);                                                    \
+        else                                                                                                    \
+            hipLaunchKernelGGL((gemm_mfma_wave<TB, false, TA, TBT>), grid, block, g.lds_bytes, st, m, n, k,     \
+                               batch, alpha, A, B, beta, C);                                                    \
         break;
         switch (tb) {
             X(1) X(2) X(3) X(4)

@@ -89,8 +89,13 @@ inline int bucket8_host(int n) { return ((n + 7) / 8) * 8; }
 // LDS floats of one wavefront of the wave scope.  The Cholesky family keeps
 // rows in VGPRs and needs only an 8-row chunk buffer for its coalesced
 // stores and backward substitution.
+constexpr int kGemmStageStride = 68;  // LDS row stride of the staged 16-row output block of the MFMA GEMM
+
 inline size_t wave_region_floats(const Shape& s) {
     switch (s.op) {
+    case GLASS_OP_GEMM:
+        // MFMA path: one 16-row block of C staged for full-row stores
+        return gemm_uses_mfma(s) ? (size_t)16 * kGemmStageStride : region_floats(s);
     case GLASS_OP_POTRF:
     case GLASS_OP_POTRS:
     case GLASS_OP_POSV:
