@@ -71,8 +71,10 @@ typedef enum {
     GLASS_SCOPE_THREAD = 0,    /* one problem per lane                       */
     GLASS_SCOPE_WAVE = 1,      /* one problem per 64-lane wavefront          */
     GLASS_SCOPE_WORKGROUP = 2, /* one problem per workgroup at a time        */
-    GLASS_SCOPE_SUBWAVE = 3    /* ragged batches only: four problems per
-                                  wavefront, one per 16-lane row (n <= 16)  */
+    GLASS_SCOPE_SUBWAVE = 3    /* 64/SEG problems per wavefront, one per
+                                  SEG-lane segment: SEG = 16 for n <= 16,
+                                  32 for 16 < n <= 32.  POTRF, POTRS, POSV,
+                                  TRSV and the ragged solve only            */
 } glass_scope_t;
 
 /* A placement (Sec. III-A, Sec. IV-C).  `pack` P in {1,2,4,8} counts the
@@ -80,7 +82,8 @@ typedef enum {
  *   thread    : workgroup of 64P lanes, 64P problems per workgroup;
  *   wave      : workgroup of P wavefronts, P problems (one per wavefront);
  *   workgroup : workgroup of T(n) = 64*min(4, ceil(n/16)) lanes that solves
- *               P problems one after the other.
+ *               P problems one after the other;
+ *   subwave   : workgroup of P wavefronts, P*64/SEG problems.
  * wg_threads and problems_per_wg are outputs (what a launch uses); as input
  * only scope and pack are read. */
 typedef struct {

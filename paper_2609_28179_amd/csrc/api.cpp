@@ -47,7 +47,7 @@ void table_lookup(glass_op_t op, int n, long long batch, int* scope, int* pack) 
 
 bool valid_force(const glass_placement_t* f) {
     if (!f) return true;
-    if (f->scope < GLASS_SCOPE_THREAD || f->scope > GLASS_SCOPE_WORKGROUP) return false;
+    if (f->scope < GLASS_SCOPE_THREAD || f->scope > GLASS_SCOPE_SUBWAVE) return false;
     return f->pack == 1 || f->pack == 2 || f->pack == 4 || f->pack == 8;
 }
 
@@ -325,7 +325,7 @@ glass_status_t glass_query_placement(glass_op_t op, int n, int batch, glass_plac
 
 int glass_placement_feasible(glass_op_t op, int n, int nrhs, int scope, int pack) {
     if ((int)op < GLASS_OP_GEMM || (int)op > GLASS_OP_POSV_ADJOINT) return GLASS_ERR_INVALID_VALUE;
-    if (scope < GLASS_SCOPE_THREAD || scope > GLASS_SCOPE_WORKGROUP) return GLASS_ERR_INVALID_VALUE;
+    if (scope < GLASS_SCOPE_THREAD || scope > GLASS_SCOPE_SUBWAVE) return GLASS_ERR_INVALID_VALUE;
     if (!is_se3(op) && !size_ok(n)) return GLASS_ERR_UNSUPPORTED;
     if (!size_ok(nrhs)) return GLASS_ERR_UNSUPPORTED;
     const int order = is_se3(op) ? 4 : n;

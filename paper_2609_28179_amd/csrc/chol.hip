@@ -356,6 +356,7 @@ inline int finish() { return (int)hipGetLastError(); }
 }  // namespace
 
 int launch_potrf(const Shape& sh, const Geometry& g, int batch, float* A, int32_t* info, void* stream) {
+    if (g.scope == GLASS_SCOPE_SUBWAVE) return launch_chol_subwave(sh, g, batch, A, nullptr, info, stream);
     (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
     hipStream_t st = (hipStream_t)stream;
     const int n = sh.n;
@@ -384,6 +385,7 @@ int launch_potrf(const Shape& sh, const Geometry& g, int batch, float* A, int32_
 }
 
 int launch_posv(const Shape& sh, const Geometry& g, int batch, float* A, float* B, int32_t* info, void* stream) {
+    if (g.scope == GLASS_SCOPE_SUBWAVE) return launch_chol_subwave(sh, g, batch, A, B, info, stream);
     (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
     hipStream_t st = (hipStream_t)stream;
     const int n = sh.n, r = sh.nrhs;
@@ -417,6 +419,7 @@ int launch_posv(const Shape& sh, const Geometry& g, int batch, float* A, float* 
 }
 
 int launch_potrs(const Shape& sh, const Geometry& g, int batch, const float* L, float* B, void* stream) {
+    if (g.scope == GLASS_SCOPE_SUBWAVE) return launch_chol_subwave(sh, g, batch, const_cast<float*>(L), B, nullptr, stream);
     (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
     hipStream_t st = (hipStream_t)stream;
     const int n = sh.n, r = sh.nrhs;
@@ -450,6 +453,7 @@ int launch_potrs(const Shape& sh, const Geometry& g, int batch, const float* L, 
 }
 
 int launch_trsv(const Shape& sh, const Geometry& g, int batch, const float* L, float* x, void* stream) {
+    if (g.scope == GLASS_SCOPE_SUBWAVE) return launch_chol_subwave(sh, g, batch, const_cast<float*>(L), x, nullptr, stream);
     (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
     hipStream_t st = (hipStream_t)stream;
     const int n = sh.n, tr = sh.trans;

@@ -107,6 +107,20 @@ inline size_t wave_region_floats(const Shape& s) {
     }
 }
 
+// Sub-wave scope of the batched Cholesky family (orders <= 32): 64 / SEG
+// problems per wavefront, one per SEG-lane segment, SEG = 16 up to order 16
+// and 32 above.  LDS per wavefront: one block of L per segment, rows padded
+// to NB + 4 floats (NB = order rounded up to 8).
+constexpr int kSubwaveMaxN = 32;
+inline int subwave_seg(int n) { return n <= 16 ? 16 : 32; }
+inline size_t subwave_region_floats(int n) {
+    const int nb = bucket8_host(n);
+    return (size_t)(kWave / subwave_seg(n)) * nb * (nb + 4);
+}
+inline bool subwave_op(glass_op_t op) {
+    return op == GLASS_OP_POTRF || op == GLASS_OP_POSV || op == GLASS_OP_POTRS || op == GLASS_OP_TRSV;
+}
+
 // LDS floats of a thread-scope workgroup of `t` lanes.
 inline size_t thread_lds_floats(const Shape& s, int t) {
     const int n = s.n;
@@ -163,6 +177,11 @@ inline bool make_geometry(const Shape& s, int scope, int pack, long long batch, 
         out.threads = kWave * pack;
         out.problems_per_wg = pack;
         out.lds_bytes = wave_region_floats(s) * pack * sizeof(float);
+    } else if (scope == GLASS_SCOPE_SUBWAVE) {
+        if (!subwave_op(s.op) || s.n > kSubwaveMaxN) return false;
+        out.threads = kWave * pack;
+        out.problems_per_wg = pack * (kWave / subwave_seg(s.n));
+        out.lds_bytes = subwave_region_floats(s.n) * pack * sizeof(float);
     } else if (scope == GLASS_SCOPE_WORKGROUP) {
         if (s.op == GLASS_OP_POSV_ADJOINT) return false;
         int order = s.n;
@@ -194,6 +213,10 @@ int launch_potrs(const Shape& s, const Geometry& g, int batch, const float* L, f
 int launch_posv(const Shape& s, const Geometry& g, int batch, float* A, float* B, int32_t* info,
                 void* stream);
 int launch_trsv(const Shape& s, const Geometry& g, int batch, const float* L, float* x, void* stream);
+// Sub-wave scope of POTRF / POSV / POTRS / TRSV (A is L for the solves; B is
+// x for TRSV; info may be NULL).
+int launch_chol_subwave(const Shape& s, const Geometry& g, int batch, float* A, float* B, int32_t* info,
+                        void* stream);
 int launch_se3(const Shape& s, const Geometry& g, int batch, const float* Ta, const float* Tb,
                float* Tout, void* stream);
 // Placement (scope) of each of the eight ragged size classes (orders 8k+1 ..

@@ -1,0 +1,288 @@
+// subwave.hip -- sub-wave scope of the batched Cholesky family: 64 / SEG
+// problems per wavefront, one per SEG-lane segment (SEG = 16 for orders up to
+// 16, 32 for orders up to 32; Sec. IV-C packing below the warp granule).
+//
+// A problem of order n <= SEG uses only n rows of a wavefront at wave scope;
+// here every segment runs its own problem with lane i of the segment owning
+// row i.  Broadcasts stay inside a segment: DPP row_newbcast reaches the 16
+// lanes of a row, and for SEG = 32 v_permlane16_swap first replicates each
+// 16-lane row across its 32-lane half (replicate_rows<2>), so the two halves
+// of the wavefront never mix.  The per-segment pivot, 1 / L_ii and the solved
+// unknowns use the same broadcast and a literal lane mask that repeats every
+// SEG lanes.  The backward substitution reads L from a per-segment LDS block;
+// L leaves through that block as one contiguous copy of the wavefront's
+// problems (they are adjacent in the batch).
+#include "device_common.hpp"
+#include "glass_internal.hpp"
+#include "chol_device.hpp"
+
+namespace glass {
+namespace {
+
+template <int SEG>
+constexpr unsigned long long seg_mask() {
+    return SEG == 16 ? 0x0001000100010001ull : 0x0000000100000001ull;
+}
+
+// Lane K of every segment, broadcast to its segment.  Inline asm gets no
+// compiler wait states: the DPP read is preceded by s_nop 1.
+template <int SEG, int K>
+GLASS_DEV float seg_bcast(float v) {
+    float src = v;
+    if (SEG == 32) {
+        float R[4];
+        replicate_rows<2>(v, R);  // ends with the wait states a DPP read needs
+        src = R[K / 16];
+    }
+    float r;
+    asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
+                 : "=v"(r)
+                 : "v"(src), "n"(K % 16));
+    return r;
+}
+
+// v in lane K of every segment, `other` elsewhere (literal mask; s_nop 1 covers
+// a transcendental or DPP result read as an operand).
+template <int SEG, int K>
+GLASS_DEV float seg_select(float other, float v) {
+    float r;
+    asm("s_nop 1\n\tv_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(other), "v"(v), "s"(seg_mask<SEG>() << K));
+    return r;
+}
+
+template <int SEG, int NB, int J>
+struct SegStep {
+    static GLASS_DEV void run(float (&a)[NB], int& info, float& myinv) {
+        const float d = seg_bcast<SEG, J>(a[J]);
+        if (!(d > 0.f) && info == 0) info = J + 1;
+        const float inv = rsq(d);
+        const float v = a[J] * inv;  // in lane J of the segment, a[J] is the pivot itself
+        myinv = seg_select<SEG, J>(myinv, inv);
+        a[J] = v;
+        float R[4];
+        replicate_rows<SEG == 16 ? 1 : 2>(v, R);
+        WaveUpd<NB, J, J + 1>::run(a, R, -v);
+        SegStep<SEG, NB, J + 1>::run(a, info, myinv);
+    }
+};
+template <int SEG, int NB>
+struct SegStep<SEG, NB, NB> {
+    static GLASS_DEV void run(float (&)[NB], int&, float&) {}
+};
+
+template <int SEG, int NB, int K, int RG>
+struct SegFwd {
+    static GLASS_DEV void run(const float (&a)[NB], float (&acc)[RG], float (&y)[RG], float myinv) {
+#pragma unroll
+        for (int c = 0; c < RG; ++c) {
+            const float yk = seg_bcast<SEG, K>(acc[c] * myinv);
+            acc[c] = fmaf(-a[K], yk, acc[c]);
+            y[c] = seg_select<SEG, K>(y[c], yk);
+        }
+        SegFwd<SEG, NB, K + 1, RG>::run(a, acc, y, myinv);
+    }
+};
+template <int SEG, int NB, int RG>
+struct SegFwd<SEG, NB, NB, RG> {
+    static GLASS_DEV void run(const float (&)[NB], float (&)[RG], float (&)[RG], float) {}
+};
+
+// Backward substitution L^T x = y; row K of the segment's L is read from its
+// LDS block (row stride NB + 4; lane i takes L_Ki).
+template <int SEG, int NB, int K, int RG>
+struct SegBwd {
+    static GLASS_DEV void run(const float* sb, int i, float (&acc)[RG], float myinv) {
+        const float lki = i < K ? sb[K * (NB + 4) + i] : 0.f;
+#pragma unroll
+        for (int c = 0; c < RG; ++c) {
+            const float xk = seg_bcast<SEG, K>(acc[c] * myinv);
+            acc[c] = seg_select<SEG, K>(fmaf(-lki, xk, acc[c]), xk);
+        }
+        SegBwd<SEG, NB, K - 1, RG>::run(sb, i, acc, myinv);
+    }
+};
+template <int SEG, int NB, int RG>
+struct SegBwd<SEG, NB, -1, RG> {
+    static GLASS_DEV void run(const float*, int, float (&)[RG], float) {}
+};
+
+// Row i of segment s's problem (lane 16s + i or 32s + i) from the wavefront's
+// np adjacent problems starting at base.  MASK and the padding follow
+// rows_load_lower (identity rows for a factorization, zero rows otherwise;
+// a segment past np holds only padding rows).
+template <int NB, bool MASK>
+GLASS_DEV void seg_load_rows(float (&a)[NB], const float* base, int np, int n, int s, int i) {
+    const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(base, (uint32_t)(np * n * n) * 4u);
+    const bool row = s < np && i < n;
+    const int off = s * n * n + i * n;
+#pragma unroll
+    for (int t = 0; t < NB / 4; ++t) {
+        f4_t v = {0.f, 0.f, 0.f, 0.f};
+        if (row && 4 * t <= i) {
+            if (i * n + 4 * t + 4 <= n * n) {
+                v = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off * 4, t * 16, 0));
+            } else {  // last row of the problem: element-wise, never past the problem
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (4 * t + e < n)
+                        v[e] = __builtin_bit_cast(
+                            float, __builtin_amdgcn_raw_buffer_load_b32(rs, (off + 4 * t + e) * 4, 0, 0));
+            }
+        }
+        if (MASK) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) a[4 * t + e] = (4 * t + e <= i) ? v[e] : 0.f;
+        } else {
+            const bool dblk = !row && t == (i >> 2);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) a[4 * t + e] = (dblk && e == (i & 3)) ? 1.f : v[e];
+        }
+    }
+}
+
+// Rows of L (strict upper +0) into the segment's LDS block.
+template <int NB>
+GLASS_DEV void seg_rows_to_lds(const float (&a)[NB], float* sb, int i) {
+    if (i < NB) {
+#pragma unroll
+        for (int t = 0; t < NB / 4; ++t) {
+            f4_t v;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = a[4 * t + e];
+            *reinterpret_cast<f4_t*>(sb + i * (NB + 4) + 4 * t) = v;
+        }
+    }
+}
+
+// The wavefront's np problems of L (contiguous in global memory) from the
+// segment blocks: one flat, coalesced copy (16-byte stores when n % 4 == 0
+// and dst is 16-byte aligned, so four consecutive elements share a row).
+template <int NB>
+GLASS_DEV void seg_store_L(float* __restrict__ dst, const float* buf, int np, int n, bool vec, int lane) {
+    const int nn = n * n;
+    const FastDiv fnn = make_fastdiv((uint32_t)nn), fn = make_fastdiv((uint32_t)n);
+    if (vec) {
+        for (int q = lane; q < np * nn / 4; q += 64) {
+            const int g = 4 * q;
+            const int s = (int)fdiv((uint32_t)g, fnn), rem = g - s * nn;
+            const int i = (int)fdiv((uint32_t)rem, fn), j = rem - i * n;
+            reinterpret_cast<f4_t*>(dst)[q] =
+                *reinterpret_cast<const f4_t*>(buf + s * NB * (NB + 4) + i * (NB + 4) + j);
+        }
+        return;
+    }
+    for (int g = lane; g < np * nn; g += 64) {
+        const int s = (int)fdiv((uint32_t)g, fnn), rem = g - s * nn;
+        const int i = (int)fdiv((uint32_t)rem, fn), j = rem - i * n;
+        dst[g] = buf[s * NB * (NB + 4) + i * (NB + 4) + j];
+    }
+}
+
+template <int SEG, int NB, int RG>
+GLASS_DEV void seg_solve_cols(const float (&a)[NB], const float* sb, float* Bs, int n, int r, int c0, int i,
+                              float myinv, bool act, bool fwd, bool bwd) {
+    float acc[RG], y[RG];
+#pragma unroll
+    for (int c = 0; c < RG; ++c) {
+        acc[c] = (act && i < n && c0 + c < r) ? Bs[i * r + c0 + c] : 0.f;
+        y[c] = acc[c];
+    }
+    if (fwd) {
+#pragma unroll
+        for (int c = 0; c < RG; ++c) y[c] = 0.f;
+        SegFwd<SEG, NB, 0, RG>::run(a, acc, y, myinv);
+    }
+    if (bwd) SegBwd<SEG, NB, NB - 1, RG>::run(sb, i, y, myinv);
+#pragma unroll
+    for (int c = 0; c < RG; ++c)
+        if (act && i < n && c0 + c < r) Bs[i * r + c0 + c] = y[c];
+}
+
+// All nrhs columns of every segment in groups of 8 / 4 / 1 (nrhs is the
+// same for the whole batch, so the loop is uniform).
+template <int SEG, int NB>
+GLASS_DEV void seg_solve_all(const float (&a)[NB], const float* sb, float* Bs, int n, int r, int i, float myinv,
+                             bool act, bool fwd, bool bwd) {
+    for (int c0 = 0; c0 < r;) {
+        const int left = r - c0;
+        if (left >= 5) {
+            seg_solve_cols<SEG, NB, 8>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd);
+            c0 += 8;
+        } else if (left >= 2) {
+            seg_solve_cols<SEG, NB, 4>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd);
+            c0 += 4;
+        } else {
+            seg_solve_cols<SEG, NB, 1>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd);
+            c0 += 1;
+        }
+    }
+}
+
+// op: 0 POTRF, 1 POSV, 2 POTRS, 3 TRSV (trans selects forward 0 / backward 1).
+template <int SEG, int NB, int OP>
+__global__ void __launch_bounds__(512) chol_seg(int n, int nrhs, int trans, int batch, float* __restrict__ A,
+                                                float* __restrict__ B, int32_t* __restrict__ info, int region) {
+    extern __shared__ float lds[];
+    constexpr int PPW = 64 / SEG;
+    const int w = wave_index(), lane = threadIdx.x & 63;
+    const int s = lane / SEG, i = lane % SEG;
+    const long long p0 = ((long long)blockIdx.x * (blockDim.x >> 6) + w) * PPW;
+    if (p0 >= batch) return;
+    const int np = (int)min((long long)PPW, (long long)batch - p0);
+    const bool act = s < np;
+    float* buf = lds + (size_t)w * region;
+    float* sb = buf + s * NB * (NB + 4);
+    float* Ab = A + p0 * n * n;
+    float a[NB];
+    float myinv = 1.f;
+    int inf = 0;
+    if (OP <= 1) {
+        seg_load_rows<NB, false>(a, Ab, np, n, s, i);
+        SegStep<SEG, NB, 0>::run(a, inf, myinv);
+#pragma unroll
+        for (int k = 0; k < NB; ++k) a[k] = k <= i ? a[k] : 0.f;
+    } else {
+        seg_load_rows<NB, true>(a, Ab, np, n, s, i);
+        myinv = (act && i < n) ? 1.0f / Ab[s * n * n + i * n + i] : 1.f;
+    }
+    const bool fwd = OP != 3 || trans == 0, bwd = OP != 3 || trans == 1;
+    if (OP <= 1 || bwd) {
+        seg_rows_to_lds<NB>(a, sb, i);
+        wave_sync();
+    }
+    if (OP <= 1) {
+        seg_store_L<NB>(Ab, buf, np, n, (n & 3) == 0 && aligned16(A), lane);
+        if (info && act && i == 0) info[p0 + s] = inf;
+    }
+    if (OP == 0) return;
+    const int r = OP == 3 ? 1 : nrhs;
+    float* Bs = B + (p0 + s) * n * r;
+    const bool solve = act && inf == 0;  // a failed factorization leaves B untouched
+    seg_solve_all<SEG, NB>(a, sb, Bs, n, r, i, myinv, solve, fwd, bwd);
+}
+
+}  // namespace
+
+int launch_chol_subwave(const Shape& sh, const Geometry& g, int batch, float* A, float* B, int32_t* info,
+                        void* stream) {
+    (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
+    hipStream_t st = (hipStream_t)stream;
+    const int n = sh.n, nb = bucket8_host(n);
+    if (n > kSubwaveMaxN) return (int)hipErrorInvalidValue;
+    const int region = (int)subwave_region_floats(n);
+    dim3 grid((unsigned)g.grid), block(g.threads);
+    const int op = sh.op == GLASS_OP_POTRF ? 0 : sh.op == GLASS_OP_POSV ? 1 : sh.op == GLASS_OP_POTRS ? 2 : 3;
+#define SW(SEG, NB, OP)                                                                                         \
+    if (nb == NB && op == OP) {                                                                                 \
+        hipLaunchKernelGGL((chol_seg<SEG, NB, OP>), grid, block, g.lds_bytes, st, n, sh.nrhs, sh.trans, batch, A, \
+                           B, info, region);                                                                    \
+        return (int)hipGetLastError();                                                                          \
+    }
+#define SW_OPS(SEG, NB) SW(SEG, NB, 0) SW(SEG, NB, 1) SW(SEG, NB, 2) SW(SEG, NB, 3)
+    SW_OPS(16, 8) SW_OPS(16, 16) SW_OPS(32, 24) SW_OPS(32, 32)
+#undef SW_OPS
+#undef SW
+    return (int)hipErrorInvalidValue;
+}
+
+}  // namespace glass

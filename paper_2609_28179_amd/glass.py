@@ -32,9 +32,9 @@ OP_GEMM, OP_GEMV, OP_POTRF, OP_POTRS, OP_POSV, OP_TRSV, OP_SE3_COMPOSE, OP_SE3_I
 SCOPE_THREAD, SCOPE_WAVE, SCOPE_WORKGROUP, SCOPE_SUBWAVE = 0, 1, 2, 3
 OPS = {"gemm": OP_GEMM, "gemv": OP_GEMV, "potrf": OP_POTRF, "potrs": OP_POTRS, "posv": OP_POSV,
        "trsv": OP_TRSV, "se3_compose": OP_SE3_COMPOSE, "se3_inverse": OP_SE3_INVERSE}
-SCOPES = {"thread": SCOPE_THREAD, "wave": SCOPE_WAVE, "workgroup": SCOPE_WORKGROUP}
+SCOPES = {"thread": SCOPE_THREAD, "wave": SCOPE_WAVE, "workgroup": SCOPE_WORKGROUP, "subwave": SCOPE_SUBWAVE}
 SCOPE_NAMES = {v: k for k, v in SCOPES.items()}
-RAGGED_SCOPES = dict(SCOPES, subwave=SCOPE_SUBWAVE)
+RAGGED_SCOPES = SCOPES
 
 
 class Placement(ctypes.Structure):

@@ -75,7 +75,7 @@ def heldout_cells():
 
 def feasible_placements(glass, op: str, n: int, nrhs: int = 1):
     out = []
-    for scope in (glass.SCOPE_THREAD, glass.SCOPE_WAVE, glass.SCOPE_WORKGROUP):
+    for scope in (glass.SCOPE_THREAD, glass.SCOPE_WAVE, glass.SCOPE_WORKGROUP, glass.SCOPE_SUBWAVE):
         for p in PACKS:
             if glass.glass_placement_feasible(glass.OPS[op], n, nrhs, scope, p) == 1:
                 out.append((scope, p))

@@ -15,7 +15,7 @@ from paper_2609_28179_amd import inputs
 
 TOL = 1e-4
 PACKS = (1, 2, 4, 8)
-SCOPES = ("thread", "wave", "workgroup")
+SCOPES = ("thread", "wave", "workgroup", "subwave")
 
 
 def normwise(got, ref):

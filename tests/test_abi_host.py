@@ -129,7 +129,8 @@ def test_query_placement_matches_reference_lookup(glass):
                 if glass.glass_placement_feasible(op, n, 1, scope, pack) != 1:
                     scope, pack = glass.SCOPE_WAVE, 1
                 assert (got.scope, got.pack) == (scope, pack), (opname, n, b)
-                assert got.problems_per_wg == (64 * pack if scope == 0 else pack)
+                per = {0: 64 * pack, 3: pack * (4 if n <= 16 else 2)}.get(scope, pack)
+                assert got.problems_per_wg == per
     with pytest.raises(glass.GlassError):
         glass.glass_query_placement(glass.OP_POSV, 0, 16)
     with pytest.raises(glass.GlassError):
@@ -163,10 +164,26 @@ def test_feasibility_rule_shape(glass):
             assert g.glass_placement_feasible(op, n, 64, g.SCOPE_WAVE, 1) == 1
             assert g.glass_placement_feasible(op, n, 1, g.SCOPE_WORKGROUP, 8) == 1
             # monotone in n: feasible at n implies feasible below n
-            for scope in range(3):
+            for scope in range(4):
                 for pack in (1, 2, 4, 8):
                     if n > 1 and g.glass_placement_feasible(op, n, 1, scope, pack) == 1:
                         assert g.glass_placement_feasible(op, n - 1, 1, scope, pack) == 1
+
+
+def test_subwave_feasibility(glass):
+    g = glass
+    for op in ("potrf", "posv", "potrs", "trsv"):
+        for n in (1, 16, 17, 32):
+            assert g.glass_placement_feasible(g.OPS[op], n, 1, g.SCOPE_SUBWAVE, 1) == 1
+        assert g.glass_placement_feasible(g.OPS[op], 33, 1, g.SCOPE_SUBWAVE, 1) == 0
+        # 2 problems x 32 x 36 floats per wavefront: 8 wavefronts exceed 64 KiB
+        assert g.glass_placement_feasible(g.OPS[op], 32, 1, g.SCOPE_SUBWAVE, 4) == 1
+        assert g.glass_placement_feasible(g.OPS[op], 32, 1, g.SCOPE_SUBWAVE, 8) == 0
+        assert g.glass_placement_feasible(g.OPS[op], 16, 1, g.SCOPE_SUBWAVE, 8) == 1
+    for op in ("gemm", "gemv", "se3_compose", "se3_inverse"):
+        assert g.glass_placement_feasible(g.OPS[op], 8, 1, g.SCOPE_SUBWAVE, 1) == 0
+    assert g.glass_placement_feasible(g.OP_POSV_ADJOINT, 8, 1, g.SCOPE_SUBWAVE, 1) == 0
+    assert g.glass_placement_feasible(g.OP_POSV, 8, 1, 4, 1) == g.ERR_INVALID_VALUE
 
 
 def test_single_hip_runtime_in_process():

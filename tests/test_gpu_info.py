@@ -1,0 +1,89 @@
+"""GPU: failed factorizations inside a batch, at every scope.
+
+Problems whose matrix is clearly indefinite at a planted column k (A_kk set
+to -100, far below any rounding margin) must report info = k + 1 exactly,
+and every other problem of the batch -- in particular its neighbours that
+share a wavefront at sub-wave scope -- must still match the oracle: a NaN
+born in one problem may not leak into another.  B of a failed problem is
+unspecified by the contract and is not compared.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import TOL, guarded, guards_intact, normwise
+from paper_2609_28179_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+# planted failures: (problem, column); neighbours 2..5 share one sub-wave
+# wavefront at orders <= 16 (four per wavefront), 32/33 at orders <= 32.
+PLANTS = ((2, 0), (3, 5), (5, 1), (32, 3), (66, 2))
+BATCH = 67
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2609_28179_amd import glass
+    assert torch.cuda.is_available()
+    return glass, torch
+
+
+def _planted(n, seed):
+    rng = np.random.default_rng(seed)
+    A = inputs.spd(rng, BATCH, n)
+    B = inputs.uniform(rng, (BATCH, n, 2))
+    want = np.zeros(BATCH, np.int32)
+    for p, k in PLANTS:
+        k = min(k, n - 1)
+        A[p, k, k] = -100.0
+        want[p] = k + 1
+    return A, B, want
+
+
+@pytest.mark.parametrize("scope", ["thread", "wave", "workgroup", "subwave"])
+@pytest.mark.parametrize("op", ["potrf", "posv"])
+def test_planted_failures(env, op, scope):
+    glass, torch = env
+    fails = []
+    for n in (1, 3, 8, 13, 16, 17, 24, 32, 40):
+        if glass.glass_placement_feasible(glass.OPS[op], n, 2, glass.SCOPES[scope], 1) != 1:
+            continue
+        print(f"{op} n={n} {scope} planted failures", flush=True)
+        sys.stdout.flush()
+        A, B, want = _planted(n, 1000 + n)
+        if op == "potrf":
+            L_ref, info_ref = oracle.potrf(A)
+        else:
+            L_ref, X_ref, info_ref = oracle.posv(A, B)
+        assert np.array_equal(info_ref, want), "oracle must report the planted pivots"
+        Af, Ad = guarded(torch, A, "cuda:0")
+        Bf, Bd = guarded(torch, B, "cuda:0")
+        info = torch.full((BATCH,), -7, dtype=torch.int32, device="cuda:0")
+        if op == "potrf":
+            st = glass.glass_potrf_batched(n, BATCH, Ad, info, (scope, 1))
+        else:
+            st = glass.glass_posv_batched(n, 2, BATCH, Ad, Bd, info, (scope, 1))
+        torch.cuda.synchronize()
+        label = f"{op} n={n} {scope}"
+        if st != 0:
+            fails.append(f"{label}: status {st}")
+            continue
+        got = info.cpu().numpy()
+        if not np.array_equal(got, want):
+            fails.append(f"{label}: info {got[want != 0]} vs {want[want != 0]}, "
+                         f"{int(np.count_nonzero(got[want == 0]))} spurious")
+        ok = want == 0
+        err = normwise(np.tril(Ad.cpu().numpy())[ok], L_ref[ok]).max()
+        if op == "posv":
+            err = max(err, normwise(Bd.cpu().numpy()[ok], X_ref[ok]).max())
+        if not err <= TOL:
+            fails.append(f"{label}: healthy problems err {err:.3e}")
+        if not (guards_intact(Af) and guards_intact(Bf)):
+            fails.append(f"{label}: guard band written")
+    assert not fails, "\n".join(fails)

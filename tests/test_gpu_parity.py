@@ -48,7 +48,7 @@ def _check(res, label, fails):
             fails.append(f"{label}: {key} failed")
 
 
-@pytest.mark.parametrize("scope", ["thread", "wave", "workgroup"])
+@pytest.mark.parametrize("scope", ["thread", "wave", "workgroup", "subwave"])
 @pytest.mark.parametrize("op", OPS_N)
 def test_parity_square_ops(env, op, scope):
     glass, torch = env
@@ -71,7 +71,7 @@ def test_parity_square_ops(env, op, scope):
     assert not fails, "\n".join(fails[:40])
 
 
-@pytest.mark.parametrize("scope", ["thread", "wave", "workgroup"])
+@pytest.mark.parametrize("scope", ["thread", "wave", "workgroup", "subwave"])
 @pytest.mark.parametrize("op", ["se3_compose", "se3_inverse"])
 def test_parity_se3(env, op, scope):
     glass, torch = env
@@ -90,7 +90,7 @@ def test_parity_se3(env, op, scope):
     assert not fails, "\n".join(fails)
 
 
-@pytest.mark.parametrize("scope", ["wave", "workgroup", "thread"])
+@pytest.mark.parametrize("scope", ["wave", "workgroup", "thread", "subwave"])
 @pytest.mark.parametrize("op,nrhs", [("posv", 2), ("posv", 3), ("posv", 4), ("posv", 8), ("posv", 9), ("posv", 12),
                                      ("potrs", 5), ("potrs", 12), ("potrs", 64), ("posv", 64)])
 def test_parity_multi_rhs(env, op, nrhs, scope):
@@ -107,7 +107,7 @@ def test_parity_multi_rhs(env, op, nrhs, scope):
     assert not fails, "\n".join(fails)
 
 
-@pytest.mark.parametrize("scope", ["thread", "wave", "workgroup"])
+@pytest.mark.parametrize("scope", ["thread", "wave", "workgroup", "subwave"])
 def test_parity_trsv_transposed(env, scope):
     glass, torch = env
     fails = []
@@ -120,7 +120,7 @@ def test_parity_trsv_transposed(env, scope):
     assert not fails, "\n".join(fails)
 
 
-@pytest.mark.parametrize("scope", ["thread", "wave", "workgroup"])
+@pytest.mark.parametrize("scope", ["thread", "wave", "workgroup", "subwave"])
 @pytest.mark.parametrize("op", ["gemm", "potrf", "posv", "trsv", "gemv", "potrs", "se3_compose"])
 def test_bit_identical_across_packs(env, op, scope):
     glass, torch = env
