@@ -357,6 +357,7 @@ inline int finish() { return (int)hipGetLastError(); }
 
 int launch_potrf(const Shape& sh, const Geometry& g, int batch, float* A, int32_t* info, void* stream) {
     if (g.scope == GLASS_SCOPE_SUBWAVE) return launch_chol_subwave(sh, g, batch, A, nullptr, info, stream);
+    if (g.scope == GLASS_SCOPE_WAVE && sh.n >= kBlkMinN) return launch_chol_blk(sh, g, batch, A, nullptr, info, stream);
     (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
     hipStream_t st = (hipStream_t)stream;
     const int n = sh.n;
@@ -386,6 +387,7 @@ int launch_potrf(const Shape& sh, const Geometry& g, int batch, float* A, int32_
 
 int launch_posv(const Shape& sh, const Geometry& g, int batch, float* A, float* B, int32_t* info, void* stream) {
     if (g.scope == GLASS_SCOPE_SUBWAVE) return launch_chol_subwave(sh, g, batch, A, B, info, stream);
+    if (g.scope == GLASS_SCOPE_WAVE && sh.n >= kBlkMinN) return launch_chol_blk(sh, g, batch, A, B, info, stream);
     (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
     hipStream_t st = (hipStream_t)stream;
     const int n = sh.n, r = sh.nrhs;
@@ -420,6 +422,7 @@ int launch_posv(const Shape& sh, const Geometry& g, int batch, float* A, float* 
 
 int launch_potrs(const Shape& sh, const Geometry& g, int batch, const float* L, float* B, void* stream) {
     if (g.scope == GLASS_SCOPE_SUBWAVE) return launch_chol_subwave(sh, g, batch, const_cast<float*>(L), B, nullptr, stream);
+    if (g.scope == GLASS_SCOPE_WAVE && sh.n >= kBlkMinN) return launch_chol_blk(sh, g, batch, const_cast<float*>(L), B, nullptr, stream);
     (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
     hipStream_t st = (hipStream_t)stream;
     const int n = sh.n, r = sh.nrhs;
@@ -454,6 +457,7 @@ int launch_potrs(const Shape& sh, const Geometry& g, int batch, const float* L, 
 
 int launch_trsv(const Shape& sh, const Geometry& g, int batch, const float* L, float* x, void* stream) {
     if (g.scope == GLASS_SCOPE_SUBWAVE) return launch_chol_subwave(sh, g, batch, const_cast<float*>(L), x, nullptr, stream);
+    if (g.scope == GLASS_SCOPE_WAVE && sh.n >= kBlkMinN) return launch_chol_blk(sh, g, batch, const_cast<float*>(L), x, nullptr, stream);
     (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
     hipStream_t st = (hipStream_t)stream;
     const int n = sh.n, tr = sh.trans;

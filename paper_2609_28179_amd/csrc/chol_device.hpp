@@ -420,6 +420,82 @@ GLASS_DEV void wave_solve_all(const float (&a)[NB], float* buf, float* Lg, bool 
     }
 }
 
+// --------------------------------------------------- segments of a wavefront
+// A wavefront split into 64 / SEG segments of SEG lanes (SEG = 16: the four
+// 16-lane DPP rows; SEG = 32: the two halves), each running its own problem
+// with lane i of the segment owning row i.  Broadcasts stay inside a segment.
+
+template <int SEG>
+constexpr unsigned long long seg_mask() {
+    return SEG == 16 ? 0x0001000100010001ull : 0x0000000100000001ull;
+}
+
+// Lane K of every segment, broadcast to its segment.  Inline asm gets no
+// compiler wait states: the DPP read is preceded by s_nop 1.
+template <int SEG, int K>
+GLASS_DEV float seg_bcast(float v) {
+    float src = v;
+    if (SEG == 32) {
+        float R[4];
+        replicate_rows<2>(v, R);  // ends with the wait states a DPP read needs
+        src = R[K / 16];
+    }
+    float r;
+    asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
+                 : "=v"(r)
+                 : "v"(src), "n"(K % 16));
+    return r;
+}
+
+// v in lane K of every segment, `other` elsewhere (literal mask; s_nop 1 covers
+// a transcendental or DPP result read as an operand).
+template <int SEG, int K>
+GLASS_DEV float seg_select(float other, float v) {
+    float r;
+    asm("s_nop 1\n\tv_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(other), "v"(v), "s"(seg_mask<SEG>() << K));
+    return r;
+}
+
+// One column step.  SEG = 16: the pivot is one DPP broadcast and the scaled
+// column l_iJ = a_iJ / sqrt(d) is broadcast for the update.  SEG = 32: a
+// cross-row broadcast needs a permlane16 swap first, so the raw column a_iJ is
+// replicated once and serves both the pivot and the update, which then scales
+// by a_iJ / d in the lane (a_iK -= a_KJ * (a_iJ / d), the same product as
+// l_iJ * l_KJ).
+template <int SEG, int NB, int J>
+struct SegStep {
+    static GLASS_DEV void run(float (&a)[NB], int& info, float& myinv) {
+        float R[4];
+        float d, nv;
+        if (SEG == 16) {
+            d = seg_bcast<SEG, J>(a[J]);
+        } else {
+            replicate_rows<2>(a[J], R);
+            asm volatile("v_mov_b32_dpp %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
+                         : "=v"(d)
+                         : "v"(R[J / 16]), "n"(J % 16));
+        }
+        if (!(d > 0.f) && info == 0) info = J + 1;
+        const float inv = rsq(d);
+        myinv = seg_select<SEG, J>(myinv, inv);
+        if (SEG == 16) {
+            const float v = a[J] * inv;  // in lane J of the segment, a[J] is the pivot itself
+            a[J] = v;
+            replicate_rows<1>(v, R);
+            nv = -v;
+        } else {
+            nv = -(a[J] * (inv * inv));
+            a[J] *= inv;
+        }
+        WaveUpd<NB, J, J + 1>::run(a, R, nv);
+        SegStep<SEG, NB, J + 1>::run(a, info, myinv);
+    }
+};
+template <int SEG, int NB>
+struct SegStep<SEG, NB, NB> {
+    static GLASS_DEV void run(float (&)[NB], int&, float&) {}
+};
+
 // 1 / L_ii of lane i's row (1 beyond n), read from global memory.
 GLASS_DEV float diag_inv(const float* Lg, int n, int lane) {
     return lane < n ? 1.0f / Lg[lane * n + lane] : 1.f;

@@ -91,6 +91,12 @@ inline int bucket8_host(int n) { return ((n + 7) / 8) * 8; }
 // stores and backward substitution.
 constexpr int kGemmStageStride = 68;  // LDS row stride of the staged 16-row output block of the MFMA GEMM
 
+// Orders above 32 of POTRF / POSV / POTRS / TRSV run the blocked MFMA
+// kernel at wave scope; its LDS per wavefront holds one staged 16-row block
+// row of L or four 16 x 16 exchange blocks.
+constexpr int kBlkMinN = 33;
+constexpr int kBlkRegionFloats = 1280;
+
 inline size_t wave_region_floats(const Shape& s) {
     switch (s.op) {
     case GLASS_OP_GEMM:
@@ -100,6 +106,7 @@ inline size_t wave_region_floats(const Shape& s) {
     case GLASS_OP_POTRS:
     case GLASS_OP_POSV:
     case GLASS_OP_TRSV:
+        return s.n >= kBlkMinN ? (size_t)kBlkRegionFloats : (size_t)8 * bucket8_host(s.n);
     case GLASS_OP_POSV_ADJOINT:
         return (size_t)8 * bucket8_host(s.n);
     default:
@@ -214,7 +221,10 @@ int launch_posv(const Shape& s, const Geometry& g, int batch, float* A, float* B
                 void* stream);
 int launch_trsv(const Shape& s, const Geometry& g, int batch, const float* L, float* x, void* stream);
 // Sub-wave scope of POTRF / POSV / POTRS / TRSV (A is L for the solves; B is
-// x for TRSV; info may be NULL).
+// x for TRSV; info may be NULL), and their blocked wave-scope kernel for
+// orders kBlkMinN .. 64 (same arguments).
+int launch_chol_blk(const Shape& s, const Geometry& g, int batch, float* A, float* B, int32_t* info,
+                    void* stream);
 int launch_chol_subwave(const Shape& s, const Geometry& g, int batch, float* A, float* B, int32_t* info,
                         void* stream);
 int launch_se3(const Shape& s, const Geometry& g, int batch, const float* Ta, const float* Tb,

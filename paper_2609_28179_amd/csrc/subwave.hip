@@ -19,57 +19,6 @@
 namespace glass {
 namespace {
 
-template <int SEG>
-constexpr unsigned long long seg_mask() {
-    return SEG == 16 ? 0x0001000100010001ull : 0x0000000100000001ull;
-}
-
-// Lane K of every segment, broadcast to its segment.  Inline asm gets no
-// compiler wait states: the DPP read is preceded by s_nop 1.
-template <int SEG, int K>
-GLASS_DEV float seg_bcast(float v) {
-    float src = v;
-    if (SEG == 32) {
-        float R[4];
-        replicate_rows<2>(v, R);  // ends with the wait states a DPP read needs
-        src = R[K / 16];
-    }
-    float r;
-    asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
-                 : "=v"(r)
-                 : "v"(src), "n"(K % 16));
-    return r;
-}
-
-// v in lane K of every segment, `other` elsewhere (literal mask; s_nop 1 covers
-// a transcendental or DPP result read as an operand).
-template <int SEG, int K>
-GLASS_DEV float seg_select(float other, float v) {
-    float r;
-    asm("s_nop 1\n\tv_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(other), "v"(v), "s"(seg_mask<SEG>() << K));
-    return r;
-}
-
-template <int SEG, int NB, int J>
-struct SegStep {
-    static GLASS_DEV void run(float (&a)[NB], int& info, float& myinv) {
-        const float d = seg_bcast<SEG, J>(a[J]);
-        if (!(d > 0.f) && info == 0) info = J + 1;
-        const float inv = rsq(d);
-        const float v = a[J] * inv;  // in lane J of the segment, a[J] is the pivot itself
-        myinv = seg_select<SEG, J>(myinv, inv);
-        a[J] = v;
-        float R[4];
-        replicate_rows<SEG == 16 ? 1 : 2>(v, R);
-        WaveUpd<NB, J, J + 1>::run(a, R, -v);
-        SegStep<SEG, NB, J + 1>::run(a, info, myinv);
-    }
-};
-template <int SEG, int NB>
-struct SegStep<SEG, NB, NB> {
-    static GLASS_DEV void run(float (&)[NB], int&, float&) {}
-};
-
 template <int SEG, int NB, int K, int RG>
 struct SegFwd {
     static GLASS_DEV void run(const float (&a)[NB], float (&acc)[RG], float (&y)[RG], float myinv) {
