@@ -154,7 +154,8 @@ def emit(args):
         "// paper_2609_28179_amd/autotune.py emit from the sweep records in\n"
         "// paper_2609_28179_amd/tuning/sweep_gfx950.jsonl.  Do not edit by hand.\n"
         "// Layout: kPlace[op][n_index][batch_index] = {scope, pack}; scope 0 thread,\n"
-        "// 1 wave, 2 workgroup.  The SE(3) rows repeat across n (n does not apply).\n"
+        "// 1 wave, 2 workgroup, 3 sub-wave.  The SE(3) rows repeat across n (n does\n"
+        "// not apply).\n"
         f"static const char kTableProvenance[] = \"{prov}\";\n"
         f"static const int kTableN[{len(nk)}] = {{{', '.join(map(str, nk))}}};\n"
         f"static const int kTableB[{len(bk)}] = {{{', '.join(map(str, bk))}}};\n"
@@ -175,7 +176,7 @@ def summary(args):
         ratios.append(fixed / c["median_us"])
         gaps.append(worst / c["median_us"])
         ab = timing.alg_bytes(op, n) * b
-        lines.append(f"| {op} | {n} | {b} | {'TWG'[c['winner'][0]]}{c['winner'][1]} | {c['median_us']:.2f} | "
+        lines.append(f"| {op} | {n} | {b} | {'TWGS'[c['winner'][0]]}{c['winner'][1]} | {c['median_us']:.2f} | "
                      f"{fixed:.2f} | {fixed / c['median_us']:.2f} | {worst / c['median_us']:.1f} | "
                      f"{ab / (c['median_us'] * 1e-6) / 1e9:.0f} | {len(c['margin'])} |")
     g = lambda v: float(np.exp(np.mean(np.log(v))))

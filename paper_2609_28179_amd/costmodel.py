@@ -11,13 +11,13 @@ choice.
 
 Model: a 3-layer perceptron d -> 64 -> 64 -> 1 with ReLU, FP32, run by the
 hand-written kernels behind glass_mlp_forward / glass_mlp_backward /
-glass_mlp_adam.  Features (d = 14): one-hot op over the eight table ops, ln n
-(ln 4 for SE(3)), ln batch, one-hot scope (thread, wave, workgroup), log2
-pack; each column standardised with the training set's mean and standard
+glass_mlp_adam.  Features (d = 15): one-hot op over the eight table ops, ln n
+(ln 4 for SE(3)), ln batch, one-hot scope (thread, wave, workgroup,
+sub-wave), log2 pack; each column standardised with the training set's mean and standard
 deviation (columns with zero spread are left centred).  Target: ln of the
 median microseconds per launch.  Loss: mean squared error over the whole
-training set every step (full batch); Adam with lr 3e-3 (picked by
-leave-one-order-out cross-validation on the sweep), beta (0.9, 0.999),
+training set every step (full batch); Adam with lr 1e-3 for 2000 steps
+(picked by leave-one-order-out cross-validation on the sweep), beta (0.9, 0.999),
 eps 1e-8; He-normal initial weights from a fixed seed.
 
   python -m paper_2609_28179_amd.costmodel cv       [--sweep FILE] [--configs STEPS:LR,...]
@@ -44,11 +44,11 @@ DEFAULT_MODEL = os.path.join(TUNING, "costmodel_gfx950")
 DEFAULT_EVAL = os.path.join(TUNING, "costmodel_eval_gfx950.json")
 
 FEATURE_OPS = ("gemm", "gemv", "potrf", "potrs", "posv", "trsv", "se3_compose", "se3_inverse")
-D = 14
+D = 15
 HIDDEN = 64
 TOP_K = 3
-STEPS = 5000
-LR = 3e-3   # chosen by leave-one-order-out cross-validation on the training sweep
+STEPS = 2000
+LR = 1e-3   # chosen by leave-one-order-out cross-validation on the training sweep
 SEED = 0
 
 
@@ -58,7 +58,7 @@ def features(op: str, n: int, batch: int, scope: int, pack: int) -> np.ndarray:
     f[8] = np.log(4 if op.startswith("se3") else n)
     f[9] = np.log(batch)
     f[10 + scope] = 1.0
-    f[13] = np.log2(pack)
+    f[14] = np.log2(pack)
     return f
 
 
@@ -137,7 +137,7 @@ class CostModel:
         history.append([steps + 1, mse])
         meta = {"d": D, "hidden": HIDDEN, "steps": steps, "lr": lr, "seed": seed, "samples": N,
                 "final_mse": mse, "history": history,
-                "features": "one-hot op (8), ln n, ln batch, one-hot scope (3), log2 pack; standardised",
+                "features": "one-hot op (8), ln n, ln batch, one-hot scope (4), log2 pack; standardised",
                 "target": "ln median us per launch"}
         return cls(p.cpu().numpy(), mu, sd, meta)
 

@@ -1,0 +1,346 @@
+// chol_blk.hpp -- device routines of the blocked MFMA Cholesky family
+// (orders 33..64, one problem per wavefront); used by the batched kernels
+// (chol_blk.hip) and the ragged solver (ragged.hip).
+//
+// POTRF / POSV / POTRS / TRSV of one problem of order 33..64 per wavefront,
+// blocked in 16 x 16 tiles, with every block product on the matrix cores
+// (v_mfma_f32_16x16x4_f32).
+//
+// Right-looking block Cholesky (the factorization of Sec. III-B, in blocks):
+// for each block column k, factor the diagonal block A_kk = L_kk L_kk^T, form
+// the panel L_ik = A_ik L_kk^{-T} for i > k, and update the trailing blocks
+// A_ij -= L_ik L_jk^T for k < j <= i.  The unblocked row-per-lane kernel
+// issues one v_fmac per lane for every (step, trailing column), two thirds of
+// which fall on the upper part; here the trailing update is a dense
+// 16 x 16 x 16 contraction per lower block.
+//
+// Register layout ("T layout"): block (i, j) of the lower triangle sits in
+// four VGPRs per lane; lane (q, r) = (lane / 16, lane % 16) holds
+// A[16 i + r][16 j + 4 q + c], c = 0..3 -- one 16-byte piece of a row, so
+// loads and stores are row-major vectors.  Read as an MFMA accumulator
+// (lane (q, r) holds D[4 q + c][r]) the same registers hold the block's
+// transpose.  With M in T layout as the A operand and X in accumulator
+// layout as the B operand, four v_mfma_f32_16x16x4_f32 (k = 4 q + c in step c)
+// give D = M X + C in accumulator layout, and each product of the algorithm
+// has that form with no data movement:
+//   panel     L_ik^T  = L_kk^{-1} A_ik^T            M = L_kk^{-1}
+//   update    A_ij^T -= L_jk L_ik^T                 M = -L_jk
+//   forward   Y_k = L_kk^{-1} (B_k - sum_j L_kj Y_j)  M = L_kk^{-1}, -L_kj
+// The backward substitution needs L_ik^T and L_kk^{-T} as M; those come from
+// a transpose through LDS.  A diagonal block goes through LDS into
+// row-per-lane form (each 16-lane row of the wavefront receives all 16 rows),
+// is factored with the 16-lane DPP column steps, and is inverted by forward
+// substitution against the identity, which yields L_kk^{-1} in T layout.
+//
+// Rows past n are identity rows (unit pivots that leave the real rows alone;
+// L = I there for the solves) and columns past n are zero.
+#pragma once
+
+#include "device_common.hpp"
+#include "glass_internal.hpp"
+#include "chol_device.hpp"
+
+namespace glass {
+
+constexpr int kXS = 20;  // LDS row stride of a 16 x 16 exchange block
+constexpr int kRS = 68;  // LDS row stride of a staged block row of L (64 + 4)
+static_assert(16 * kRS <= kBlkRegionFloats && 4 * 16 * kXS <= kBlkRegionFloats, "LDS region");
+
+constexpr int BI(int i, int j) { return i * (i + 1) / 2 + j; }
+
+GLASS_DEV f4_t zero4() { return f4_t{0.f, 0.f, 0.f, 0.f}; }
+GLASS_DEV f4_t neg4(const f4_t& v) { return f4_t{-v[0], -v[1], -v[2], -v[3]}; }
+
+// D = M X + C for 16 x 16 blocks: M in T layout, X and C in accumulator layout.
+GLASS_DEV f4_t mma(const f4_t& m, const f4_t& x, f4_t c) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f32_16x16x4f32(m[s], x[s], c, 0, 0, 0);
+    return c;
+}
+
+// The lower blocks of the problem at Ag in T layout.  FULL: n == 16 NBLK.
+// The strict upper part of a diagonal block is not read (zero).
+template <int NBLK, bool FULL>
+GLASS_DEV void blk_load(f4_t (&T)[NBLK * (NBLK + 1) / 2], const float* Ag, int n, int q, int r) {
+    const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(Ag, (uint32_t)(n * n) * 4u);
+#pragma unroll
+    for (int i = 0; i < NBLK; ++i) {
+        const int R = 16 * i + r;
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            const int C = 16 * j + 4 * q;
+            f4_t v = zero4();
+            if (FULL) {
+                v = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, (R * n + C) * 4, 0, 0));
+            } else if (R < n) {
+                if (C + 4 <= n) {
+                    v = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, (R * n + C) * 4, 0, 0));
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (C + e < n)
+                            v[e] = __builtin_bit_cast(float,
+                                                      __builtin_amdgcn_raw_buffer_load_b32(rs, (R * n + C + e) * 4, 0, 0));
+                }
+            } else if (i == j) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = (4 * q + e == r) ? 1.f : 0.f;
+            }
+            if (i == j) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = (4 * q + e <= r) ? v[e] : 0.f;
+            }
+            T[BI(i, j)] = v;
+        }
+    }
+}
+
+// Diagonal block (T layout) to row-per-lane form: lane (q, r) receives row r
+// (every 16-lane row of the wavefront a full copy).  Returns the lane's
+// diagonal entry.
+GLASS_DEV float diag_rows(const f4_t& t, float (&a)[16], float* xs, int q, int r) {
+    *reinterpret_cast<f4_t*>(xs + r * kXS + 4 * q) = t;
+    wave_sync();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const f4_t v = *reinterpret_cast<const f4_t*>(xs + r * kXS + 4 * u);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a[4 * u + e] = v[e];
+    }
+    const float d = xs[r * kXS + r];
+    wave_sync();
+    return d;
+}
+
+// acc += bcast_K(acc) * m, the broadcast of lane K of the 16-lane row folded
+// into the v_fmac.  Consecutive calls on one register are three instructions
+// apart (four accumulators in turn), above the two wait states a DPP read of a
+// just-written VGPR needs.
+template <int K>
+GLASS_DEV void fmac_self_bcast(float& acc, float m) {
+    asm volatile("v_fmac_f32_dpp %0, %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
+                 : "+v"(acc)
+                 : "v"(m), "n"(K));
+}
+
+template <int K>
+struct InvStep {
+    static GLASS_DEV void run(float (&u)[4], const float (&m)[16]) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) fmac_self_bcast<K>(u[c], m[K]);
+        InvStep<K + 1>::run(u, m);
+    }
+};
+template <>
+struct InvStep<16> {
+    static GLASS_DEV void run(float (&)[4], const float (&)[16]) {}
+};
+
+template <int K>
+struct InvCoef {
+    static GLASS_DEV void run(const float (&a)[16], float myinv, float (&m)[16]) {
+        m[K] = seg_select<16, K>(-(a[K] * seg_bcast<16, K>(myinv)), 0.f);
+        InvCoef<K + 1>::run(a, myinv, m);
+    }
+};
+template <>
+struct InvCoef<16> {
+    static GLASS_DEV void run(const float (&)[16], float, float (&)[16]) {}
+};
+
+// L^{-1} of the 16 x 16 lower factor held row-per-lane (a: row r with a zero
+// strict upper part, myinv = 1 / L_rr), in T layout: lane (q, r) returns
+// row r, columns 4 q .. 4 q + 3.  With u_r = L_rr X_r (X = L^{-1}), forward
+// substitution against the identity reads u_rc = delta_rc + sum_{k<r}
+// (-L_rk / L_kk) u_kc, so the rows are finished in order k = 0..15 and each
+// step is one v_fmac with lane k's u broadcast.
+GLASS_DEV f4_t tri_inverse(const float (&a)[16], float myinv, int q, int r) {
+    float m[16];
+    InvCoef<0>::run(a, myinv, m);
+    float u[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) u[c] = (4 * q + c == r) ? 1.f : 0.f;
+    asm volatile("s_nop 1" : "+v"(u[0]), "+v"(u[1]), "+v"(u[2]), "+v"(u[3]));
+    InvStep<0>::run(u, m);
+    return f4_t{u[0] * myinv, u[1] * myinv, u[2] * myinv, u[3] * myinv};
+}
+
+// Block row k of L (rows 16 k .. 16 k + 15): the finished blocks left of the
+// diagonal, the diagonal block from its rows and +0 to the right, staged in
+// LDS and stored as whole rows.
+template <int NBLK, bool FULL>
+GLASS_DEV void store_block_row(const f4_t (&T)[NBLK * (NBLK + 1) / 2], int k, const float (&a)[16], float* Ag,
+                               int n, float* xs, int q, int r, int lane, bool vec) {
+#pragma unroll
+    for (int j = 0; j < NBLK; ++j) {
+        if (j < k) *reinterpret_cast<f4_t*>(xs + r * kRS + 16 * j + 4 * q) = T[BI(k, j)];
+        if (j > k) *reinterpret_cast<f4_t*>(xs + r * kRS + 16 * j + 4 * q) = zero4();
+    }
+    if (q == 0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            *reinterpret_cast<f4_t*>(xs + r * kRS + 16 * k + 4 * u) =
+                f4_t{a[4 * u], a[4 * u + 1], a[4 * u + 2], a[4 * u + 3]};
+    }
+    wave_sync();
+    float* dst = Ag + (size_t)16 * k * n;
+    if (FULL) {
+        constexpr int N4 = 4 * NBLK;  // 16-byte pieces per row
+#pragma unroll
+        for (int g = lane; g < 16 * N4; g += 64) {
+            const int rr = g / N4, c4 = g % N4;
+            reinterpret_cast<f4_t*>(dst)[g] = *reinterpret_cast<const f4_t*>(xs + rr * kRS + 4 * c4);
+        }
+    } else {
+        const int rows = min(16, n - 16 * k);
+        if (vec) {
+            const int n4 = n >> 2;
+            const FastDiv f4 = make_fastdiv((uint32_t)n4);
+            for (int g = lane; g < rows * n4; g += 64) {
+                const int rr = (int)fdiv((uint32_t)g, f4), c4 = g - rr * n4;
+                reinterpret_cast<f4_t*>(dst)[g] = *reinterpret_cast<const f4_t*>(xs + rr * kRS + 4 * c4);
+            }
+        } else {
+            const FastDiv fn = make_fastdiv((uint32_t)n);
+            for (int g = lane; g < rows * n; g += 64) {
+                const int rr = (int)fdiv((uint32_t)g, fn), cc = g - rr * n;
+                dst[g] = xs[rr * kRS + cc];
+            }
+        }
+    }
+    wave_sync();
+}
+
+// Transposes of up to four blocks through LDS (exchange areas of 16 x kXS):
+// a block in T layout comes back in T layout of its transpose.
+template <int NB>
+GLASS_DEV void transpose_blocks(f4_t (&v)[4], float* xs, int q, int r) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) *reinterpret_cast<f4_t*>(xs + b * 16 * kXS + r * kXS + 4 * q) = v[b];
+    wave_sync();
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[b][c] = xs[b * 16 * kXS + (4 * q + c) * kXS + r];
+    wave_sync();
+}
+
+// Columns cb .. cb + 15 of the row-major [n][nr] right-hand sides, in
+// accumulator layout per block row (lane (q, r), element e: row 16 k + 4 q + e,
+// column cb + r).
+template <int NBLK, bool FULL>
+GLASS_DEV void rhs_load(f4_t (&Y)[NBLK], const float* Bg, int n, int nr, int cb, int q, int r) {
+    const int col = cb + r;
+#pragma unroll
+    for (int k = 0; k < NBLK; ++k)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int R = 16 * k + 4 * q + e;
+            Y[k][e] = ((FULL || R < n) && col < nr) ? Bg[R * nr + col] : 0.f;
+        }
+}
+
+template <int NBLK, bool FULL>
+GLASS_DEV void rhs_store(const f4_t (&Y)[NBLK], float* Bg, int n, int nr, int cb, int q, int r) {
+    const int col = cb + r;
+#pragma unroll
+    for (int k = 0; k < NBLK; ++k)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int R = 16 * k + 4 * q + e;
+            if ((FULL || R < n) && col < nr) Bg[R * nr + col] = Y[k][e];
+        }
+}
+
+template <int NBLK, int K>
+struct BwdBlk {
+    // X_K = L_KK^{-T} (Y_K - sum_{i>K} L_iK^T X_i); nT holds -L blocks.
+    static GLASS_DEV void run(const f4_t (&nT)[NBLK * (NBLK + 1) / 2], const f4_t (&linv)[NBLK], f4_t (&Y)[NBLK],
+                              float* xs, int q, int r) {
+        constexpr int NI = NBLK - 1 - K;
+        f4_t v[4];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) v[i] = nT[BI(K + 1 + i, K)];
+        v[NI] = linv[K];
+        transpose_blocks<NI + 1>(v, xs, q, r);
+        f4_t s = Y[K];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) s = mma(v[i], Y[K + 1 + i], s);
+        Y[K] = mma(v[NI], s, zero4());
+        BwdBlk<NBLK, K - 1>::run(nT, linv, Y, xs, q, r);
+    }
+};
+template <int NBLK>
+struct BwdBlk<NBLK, -1> {
+    static GLASS_DEV void run(const f4_t (&)[NBLK * (NBLK + 1) / 2], const f4_t (&)[NBLK], f4_t (&)[NBLK], float*,
+                              int, int) {}
+};
+
+// One problem: factor (POTRF, POSV) or take L as given (POTRS, TRSV), then
+// solve.  op: 0 POTRF, 1 POSV, 2 POTRS, 3 TRSV (trans: 0 forward, 1 backward);
+// Ag is A (L for the solves), Bg the problem's [n][nr] right-hand sides (nr =
+// 1 for TRSV); vec: Ag 16-byte aligned with n % 4 == 0.  xs: the wavefront's
+// kBlkRegionFloats of LDS.  Returns info (0 for the solves); a failed
+// factorization leaves B untouched.
+template <int NBLK, int OP, bool FULL>
+GLASS_DEV int blk_one(float* Ag, float* Bg, int n, int nrhs, int trans, bool vec, float* xs, int lane) {
+    constexpr int NT = NBLK * (NBLK + 1) / 2;
+    const int q = lane >> 4, r = lane & 15;
+    f4_t T[NT];
+    blk_load<NBLK, FULL>(T, Ag, n, q, r);
+    f4_t linv[NBLK];
+    int inf = 0;
+#pragma unroll
+    for (int k = 0; k < NBLK; ++k) {
+        float a[16];
+        const float d = diag_rows(T[BI(k, k)], a, xs, q, r);
+        float myinv = 1.f;
+        if (OP <= 1) {
+            int f = 0;
+            SegStep<16, 16, 0>::run(a, f, myinv);
+#pragma unroll
+            for (int c = 0; c < 16; ++c) a[c] = c <= r ? a[c] : 0.f;
+            if (inf == 0 && f != 0) inf = 16 * k + f;
+            store_block_row<NBLK, FULL>(T, k, a, Ag, n, xs, q, r, lane, vec);
+        } else {
+            myinv = 1.0f / d;
+        }
+        if (OP >= 1 || k + 1 < NBLK) linv[k] = tri_inverse(a, myinv, q, r);
+        if (OP <= 1) {
+#pragma unroll
+            for (int i = k + 1; i < NBLK; ++i) T[BI(i, k)] = mma(linv[k], T[BI(i, k)], zero4());
+#pragma unroll
+            for (int j = k + 1; j < NBLK; ++j) {
+                const f4_t nq = neg4(T[BI(j, k)]);
+#pragma unroll
+                for (int i = j; i < NBLK; ++i) T[BI(i, j)] = mma(nq, T[BI(i, k)], T[BI(i, j)]);
+            }
+        }
+    }
+    if (OP == 0 || inf != 0) return inf;  // a failed factorization leaves B untouched
+    // off-diagonal blocks of L, negated: the forward pass subtracts L_kj Y_j
+#pragma unroll
+    for (int k = 1; k < NBLK; ++k)
+#pragma unroll
+        for (int j = 0; j < k; ++j) T[BI(k, j)] = neg4(T[BI(k, j)]);
+    const int nr = OP == 3 ? 1 : nrhs;
+    const bool fwd = OP != 3 || trans == 0, bwd = OP != 3 || trans != 0;
+    for (int cb = 0; cb < nr; cb += 16) {
+        f4_t Y[NBLK];
+        rhs_load<NBLK, FULL>(Y, Bg, n, nr, cb, q, r);
+        if (fwd) {
+#pragma unroll
+            for (int k = 0; k < NBLK; ++k) {
+                f4_t s = Y[k];
+#pragma unroll
+                for (int j = 0; j < k; ++j) s = mma(T[BI(k, j)], Y[j], s);
+                Y[k] = mma(linv[k], s, zero4());
+            }
+        }
+        if (bwd) BwdBlk<NBLK, NBLK - 1>::run(T, linv, Y, xs, q, r);
+        rhs_store<NBLK, FULL>(Y, Bg, n, nr, cb, q, r);
+    }
+    return 0;
+}
+
+}  // namespace glass

@@ -2,12 +2,14 @@
 // and right-hand-side count) in one launch sequence.
 //
 // Problems are grouped into eight size classes k = ceil(n/8) - 1 (orders
-// 8k+1 .. 8k+8).  Every class has one placement (Sec. III-A, Sec. IV-C),
-// thread scope (class 0 only: a wavefront takes 64 problems, one per lane) or
-// wave scope (a wavefront takes one problem); within a class a problem is
+// 8k+1 .. 8k+8).  Every class has one placement (Sec. III-A, Sec. IV-C):
+// thread scope (class 0 only: a wavefront takes 64 problems, one per lane),
+// sub-wave scope (classes 0 and 1: four problems per wavefront, one per
+// 16-lane row) or wave scope (a wavefront takes one problem; orders above 32
+// run the blocked MFMA routines of chol_blk.hpp).  Within a class a problem is
 // padded with an identity block up to the class order, so one code path
 // serves all its n.  (Thread scope stops at order 8 here because every path
-// of the persistent kernel shares one register allocation.)
+// of a solve kernel shares one register allocation.)
 //
 // Launch sequence (all on one stream, no host synchronisation, capturable):
 //   1. ragged_count    per-chunk class histograms (each block a fixed chunk);
@@ -18,10 +20,14 @@
 //                      perm[] (ranks from wavefront ballots, so the permutation
 //                      is deterministic: equal classes keep index order);
 //   4. ragged_solve    one wavefront per work item of the class-sorted list
-//                      (64 problems of a thread-scope class, or one problem).
+//                      (64 problems of a thread-scope class, four at sub-wave
+//                      scope, or one problem), in two launches: the classes
+//                      above order 32 (the blocked routines need more
+//                      registers), then the rest at the smaller allocation.
 #include "device_common.hpp"
 #include "glass_internal.hpp"
 #include "chol_device.hpp"
+#include "chol_blk.hpp"
 
 namespace glass {
 
@@ -30,6 +36,7 @@ namespace {
 constexpr int kClasses = 8;
 constexpr int kChunk = 1024;        // problems per histogram / scatter block
 constexpr int kScanThreads = 256;
+constexpr int kBigClass = 4;        // classes from here on (orders above 32) run the blocked routines
 
 // Work items of a class of `cnt` problems: 64 problems per item at thread
 // scope, 4 at sub-wave scope, 1 at wave scope.
@@ -343,13 +350,19 @@ GLASS_DEV void ragged_subwave(float* A, float* B, const int64_t* offA, const int
 // from an atomic counter in lane 0 compiled to a per-lane exit in which lanes
 // 1..63 never saw a new item and could not leave, so the launch covers the
 // list instead and hardware dispatch order provides the largest-first order.
+// BIG selects the classes of orders above 32 (blocked MFMA routines, which
+// need more registers) or the rest; the two instances are launched over the
+// same item range, the BIG one first, and each leaves the other's items.
+template <bool BIG>
 __global__ void __launch_bounds__(256) ragged_solve(const int32_t* __restrict__ nvec,
                                                     const int32_t* __restrict__ rvec,
                                                     const int64_t* __restrict__ offA,
                                                     const int64_t* __restrict__ offB, float* A, float* B,
                                                     int32_t* info, const int32_t* __restrict__ perm,
                                                     const int32_t* __restrict__ meta, RaggedScopes scopes) {
-    __shared__ float chunk[4][1024];  // per wavefront: 8 rows of 64 (wave) or four 16 x 16 blocks (sub-wave)
+    // per wavefront: 8 rows of 64 (wave, orders <= 32), four 16 x 16 blocks
+    // (sub-wave) or the blocked routines' staging (orders above 32)
+    __shared__ float chunk[4][BIG ? kBlkRegionFloats : 1024];
     const int lane = threadIdx.x & 63, w = wave_index();
     const int item = blockIdx.x * 4 + w;
     if (item >= meta[3 * kClasses]) return;
@@ -360,6 +373,7 @@ __global__ void __launch_bounds__(256) ragged_solve(const int32_t* __restrict__ 
         const int nit = items_of(scopes.s[c], cnt);
         if (cnt > 0 && item >= ib && item < ib + nit) k = c;
     }
+    if (BIG != (k >= kBigClass)) return;
     const int rel = item - meta[2 * kClasses + k];
     const int cbase = meta[kClasses + k];
     if (scopes.s[k] == kScopeSubwave) {  // classes 0 and 1 only (checked by the caller)
@@ -400,15 +414,17 @@ __global__ void __launch_bounds__(256) ragged_solve(const int32_t* __restrict__ 
     float* Ag = A + uniform_i64(offA[e]);
     float* Bg = B + uniform_i64(offB[e]);
     float* buf = chunk[w];
+    if (BIG) {  // problem offsets are arbitrary: 4-byte stores
+        const int inf = k <= 5 ? blk_one<3, 1, false>(Ag, Bg, n, r, 0, false, buf, lane)
+                               : blk_one<4, 1, false>(Ag, Bg, n, r, 0, false, buf, lane);
+        if (lane == 0) info[e] = inf;
+        return;
+    }
     switch (k) {
     case 0: ragged_wave_one<8>(Ag, Bg, n, r, info + e, buf, lane); break;
     case 1: ragged_wave_one<16>(Ag, Bg, n, r, info + e, buf, lane); break;
     case 2: ragged_wave_one<24>(Ag, Bg, n, r, info + e, buf, lane); break;
-    case 3: ragged_wave_one<32>(Ag, Bg, n, r, info + e, buf, lane); break;
-    case 4: ragged_wave_one<40>(Ag, Bg, n, r, info + e, buf, lane); break;
-    case 5: ragged_wave_one<48>(Ag, Bg, n, r, info + e, buf, lane); break;
-    case 6: ragged_wave_one<56>(Ag, Bg, n, r, info + e, buf, lane); break;
-    default: ragged_wave_one<64>(Ag, Bg, n, r, info + e, buf, lane); break;
+    default: ragged_wave_one<32>(Ag, Bg, n, r, info + e, buf, lane); break;
     }
 }
 
@@ -432,8 +448,10 @@ int launch_posv_ragged(int count, const int32_t* n, const int32_t* nrhs, const i
     hipLaunchKernelGGL(ragged_scan, dim3(1), dim3(kScanThreads), 0, st, nchunks, hist, meta, scopes);
     hipLaunchKernelGGL(ragged_scatter, dim3(nchunks), dim3(256), 0, st, count, n, hist, perm);
     // work items never outnumber problems: ceil(count / 4) four-wave blocks cover the list
-    hipLaunchKernelGGL(ragged_solve, dim3((count + 3) / 4), dim3(256), 0, st, n, nrhs, offA, offB, A, B, info, perm,
-                       meta, scopes);
+    hipLaunchKernelGGL(ragged_solve<true>, dim3((count + 3) / 4), dim3(256), 0, st, n, nrhs, offA, offB, A, B, info,
+                       perm, meta, scopes);
+    hipLaunchKernelGGL(ragged_solve<false>, dim3((count + 3) / 4), dim3(256), 0, st, n, nrhs, offA, offB, A, B, info,
+                       perm, meta, scopes);
     return (int)hipGetLastError();
 }
 
