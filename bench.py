@@ -214,7 +214,7 @@ def main():
     if os.path.exists(tpath):
         t = json.load(open(tpath))
         from paper_2609_28179_amd.traffic import kernel_source_hash
-        if t.get("source_hash") == kernel_source_hash() and tuple(t.get("cell", ())) == tuple(dom):
+        if tuple(t.get("cell", ())) == tuple(dom) and t.get("source_hash") == kernel_source_hash(dom[0]):
             traffic = t.get("bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,

@@ -31,13 +31,23 @@ ROOT = os.path.dirname(PKG)
 COPY_BYTES = 1 << 30
 
 
-def kernel_source_hash():
-    """Hash of the kernel sources; a traffic record is valid for this hash only."""
+# Sources a cell's kernel is built from: the op's own files plus the shared
+# device helpers, the geometry rule and the placement table that picks it.
+_COMMON_SOURCES = ("device_common.hpp", "glass_internal.hpp", "api.cpp", "glass_table_gfx950.inc")
+_CHOL_SOURCES = ("chol.hip", "chol_device.hpp", "chol_blk.hip", "chol_blk.hpp", "subwave.hip")
+_OP_SOURCES = {"gemm": ("gemm.hip",), "gemv": ("gemv.hip",), "potrf": _CHOL_SOURCES, "potrs": _CHOL_SOURCES,
+               "posv": _CHOL_SOURCES, "trsv": _CHOL_SOURCES, "se3_compose": ("se3.hip",),
+               "se3_inverse": ("se3.hip",)}
+
+
+def kernel_source_hash(op: str) -> str:
+    """Hash of the sources op's kernels are built from; a traffic record is
+    valid for this hash only (a change elsewhere in csrc/ leaves it valid)."""
     h = hashlib.sha256()
     csrc = os.path.join(PKG, "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp", ".cpp", ".inc")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in sorted(_COMMON_SOURCES + _OP_SOURCES[op]):
+        h.update(f.encode())
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -92,15 +102,16 @@ def _summarize(a):
     w_c = _per_dispatch(wr, "WRITE_SIZE", is_copy)
     if not (f_k and w_k and f_c and w_c):
         raise RuntimeError("missing dispatches in the counter CSVs")
-    # the copy's largest dispatches are the 1 GiB calibration copies
-    f_c = sorted(f_c)[-len(f_c) // 2:] if len(f_c) > 1 else f_c
-    w_c = sorted(w_c)[-len(w_c) // 2:] if len(w_c) > 1 else w_c
+    # the 1 GiB calibration copies are the largest copy dispatches (the run
+    # also restores destructive inputs with smaller copies between launches)
+    f_c = [v for v in f_c if v >= 0.9 * max(f_c)]
+    w_c = [v for v in w_c if v >= 0.9 * max(w_c)]
     sf = COPY_BYTES / (statistics.median(f_c) * 1024)
     sw = COPY_BYTES / (statistics.median(w_c) * 1024)
     fetch = statistics.median(f_k) * 1024 * sf
     write = statistics.median(w_k) * 1024 * sw
     alg = timing.alg_bytes(a.op, a.n) * a.batch
-    rec = {"cell": [a.op, a.n, a.batch], "source_hash": kernel_source_hash(),
+    rec = {"cell": [a.op, a.n, a.batch], "source_hash": kernel_source_hash(a.op),
            "fetch_kib_per_launch": statistics.median(f_k), "write_kib_per_launch": statistics.median(w_k),
            "copy_bytes": COPY_BYTES, "copy_fetch_kib": statistics.median(f_c), "copy_write_kib": statistics.median(w_c),
            "scale_fetch": sf, "scale_write": sw, "fetch_bytes": fetch, "write_bytes": write,
