@@ -207,9 +207,9 @@ glass_status_t glass_posv_adjoint_batched(int n, int nrhs, int batch, const floa
  * Problems are grouped into eight size classes (orders 8k+1 .. 8k+8) by a
  * deterministic stable counting sort on the device, largest class first;
  * class_scope (HOST int32[8] or NULL) picks each class's scope: thread
- * (class 0 only, 64 problems per wavefront), sub-wave (classes 0 and 1, four
- * problems per wavefront, one per 16-lane row) or wave (one problem per
- * wavefront); a scope a class cannot take is GLASS_ERR_INFEASIBLE_PLACEMENT,
+ * (class 0 only, 64 problems per wavefront), sub-wave (classes 0 and 1: four
+ * problems per wavefront, one per 16-lane row; class 2: two, one per 32-lane
+ * half) or wave (one problem per wavefront); a scope a class cannot take is GLASS_ERR_INFEASIBLE_PLACEMENT,
  * another value GLASS_ERR_INVALID_VALUE.  NULL takes the measured per-class
  * choice of the built-in ragged table (glass_ragged_table_provenance()).
  * Concurrent calls must not share a workspace. */

@@ -73,6 +73,8 @@ def sweep(args):
     cells = timing.heldout_cells() if args.cells == "heldout" else timing.sweep_cells()
     if args.ops:
         cells = [c for c in cells if c[0] in args.ops.split(",")]
+    if args.ns:
+        cells = [c for c in cells if c[1] in [int(x) for x in args.ns.split(",")]]
     if args.max_batch:
         cells = [c for c in cells if c[2] <= args.max_batch]
     with open(args.out, "a") as f:
@@ -200,7 +202,7 @@ RAGGED_PER_SIZE = 5556   # problems per order: the density of the 50,000-system 
 
 def ragged_options(k):
     """Placements a size class k (orders 8k+1 .. 8k+8) can take."""
-    return ["wave"] + (["thread"] if k == 0 else []) + (["subwave"] if k <= 1 else [])
+    return ["wave"] + (["thread"] if k == 0 else []) + (["subwave"] if k <= 2 else [])
 
 
 def ragged_class_sizes(k):
@@ -297,6 +299,7 @@ def main(argv=None):
     s.add_argument("--warmup", type=int, default=3)
     s.add_argument("--seed", type=int, default=0)
     s.add_argument("--ops", default="")
+    s.add_argument("--ns", default="", help="comma-separated orders to sweep (default: all)")
     s.add_argument("--max-batch", type=int, default=0)
     s.add_argument("--cells", choices=("table", "heldout"), default="table",
                    help="table: the 250 cells of the dispatch table; heldout: n in {5,9,20,48} x "

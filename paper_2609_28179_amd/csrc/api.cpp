@@ -223,7 +223,7 @@ glass_status_t glass_posv_ragged(int count, const int32_t* n, const int32_t* nrh
         const int s = class_scope ? class_scope[k] : kRaggedScope[k];
         if (s != GLASS_SCOPE_THREAD && s != GLASS_SCOPE_WAVE && s != GLASS_SCOPE_SUBWAVE)
             return GLASS_ERR_INVALID_VALUE;
-        if ((s == GLASS_SCOPE_THREAD && k > 0) || (s == GLASS_SCOPE_SUBWAVE && k > 1))
+        if ((s == GLASS_SCOPE_THREAD && k > 0) || (s == GLASS_SCOPE_SUBWAVE && k > 2))
             return GLASS_ERR_INFEASIBLE_PLACEMENT;
         sc.s[k] = s;
     }

@@ -1,6 +1,6 @@
 // chol_blk.hip -- batched wave-scope kernels of POTRF / POSV / POTRS / TRSV
-// for orders 33..64 on the blocked MFMA routines of chol_blk.hpp (one problem
-// per wavefront).
+// for orders 25..64 on the blocked MFMA routines of chol_blk.hpp (one problem
+// per wavefront; 2, 3 or 4 tiles of 16 per side).
 #include "chol_blk.hpp"
 
 namespace glass {
@@ -29,7 +29,7 @@ int launch_chol_blk(const Shape& sh, const Geometry& g, int batch, float* A, flo
     hipStream_t st = (hipStream_t)stream;
     const int n = sh.n;
     if (n < kBlkMinN || n > kMaxN) return (int)hipErrorInvalidValue;
-    const int nblk = n <= 48 ? 3 : 4;
+    const int nblk = n <= 32 ? 2 : n <= 48 ? 3 : 4;
     const bool full = n == 16 * nblk && (reinterpret_cast<uintptr_t>(A) & 15) == 0;
     const int op = sh.op == GLASS_OP_POTRF ? 0 : sh.op == GLASS_OP_POSV ? 1 : sh.op == GLASS_OP_POTRS ? 2 : 3;
     dim3 grid((unsigned)g.grid), block(g.threads);
@@ -40,7 +40,7 @@ int launch_chol_blk(const Shape& sh, const Geometry& g, int batch, float* A, flo
         return (int)hipGetLastError();                                                                         \
     }
 #define BLK_OPS(NBLK, FULL) BLK(NBLK, 0, FULL) BLK(NBLK, 1, FULL) BLK(NBLK, 2, FULL) BLK(NBLK, 3, FULL)
-    BLK_OPS(3, false) BLK_OPS(3, true) BLK_OPS(4, false) BLK_OPS(4, true)
+    BLK_OPS(2, false) BLK_OPS(2, true) BLK_OPS(3, false) BLK_OPS(3, true) BLK_OPS(4, false) BLK_OPS(4, true)
 #undef BLK_OPS
 #undef BLK
     return (int)hipErrorInvalidValue;

@@ -1,8 +1,8 @@
 // chol_blk.hpp -- device routines of the blocked MFMA Cholesky family
-// (orders 33..64, one problem per wavefront); used by the batched kernels
+// (orders 25..64, one problem per wavefront); used by the batched kernels
 // (chol_blk.hip) and the ragged solver (ragged.hip).
 //
-// POTRF / POSV / POTRS / TRSV of one problem of order 33..64 per wavefront,
+// POTRF / POSV / POTRS / TRSV of one problem of order 25..64 per wavefront,
 // blocked in 16 x 16 tiles, with every block product on the matrix cores
 // (v_mfma_f32_16x16x4_f32).
 //

@@ -496,6 +496,90 @@ struct SegStep<SEG, NB, NB> {
     static GLASS_DEV void run(float (&)[NB], int&, float&) {}
 };
 
+template <int SEG, int NB, int K, int RG>
+struct SegFwd {
+    static GLASS_DEV void run(const float (&a)[NB], float (&acc)[RG], float (&y)[RG], float myinv) {
+#pragma unroll
+        for (int c = 0; c < RG; ++c) {
+            const float yk = seg_bcast<SEG, K>(acc[c] * myinv);
+            acc[c] = fmaf(-a[K], yk, acc[c]);
+            y[c] = seg_select<SEG, K>(y[c], yk);
+        }
+        SegFwd<SEG, NB, K + 1, RG>::run(a, acc, y, myinv);
+    }
+};
+template <int SEG, int NB, int RG>
+struct SegFwd<SEG, NB, NB, RG> {
+    static GLASS_DEV void run(const float (&)[NB], float (&)[RG], float (&)[RG], float) {}
+};
+
+// Backward substitution L^T x = y; row K of the segment's L is read from its
+// LDS block (row stride NB + 4; lane i takes L_Ki).
+template <int SEG, int NB, int K, int RG>
+struct SegBwd {
+    static GLASS_DEV void run(const float* sb, int i, float (&acc)[RG], float myinv) {
+        const float lki = i < K ? sb[K * (NB + 4) + i] : 0.f;
+#pragma unroll
+        for (int c = 0; c < RG; ++c) {
+            const float xk = seg_bcast<SEG, K>(acc[c] * myinv);
+            acc[c] = seg_select<SEG, K>(fmaf(-lki, xk, acc[c]), xk);
+        }
+        SegBwd<SEG, NB, K - 1, RG>::run(sb, i, acc, myinv);
+    }
+};
+template <int SEG, int NB, int RG>
+struct SegBwd<SEG, NB, -1, RG> {
+    static GLASS_DEV void run(const float*, int, float (&)[RG], float) {}
+};
+
+// Columns c0 .. c0+RG-1 of segment-local right-hand sides Bs (row-major
+// [n][r]; columns past r and rows past n are zero padding and are not
+// stored); act: this lane's segment has a problem to solve.  sb: the
+// segment's L in LDS, row stride NB + 4.
+template <int SEG, int NB, int RG>
+GLASS_DEV void seg_solve_cols(const float (&a)[NB], const float* sb, float* Bs, int n, int r, int c0, int i,
+                              float myinv, bool act, bool fwd, bool bwd) {
+    float acc[RG], y[RG];
+#pragma unroll
+    for (int c = 0; c < RG; ++c) {
+        acc[c] = (act && i < n && c0 + c < r) ? Bs[i * r + c0 + c] : 0.f;
+        y[c] = acc[c];
+    }
+    if (fwd) {
+#pragma unroll
+        for (int c = 0; c < RG; ++c) y[c] = 0.f;
+        SegFwd<SEG, NB, 0, RG>::run(a, acc, y, myinv);
+    }
+    if (bwd) SegBwd<SEG, NB, NB - 1, RG>::run(sb, i, y, myinv);
+#pragma unroll
+    for (int c = 0; c < RG; ++c)
+        if (act && i < n && c0 + c < r) Bs[i * r + c0 + c] = y[c];
+}
+
+// All columns of every segment in groups of 8 / 4 / 1.  r is this lane's
+// segment's column count (the row stride of its Bs); the groups run to
+// rloop, which must be wave-uniform and at least every segment's r (every
+// DPP step runs in all lanes): the batch's nrhs for a uniform batch (the
+// default), the wavefront's largest count for a ragged one.
+template <int SEG, int NB>
+GLASS_DEV void seg_solve_all(const float (&a)[NB], const float* sb, float* Bs, int n, int r, int i, float myinv,
+                             bool act, bool fwd, bool bwd, int rloop = -1) {
+    if (rloop < 0) rloop = r;
+    for (int c0 = 0; c0 < rloop;) {
+        const int left = rloop - c0;
+        if (left >= 5) {
+            seg_solve_cols<SEG, NB, 8>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd);
+            c0 += 8;
+        } else if (left >= 2) {
+            seg_solve_cols<SEG, NB, 4>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd);
+            c0 += 4;
+        } else {
+            seg_solve_cols<SEG, NB, 1>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd);
+            c0 += 1;
+        }
+    }
+}
+
 // 1 / L_ii of lane i's row (1 beyond n), read from global memory.
 GLASS_DEV float diag_inv(const float* Lg, int n, int lane) {
     return lane < n ? 1.0f / Lg[lane * n + lane] : 1.f;

@@ -91,10 +91,11 @@ inline int bucket8_host(int n) { return ((n + 7) / 8) * 8; }
 // stores and backward substitution.
 constexpr int kGemmStageStride = 68;  // LDS row stride of the staged 16-row output block of the MFMA GEMM
 
-// Orders above 32 of POTRF / POSV / POTRS / TRSV run the blocked MFMA
-// kernel at wave scope; its LDS per wavefront holds one staged 16-row block
-// row of L or four 16 x 16 exchange blocks.
-constexpr int kBlkMinN = 33;
+// Orders from kBlkMinN up of POTRF / POSV / POTRS / TRSV run the blocked MFMA
+// kernel at wave scope (below, the 16 x 16 tiles would be mostly padding);
+// its LDS per wavefront holds one staged 16-row block row of L or four
+// 16 x 16 exchange blocks.
+constexpr int kBlkMinN = 25;
 constexpr int kBlkRegionFloats = 1280;
 
 inline size_t wave_region_floats(const Shape& s) {
@@ -231,7 +232,8 @@ int launch_se3(const Shape& s, const Geometry& g, int batch, const float* Ta, co
                float* Tout, void* stream);
 // Placement (scope) of each of the eight ragged size classes (orders 8k+1 ..
 // 8k+8); thread scope is available for class 0 (n <= 8), sub-wave scope
-// (GLASS_SCOPE_SUBWAVE, four problems per wavefront) for classes 0 and 1.
+// (GLASS_SCOPE_SUBWAVE: four problems per wavefront for classes 0 and 1, two
+// for class 2).
 constexpr int kScopeSubwave = GLASS_SCOPE_SUBWAVE;
 struct RaggedScopes {
     int32_t s[8];

@@ -5,11 +5,12 @@
 // 8k+1 .. 8k+8).  Every class has one placement (Sec. III-A, Sec. IV-C):
 // thread scope (class 0 only: a wavefront takes 64 problems, one per lane),
 // sub-wave scope (classes 0 and 1: four problems per wavefront, one per
-// 16-lane row) or wave scope (a wavefront takes one problem; orders above 32
-// run the blocked MFMA routines of chol_blk.hpp).  Within a class a problem is
-// padded with an identity block up to the class order, so one code path
-// serves all its n.  (Thread scope stops at order 8 here because every path
-// of a solve kernel shares one register allocation.)
+// 16-lane row; class 2: two, one per 32-lane half) or wave scope (a
+// wavefront takes one problem; orders above 24 run the blocked MFMA routines
+// of chol_blk.hpp).  Within a class a problem is padded with an identity
+// block up to the class order, so one code path serves all its n.  (Thread
+// scope stops at order 8 here because every path of a solve kernel shares
+// one register allocation.)
 //
 // Launch sequence (all on one stream, no host synchronisation, capturable):
 //   1. ragged_count    per-chunk class histograms (each block a fixed chunk);
@@ -22,7 +23,7 @@
 //   4. ragged_solve    one wavefront per work item of the class-sorted list
 //                      (64 problems of a thread-scope class, four at sub-wave
 //                      scope, or one problem), in two launches: the classes
-//                      above order 32 (the blocked routines need more
+//                      above order 24 (the blocked routines need more
 //                      registers), then the rest at the smaller allocation.
 #include "device_common.hpp"
 #include "glass_internal.hpp"
@@ -36,12 +37,19 @@ namespace {
 constexpr int kClasses = 8;
 constexpr int kChunk = 1024;        // problems per histogram / scatter block
 constexpr int kScanThreads = 256;
-constexpr int kBigClass = 4;        // classes from here on (orders above 32) run the blocked routines
+constexpr int kBigClass = 3;        // classes from here on (orders above 24) run the blocked routines
+// LDS floats per wavefront of the small-class solve: the segments' L blocks
+// (row stride NB + 4) of the sub-wave path, or the wave path's 8-row chunk
+constexpr int kRaggedSegFloats = 2 * 24 * 28;
+static_assert(4 * 16 * 20 <= kRaggedSegFloats && 8 * 24 <= kRaggedSegFloats, "ragged LDS");
 
-// Work items of a class of `cnt` problems: 64 problems per item at thread
-// scope, 4 at sub-wave scope, 1 at wave scope.
-GLASS_DEV int items_of(int scope, int cnt) {
-    return scope == GLASS_SCOPE_THREAD ? (cnt + 63) / 64 : (scope == kScopeSubwave ? (cnt + 3) / 4 : cnt);
+// Work items of class k holding `cnt` problems: 64 problems per item at
+// thread scope, 4 (classes 0, 1) or 2 (class 2) at sub-wave scope, 1 at wave
+// scope.
+GLASS_DEV int items_of(int scope, int k, int cnt) {
+    if (scope == GLASS_SCOPE_THREAD) return (cnt + 63) / 64;
+    if (scope == kScopeSubwave) return k <= 1 ? (cnt + 3) / 4 : (cnt + 1) / 2;
+    return cnt;
 }
 
 // Size class of order n; orders outside 1..64 are clamped into a class here
@@ -63,19 +71,29 @@ __global__ void __launch_bounds__(256) ragged_count(int count, const int32_t* __
     if (tid < kClasses) hist[blockIdx.x * kClasses + tid] = h[tid];
 }
 
-// One block.  Classes are laid out largest first.  meta: [0..8) class count,
-// [8..16) class base in perm, [16..24) work-item base per class, [24] total
-// work items.  Every value is formed in LDS and registers of this block; the
-// per-chunk bases are derived from those, not re-read from global memory.
+// One block of 8 x 32 threads: thread (c, t) owns class c's counts in a
+// contiguous range of chunks (ceil(nchunks / 32) of them), so every thread
+// reads only its own range.  Classes are laid out largest first.  meta:
+// [0..8) class count, [8..16) class base in perm, [16..24) work-item base per
+// class, [24] total work items.  Every value is formed in LDS and registers of
+// this block; the per-chunk bases are derived from those, not re-read.
 __global__ void __launch_bounds__(kScanThreads) ragged_scan(int nchunks, int32_t* hist, int32_t* meta,
                                                            RaggedScopes scopes) {
+    static_assert(kScanThreads == kClasses * 32, "one 32-thread group per class");
+    __shared__ int32_t part[kClasses][32];
     __shared__ int32_t tot[kClasses];
     __shared__ int32_t cbase[kClasses];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, c = tid >> 5, t = tid & 31;
+    const int per = (nchunks + 31) / 32;
+    const int b0 = min(t * per, nchunks), b1 = min(b0 + per, nchunks);
+    int s = 0;
+    for (int b = b0; b < b1; ++b) s += hist[b * kClasses + c];
+    part[c][t] = s;
+    __syncthreads();
     if (tid < kClasses) {
-        int s = 0;
-        for (int b = 0; b < nchunks; ++b) s += hist[b * kClasses + tid];
-        tot[tid] = s;
+        int sum = 0;
+        for (int u = 0; u < 32; ++u) sum += part[tid][u];
+        tot[tid] = sum;
     }
     __syncthreads();
     if (tid == 0) {
@@ -86,19 +104,18 @@ __global__ void __launch_bounds__(kScanThreads) ragged_scan(int nchunks, int32_t
             meta[kClasses + k] = base;
             meta[2 * kClasses + k] = items;
             base += tot[k];
-            items += items_of(scopes.s[k], tot[k]);
+            items += items_of(scopes.s[k], k, tot[k]);
         }
         meta[3 * kClasses] = items;  // total work items
     }
     __syncthreads();
     // per-chunk bases: class base + counts of that class in earlier chunks
-    if (tid < kClasses) {
-        int run = cbase[tid];
-        for (int b = 0; b < nchunks; ++b) {
-            const int c = hist[b * kClasses + tid];
-            hist[b * kClasses + tid] = run;
-            run += c;
-        }
+    int run = cbase[c];
+    for (int u = 0; u < t; ++u) run += part[c][u];
+    for (int b = b0; b < b1; ++b) {
+        const int v = hist[b * kClasses + c];
+        hist[b * kClasses + c] = run;
+        run += v;
     }
 }
 
@@ -183,165 +200,52 @@ GLASS_DEV void ragged_wave_one(float* __restrict__ Ag, float* __restrict__ Bg, i
     if (lane == 0) *info = inf;
 }
 
-// Sub-wave scope (classes 0 and 1, orders <= 16): four problems per
-// wavefront, one per 16-lane row; lane 16s + i owns row i of problem s.
-// Pivots and solved unknowns reach the other lanes of their row with DPP
-// row_newbcast, so the four problems never mix; rows past n are identity.
-// Inline asm operands get no compiler wait states, so each block starts with
-// the ones its inputs need (a VALU result read through DPP: two).
-template <int C>
-GLASS_DEV float row_bcast(float v) {
-    float r;
-    asm volatile("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
-                 : "=v"(r)
-                 : "v"(v), "n"(C));
-    return r;
-}
-
-// v in lane J of every 16-lane row, `other` elsewhere (literal lane mask).
-template <int J>
-GLASS_DEV float rows_select(float other, float v) {
-    float r;
-    asm("s_nop 1\n\tv_cndmask_b32_e64 %0, %1, %2, %3"
-        : "=v"(r)
-        : "v"(other), "v"(v), "s"(0x0001000100010001ull << J));
-    return r;
-}
-
-template <int J, int K>
-struct SubUpd {
-    static GLASS_DEV void run(float (&a)[16], float R, float nv) {
-        fmac_bcast<K>(a[K], R, nv);
-        SubUpd<J, K + 1>::run(a, R, nv);
-    }
-};
-template <int J>
-struct SubUpd<J, 16> {
-    static GLASS_DEV void run(float (&)[16], float, float) {}
-};
-
-template <int J>
-struct SubStep {
-    static GLASS_DEV void run(float (&a)[16], int& info, float& myinv) {
-        const float d = row_bcast<J>(a[J]);
-        if (!(d > 0.f) && info == 0) info = J + 1;
-        const float inv = rsq(d);
-        const float v = a[J] * inv;  // in lane J of the row, a[J] is the pivot itself
-        myinv = rows_select<J>(myinv, inv);
-        a[J] = v;
-        float R[4];
-        replicate_rows<1>(v, R);  // wait states before the DPP reads of v
-        SubUpd<J, J + 1>::run(a, R[0], -v);
-        SubStep<J + 1>::run(a, info, myinv);
-    }
-};
-template <>
-struct SubStep<16> {
-    static GLASS_DEV void run(float (&)[16], int&, float&) {}
-};
-
-template <int K, int RG>
-struct SubFwd {
-    static GLASS_DEV void run(const float (&a)[16], float (&acc)[RG], float (&y)[RG], float myinv) {
-#pragma unroll
-        for (int c = 0; c < RG; ++c) {
-            const float yk = row_bcast<K>(acc[c] * myinv);
-            acc[c] = fmaf(-a[K], yk, acc[c]);
-            y[c] = rows_select<K>(y[c], yk);
-        }
-        SubFwd<K + 1, RG>::run(a, acc, y, myinv);
-    }
-};
-template <int RG>
-struct SubFwd<16, RG> {
-    static GLASS_DEV void run(const float (&)[16], float (&)[RG], float (&)[RG], float) {}
-};
-
-// Backward substitution L^T x = y; row K of the problem's L is read from its
-// 16 x 16 LDS block (lane i takes L_Ki).
-template <int K, int RG>
-struct SubBwd {
-    static GLASS_DEV void run(const float* sb, int i, float (&acc)[RG], float myinv) {
-        const float lki = i < K ? sb[K * 16 + i] : 0.f;
-#pragma unroll
-        for (int c = 0; c < RG; ++c) {
-            const float xk = row_bcast<K>(acc[c] * myinv);
-            acc[c] = rows_select<K>(fmaf(-lki, xk, acc[c]), xk);
-        }
-        SubBwd<K - 1, RG>::run(sb, i, acc, myinv);
-    }
-};
-template <int RG>
-struct SubBwd<-1, RG> {
-    static GLASS_DEV void run(const float*, int, float (&)[RG], float) {}
-};
-
-template <int RG>
-GLASS_DEV void sub_solve_cols(const float (&a)[16], const float* sb, float* Bg, int n, int r, int c0, int i,
-                              float myinv) {
-    float acc[RG], y[RG];
-#pragma unroll
-    for (int c = 0; c < RG; ++c) {
-        acc[c] = (i < n && c0 + c < r) ? Bg[i * r + c0 + c] : 0.f;
-        y[c] = 0.f;
-    }
-    SubFwd<0, RG>::run(a, acc, y, myinv);
-    SubBwd<15, RG>::run(sb, i, y, myinv);
-#pragma unroll
-    for (int c = 0; c < RG; ++c)
-        if (i < n && c0 + c < r) Bg[i * r + c0 + c] = y[c];
-}
-
-// Row s of the wavefront solves problem e (e < 0: an empty row, all identity).
-GLASS_DEV void ragged_subwave(float* A, float* B, const int64_t* offA, const int64_t* offB, int e, int n, int r,
-                              int32_t* info, float* sbuf, int lane) {
-    const int seg = lane >> 4, i = lane & 15;
+// Sub-wave scope (classes 0 to 2): 64 / SEG problems per wavefront, SEG = 16
+// for classes 0 and 1 (orders <= 16), 32 for class 2 (orders 17..24); lane
+// SEG s + i owns row i of problem s.  Pivots and solved unknowns move with the
+// segment broadcasts of chol_device.hpp, so the problems never mix; rows past
+// a problem's n are identity rows.  Problems of one wavefront differ in n and
+// nrhs: loads and stores are per lane, and the column groups run to the
+// wavefront's largest nrhs so every DPP step is uniform.
+template <int SEG, int NB>
+GLASS_DEV void ragged_seg(float* A, float* B, const int64_t* offA, const int64_t* offB, int e, int n, int r,
+                          int32_t* info, float* sbuf, int lane) {
+    const int s = lane / SEG, i = lane % SEG;
     const bool act = e >= 0;
     const int nn = act ? n : 0;
     float* Ag = act ? A + offA[e] : A;
     float* Bg = act ? B + offB[e] : B;
-    float a[16];
+    float a[NB];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) a[j] = (i < nn && j <= i) ? Ag[i * nn + j] : (j == i ? 1.f : 0.f);
+    for (int j = 0; j < NB; ++j) a[j] = (i < nn && j <= i) ? Ag[i * nn + j] : (j == i ? 1.f : 0.f);
     int inf = 0;
     float myinv = 1.f;
-    SubStep<0>::run(a, inf, myinv);
+    SegStep<SEG, NB, 0>::run(a, inf, myinv);
 #pragma unroll
-    for (int j = 0; j < 16; ++j) a[j] = j <= i ? a[j] : 0.f;
-    float* sb = sbuf + seg * 256;
+    for (int j = 0; j < NB; ++j) a[j] = j <= i ? a[j] : 0.f;
+    float* sb = sbuf + s * NB * (NB + 4);
+    if (i < NB) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        f4_t v;
+        for (int t = 0; t < NB / 4; ++t) {
+            f4_t v;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = a[4 * t + q];
-        *reinterpret_cast<f4_t*>(sb + i * 16 + 4 * t) = v;
+            for (int q = 0; q < 4; ++q) v[q] = a[4 * t + q];
+            *reinterpret_cast<f4_t*>(sb + i * (NB + 4) + 4 * t) = v;
+        }
     }
     wave_sync();
     if (i < nn) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
+        for (int j = 0; j < NB; ++j)
             if (j < nn) Ag[i * nn + j] = a[j];
     }
     if (act && i == 0) info[e] = inf;
-    // column groups up to the largest right-hand-side count of the four rows
-    // (uniform, so every DPP step runs in all lanes); a failed or empty row
-    // solves zero columns and stores nothing
+    // a failed or empty segment solves zero columns and stores nothing
     const int reff = (act && inf == 0) ? r : 0;
-    int rmax = max(max(__builtin_amdgcn_readlane(reff, 0), __builtin_amdgcn_readlane(reff, 16)),
-                   max(__builtin_amdgcn_readlane(reff, 32), __builtin_amdgcn_readlane(reff, 48)));
-    for (int c0 = 0; c0 < rmax;) {
-        const int left = rmax - c0;
-        if (left >= 5) {
-            sub_solve_cols<8>(a, sb, Bg, nn, reff, c0, i, myinv);
-            c0 += 8;
-        } else if (left >= 2) {
-            sub_solve_cols<4>(a, sb, Bg, nn, reff, c0, i, myinv);
-            c0 += 4;
-        } else {
-            sub_solve_cols<1>(a, sb, Bg, nn, reff, c0, i, myinv);
-            c0 += 1;
-        }
-    }
+    int rmax = 0;
+#pragma unroll
+    for (int t = 0; t < 64 / SEG; ++t) rmax = max(rmax, __builtin_amdgcn_readlane(reff, t * SEG));
+    seg_solve_all<SEG, NB>(a, sb, Bg, nn, reff, i, myinv, reff > 0, true, true, rmax);
 }
 
 // One work item per wavefront: wavefront g of the launch takes item g of the
@@ -350,19 +254,19 @@ GLASS_DEV void ragged_subwave(float* A, float* B, const int64_t* offA, const int
 // from an atomic counter in lane 0 compiled to a per-lane exit in which lanes
 // 1..63 never saw a new item and could not leave, so the launch covers the
 // list instead and hardware dispatch order provides the largest-first order.
-// BIG selects the classes of orders above 32 (blocked MFMA routines, which
+// BIG selects the classes of orders above 24 (blocked MFMA routines, which
 // need more registers) or the rest; the two instances are launched over the
 // same item range, the BIG one first, and each leaves the other's items.
 template <bool BIG>
-__global__ void __launch_bounds__(256) ragged_solve(const int32_t* __restrict__ nvec,
+__global__ void __launch_bounds__(256, 3) ragged_solve(const int32_t* __restrict__ nvec,
                                                     const int32_t* __restrict__ rvec,
                                                     const int64_t* __restrict__ offA,
                                                     const int64_t* __restrict__ offB, float* A, float* B,
                                                     int32_t* info, const int32_t* __restrict__ perm,
                                                     const int32_t* __restrict__ meta, RaggedScopes scopes) {
     // per wavefront: 8 rows of 64 (wave, orders <= 32), four 16 x 16 blocks
-    // (sub-wave) or the blocked routines' staging (orders above 32)
-    __shared__ float chunk[4][BIG ? kBlkRegionFloats : 1024];
+    // (sub-wave) or the blocked routines' staging (orders above 24)
+    __shared__ float chunk[4][BIG ? kBlkRegionFloats : kRaggedSegFloats];
     const int lane = threadIdx.x & 63, w = wave_index();
     const int item = blockIdx.x * 4 + w;
     if (item >= meta[3 * kClasses]) return;
@@ -370,28 +274,32 @@ __global__ void __launch_bounds__(256) ragged_solve(const int32_t* __restrict__ 
 #pragma unroll
     for (int c = 0; c < kClasses; ++c) {
         const int cnt = meta[c], ib = meta[2 * kClasses + c];
-        const int nit = items_of(scopes.s[c], cnt);
+        const int nit = items_of(scopes.s[c], c, cnt);
         if (cnt > 0 && item >= ib && item < ib + nit) k = c;
     }
     if (BIG != (k >= kBigClass)) return;
     const int rel = item - meta[2 * kClasses + k];
     const int cbase = meta[kClasses + k];
-    if (scopes.s[k] == kScopeSubwave) {  // classes 0 and 1 only (checked by the caller)
-        const int q = rel * 4 + (lane >> 4);
+    if (!BIG && scopes.s[k] == kScopeSubwave) {  // classes 0 to 2 only (checked by the caller)
+        const int seg = k <= 1 ? 16 : 32;
+        const int q = rel * (64 / seg) + lane / seg;
         int e = -1, n = 0, r = 0;
         if (q < meta[k]) {
             e = perm[cbase + q];
             n = nvec[e];
             r = rvec[e];
-            if (n < 1 || n > 16 || r < 1 || r > kMaxN) {
-                if ((lane & 15) == 0) info[e] = -1;
+            if (n < 1 || n > kMaxN || r < 1 || r > kMaxN) {
+                if (lane % seg == 0) info[e] = -1;
                 e = -1;
             }
         }
-        ragged_subwave(A, B, offA, offB, e, n, r, info, chunk[w], lane);
+        if (k <= 1)
+            ragged_seg<16, 16>(A, B, offA, offB, e, n, r, info, chunk[w], lane);
+        else
+            ragged_seg<32, 24>(A, B, offA, offB, e, n, r, info, chunk[w], lane);
         return;
     }
-    if (scopes.s[k] == GLASS_SCOPE_THREAD) {
+    if (!BIG && scopes.s[k] == GLASS_SCOPE_THREAD) {
         const int q = rel * 64 + lane;
         if (q < meta[k]) {
             const int e = perm[cbase + q];
@@ -415,16 +323,16 @@ __global__ void __launch_bounds__(256) ragged_solve(const int32_t* __restrict__ 
     float* Bg = B + uniform_i64(offB[e]);
     float* buf = chunk[w];
     if (BIG) {  // problem offsets are arbitrary: 4-byte stores
-        const int inf = k <= 5 ? blk_one<3, 1, false>(Ag, Bg, n, r, 0, false, buf, lane)
-                               : blk_one<4, 1, false>(Ag, Bg, n, r, 0, false, buf, lane);
+        const int inf = k == 3   ? blk_one<2, 1, false>(Ag, Bg, n, r, 0, false, buf, lane)
+                        : k <= 5 ? blk_one<3, 1, false>(Ag, Bg, n, r, 0, false, buf, lane)
+                                 : blk_one<4, 1, false>(Ag, Bg, n, r, 0, false, buf, lane);
         if (lane == 0) info[e] = inf;
         return;
     }
     switch (k) {
     case 0: ragged_wave_one<8>(Ag, Bg, n, r, info + e, buf, lane); break;
     case 1: ragged_wave_one<16>(Ag, Bg, n, r, info + e, buf, lane); break;
-    case 2: ragged_wave_one<24>(Ag, Bg, n, r, info + e, buf, lane); break;
-    default: ragged_wave_one<32>(Ag, Bg, n, r, info + e, buf, lane); break;
+    default: ragged_wave_one<24>(Ag, Bg, n, r, info + e, buf, lane); break;  // class 2
     }
 }
 

@@ -19,42 +19,6 @@
 namespace glass {
 namespace {
 
-template <int SEG, int NB, int K, int RG>
-struct SegFwd {
-    static GLASS_DEV void run(const float (&a)[NB], float (&acc)[RG], float (&y)[RG], float myinv) {
-#pragma unroll
-        for (int c = 0; c < RG; ++c) {
-            const float yk = seg_bcast<SEG, K>(acc[c] * myinv);
-            acc[c] = fmaf(-a[K], yk, acc[c]);
-            y[c] = seg_select<SEG, K>(y[c], yk);
-        }
-        SegFwd<SEG, NB, K + 1, RG>::run(a, acc, y, myinv);
-    }
-};
-template <int SEG, int NB, int RG>
-struct SegFwd<SEG, NB, NB, RG> {
-    static GLASS_DEV void run(const float (&)[NB], float (&)[RG], float (&)[RG], float) {}
-};
-
-// Backward substitution L^T x = y; row K of the segment's L is read from its
-// LDS block (row stride NB + 4; lane i takes L_Ki).
-template <int SEG, int NB, int K, int RG>
-struct SegBwd {
-    static GLASS_DEV void run(const float* sb, int i, float (&acc)[RG], float myinv) {
-        const float lki = i < K ? sb[K * (NB + 4) + i] : 0.f;
-#pragma unroll
-        for (int c = 0; c < RG; ++c) {
-            const float xk = seg_bcast<SEG, K>(acc[c] * myinv);
-            acc[c] = seg_select<SEG, K>(fmaf(-lki, xk, acc[c]), xk);
-        }
-        SegBwd<SEG, NB, K - 1, RG>::run(sb, i, acc, myinv);
-    }
-};
-template <int SEG, int NB, int RG>
-struct SegBwd<SEG, NB, -1, RG> {
-    static GLASS_DEV void run(const float*, int, float (&)[RG], float) {}
-};
-
 // Row i of segment s's problem (lane 16s + i or 32s + i) from the wavefront's
 // np adjacent problems starting at base.  MASK and the padding follow
 // rows_load_lower (identity rows for a factorization, zero rows otherwise;
@@ -124,46 +88,6 @@ GLASS_DEV void seg_store_L(float* __restrict__ dst, const float* buf, int np, in
         const int s = (int)fdiv((uint32_t)g, fnn), rem = g - s * nn;
         const int i = (int)fdiv((uint32_t)rem, fn), j = rem - i * n;
         dst[g] = buf[s * NB * (NB + 4) + i * (NB + 4) + j];
-    }
-}
-
-template <int SEG, int NB, int RG>
-GLASS_DEV void seg_solve_cols(const float (&a)[NB], const float* sb, float* Bs, int n, int r, int c0, int i,
-                              float myinv, bool act, bool fwd, bool bwd) {
-    float acc[RG], y[RG];
-#pragma unroll
-    for (int c = 0; c < RG; ++c) {
-        acc[c] = (act && i < n && c0 + c < r) ? Bs[i * r + c0 + c] : 0.f;
-        y[c] = acc[c];
-    }
-    if (fwd) {
-#pragma unroll
-        for (int c = 0; c < RG; ++c) y[c] = 0.f;
-        SegFwd<SEG, NB, 0, RG>::run(a, acc, y, myinv);
-    }
-    if (bwd) SegBwd<SEG, NB, NB - 1, RG>::run(sb, i, y, myinv);
-#pragma unroll
-    for (int c = 0; c < RG; ++c)
-        if (act && i < n && c0 + c < r) Bs[i * r + c0 + c] = y[c];
-}
-
-// All nrhs columns of every segment in groups of 8 / 4 / 1 (nrhs is the
-// same for the whole batch, so the loop is uniform).
-template <int SEG, int NB>
-GLASS_DEV void seg_solve_all(const float (&a)[NB], const float* sb, float* Bs, int n, int r, int i, float myinv,
-                             bool act, bool fwd, bool bwd) {
-    for (int c0 = 0; c0 < r;) {
-        const int left = r - c0;
-        if (left >= 5) {
-            seg_solve_cols<SEG, NB, 8>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd);
-            c0 += 8;
-        } else if (left >= 2) {
-            seg_solve_cols<SEG, NB, 4>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd);
-            c0 += 4;
-        } else {
-            seg_solve_cols<SEG, NB, 1>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd);
-            c0 += 1;
-        }
     }
 }
 

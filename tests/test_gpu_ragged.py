@@ -23,7 +23,8 @@ def per_problem_err(case, B_gpu, B_ref, idx):
 
 
 @pytest.mark.parametrize("scopes", [None, ["wave"] * 8, ["thread"] + ["wave"] * 7,
-                                    ["subwave", "subwave"] + ["wave"] * 6, ["thread", "subwave"] + ["wave"] * 6])
+                                    ["subwave", "subwave"] + ["wave"] * 6, ["thread", "subwave"] + ["wave"] * 6,
+                                    ["subwave"] * 3 + ["wave"] * 5])
 @pytest.mark.parametrize("count,seed", [(1, 3), (77, 4), (2500, 5)])
 def test_ragged_parity(scopes, count, seed):
     import torch

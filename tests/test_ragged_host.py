@@ -54,7 +54,7 @@ def test_ragged_validation_without_device():
     assert glass.glass_posv_ragged(10, F, F, F, F, F, F, F, F, w, class_scope=[7] * 8, stream=0) == \
         glass.ERR_INVALID_VALUE
     bad = ["wave"] * 8
-    bad[2] = "subwave"   # sub-wave rows hold orders up to 16 (classes 0 and 1)
+    bad[3] = "subwave"   # sub-wave segments hold orders up to 24 (classes 0 to 2)
     assert glass.glass_posv_ragged(10, F, F, F, F, F, F, F, F, w, class_scope=bad, stream=0) == \
         glass.ERR_INFEASIBLE_PLACEMENT
     assert glass.glass_ragged_table_provenance().startswith("gfx950")
