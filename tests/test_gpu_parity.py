@@ -96,7 +96,7 @@ def test_parity_se3(env, op, scope):
 def test_parity_multi_rhs(env, op, nrhs, scope):
     glass, torch = env
     fails = []
-    for n in (1, 5, 8, 12, 16, 24, 64):
+    for n in (1, 5, 8, 12, 16, 24, 28, 40, 64):
         for pack in (1, 2):
             feas = glass.glass_placement_feasible(glass.OPS[op], n, nrhs, glass.SCOPES[scope], pack)
             if feas != 1:
@@ -111,7 +111,7 @@ def test_parity_multi_rhs(env, op, nrhs, scope):
 def test_parity_trsv_transposed(env, scope):
     glass, torch = env
     fails = []
-    for n in (1, 3, 7, 16, 33, 64):
+    for n in (1, 3, 7, 16, 25, 32, 33, 64):
         if glass.glass_placement_feasible(glass.OP_TRSV, n, 1, glass.SCOPES[scope], 1) != 1:
             continue
         label = f"trsv trans=1 n={n} {scope}"
