@@ -73,8 +73,10 @@ typedef enum {
     GLASS_SCOPE_WORKGROUP = 2, /* one problem per workgroup at a time        */
     GLASS_SCOPE_SUBWAVE = 3    /* 64/SEG problems per wavefront, one per
                                   SEG-lane segment: SEG = 16 for n <= 16,
-                                  32 for 16 < n <= 32.  POTRF, POTRS, POSV,
-                                  TRSV and the ragged solve only            */
+                                  32 for 16 < n <= 32 (POTRF, POTRS, POSV,
+                                  TRSV, the ragged solve); GEMM and GEMV
+                                  with m, n, k <= 16 (SEG = 16, no
+                                  transposes)                               */
 } glass_scope_t;
 
 /* A placement (Sec. III-A, Sec. IV-C).  `pack` P in {1,2,4,8} counts the
@@ -96,8 +98,9 @@ typedef struct {
 /* C = alpha * A B + beta * C  (Sec. III-B, BLAS L3).
  * A [batch][m][k], B [batch][k][n], C [batch][m][n].  beta == 0: C is not
  * read (NaN in C does not propagate).  C must not overlap A or B.
- * Thread scope requires m == n == k <= 12; wave and workgroup scope use FP32
- * MFMA (v_mfma_f32_16x16x4_f32) when max(m, n, k) >= 16. */
+ * Thread scope requires m == n == k <= 12; sub-wave scope m, n, k <= 16; wave
+ * and workgroup scope use FP32 MFMA (v_mfma_f32_16x16x4_f32) when
+ * max(m, n, k) >= 16. */
 glass_status_t glass_gemm_batched(int m, int n, int k, int batch, float alpha,
                                   const float* A, const float* B, float beta,
                                   float* C, const glass_placement_t* force,
@@ -117,7 +120,8 @@ glass_status_t glass_gemm_batched_ex(int transa, int transb, int m, int n, int k
 
 /* y = alpha * A x + beta * y  (Sec. III-B, BLAS L2).
  * A [batch][m][n], x [batch][n], y [batch][m]; beta == 0: y is not read.
- * y must not overlap A or x.  Thread scope requires m == n <= 16. */
+ * y must not overlap A or x.  Thread scope requires m == n <= 16, sub-wave
+ * scope m, n <= 16. */
 glass_status_t glass_gemv_batched(int m, int n, int batch, float alpha,
                                   const float* A, const float* x, float beta,
                                   float* y, const glass_placement_t* force,

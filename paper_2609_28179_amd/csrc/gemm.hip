@@ -365,6 +365,7 @@ int launch_gemm_t(const Shape& sh, const Geometry& g, int batch, float alpha, co
 
 int launch_gemm(const Shape& sh, const Geometry& g, int batch, float alpha, const float* A, const float* B,
                 float beta, float* C, void* stream) {
+    if (g.scope == GLASS_SCOPE_SUBWAVE) return launch_blas_subwave(sh, g, batch, alpha, A, B, beta, C, stream);
     (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
     hipStream_t st = (hipStream_t)stream;
     if (g.scope == GLASS_SCOPE_THREAD) {  // square, no transposes (make_geometry)

@@ -118,6 +118,7 @@ __global__ void __launch_bounds__(256) gemv_wg(int m, int n, int batch, int pack
 
 int launch_gemv(const Shape& sh, const Geometry& g, int batch, float alpha, const float* A, const float* x,
                 float beta, float* y, void* stream) {
+    if (g.scope == GLASS_SCOPE_SUBWAVE) return launch_blas_subwave(sh, g, batch, alpha, A, x, beta, y, stream);
     (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
     hipStream_t st = (hipStream_t)stream;
     dim3 grid((unsigned)g.grid), block(g.threads);

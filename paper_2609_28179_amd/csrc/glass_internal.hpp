@@ -120,6 +120,7 @@ inline size_t wave_region_floats(const Shape& s) {
 // and 32 above.  LDS per wavefront: one block of L per segment, rows padded
 // to NB + 4 floats (NB = order rounded up to 8).
 constexpr int kSubwaveMaxN = 32;
+constexpr int kSubwaveBlasMaxN = 16;  // GEMM / GEMV at sub-wave scope: m, n, k <= 16, no transposes
 inline int subwave_seg(int n) { return n <= 16 ? 16 : 32; }
 inline size_t subwave_region_floats(int n) {
     const int nb = bucket8_host(n);
@@ -186,10 +187,18 @@ inline bool make_geometry(const Shape& s, int scope, int pack, long long batch, 
         out.problems_per_wg = pack;
         out.lds_bytes = wave_region_floats(s) * pack * sizeof(float);
     } else if (scope == GLASS_SCOPE_SUBWAVE) {
-        if (!subwave_op(s.op) || s.n > kSubwaveMaxN) return false;
         out.threads = kWave * pack;
-        out.problems_per_wg = pack * (kWave / subwave_seg(s.n));
-        out.lds_bytes = subwave_region_floats(s.n) * pack * sizeof(float);
+        if (s.op == GLASS_OP_GEMM || s.op == GLASS_OP_GEMV) {
+            // four problems per wavefront, rows in 16-lane segments
+            if (s.m > kSubwaveBlasMaxN || s.n > kSubwaveBlasMaxN || s.k > kSubwaveBlasMaxN || s.trans != 0)
+                return false;
+            out.problems_per_wg = pack * (kWave / 16);
+            out.lds_bytes = 0;
+        } else {
+            if (!subwave_op(s.op) || s.n > kSubwaveMaxN) return false;
+            out.problems_per_wg = pack * (kWave / subwave_seg(s.n));
+            out.lds_bytes = subwave_region_floats(s.n) * pack * sizeof(float);
+        }
     } else if (scope == GLASS_SCOPE_WORKGROUP) {
         if (s.op == GLASS_OP_POSV_ADJOINT) return false;
         int order = s.n;
@@ -226,6 +235,9 @@ int launch_trsv(const Shape& s, const Geometry& g, int batch, const float* L, fl
 // orders kBlkMinN .. 64 (same arguments).
 int launch_chol_blk(const Shape& s, const Geometry& g, int batch, float* A, float* B, int32_t* info,
                     void* stream);
+// Sub-wave scope of GEMM (Bx = B, Cy = C) and GEMV (Bx = x, Cy = y).
+int launch_blas_subwave(const Shape& s, const Geometry& g, int batch, float alpha, const float* A, const float* Bx,
+                        float beta, float* Cy, void* stream);
 int launch_chol_subwave(const Shape& s, const Geometry& g, int batch, float* A, float* B, int32_t* info,
                         void* stream);
 int launch_se3(const Shape& s, const Geometry& g, int batch, const float* Ta, const float* Tb,
