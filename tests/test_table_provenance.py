@@ -1,0 +1,58 @@
+"""Host check of the committed dispatch table against the committed sweep it
+was generated from: every entry is the argmin-of-medians placement of its
+cell (ties to the smaller scope, then pack), and no tuned entry is slower
+than the fixed wave/P=1 placement measured in the same paired rounds.  No
+GPU: this reads the JSONL records and the generated header only."""
+import json
+import os
+
+from oracle import placement_ref as pref
+from paper_2609_28179_amd import autotune, glass, timing
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+INC = os.path.join(ROOT, "paper_2609_28179_amd", "csrc", "glass_table_gfx950.inc")
+
+
+def _records():
+    recs = []
+    for line in open(autotune.DEFAULT_SWEEP):
+        if line.strip():
+            r = json.loads(line)
+            if r.get("kind") != "meta":
+                recs.append(r)
+    return recs
+
+
+def test_table_is_the_sweep_argmin():
+    recs = _records()
+    ch = autotune.choose(recs)
+    table = pref.load_table(INC)
+    cells = timing.sweep_cells()
+    assert set(ch) == set(cells), "the sweep must cover every table cell"
+    for (op, n, b) in cells:
+        want = tuple(ch[(op, n, b)]["winner"])
+        got = pref.lookup(table, glass.OPS[op], n, b)
+        assert got == want, (op, n, b, got, want)
+
+
+def test_tuned_never_slower_than_fixed_wave():
+    for cell, c in autotune.choose(_records()).items():
+        fixed = c["medians"].get((glass.SCOPE_WAVE, 1))
+        assert fixed is not None, cell
+        assert c["median_us"] <= fixed, cell
+
+
+def test_ragged_table_is_the_ragged_sweep_argmin():
+    import re
+    inc = open(os.path.join(ROOT, "paper_2609_28179_amd", "csrc", "glass_ragged_gfx950.inc")).read()
+    built = [int(v) for v in re.search(r"kRaggedScope\[8\]\s*=\s*\{([^}]*)\}", inc).group(1).split(",")]
+    best = {}
+    for line in open(autotune.DEFAULT_RAGGED):
+        r = json.loads(line)
+        if r.get("kind") == "meta":
+            continue
+        key = (r["median_us"], autotune.ragged_options(r["class"]).index(r["scope"]))
+        if r["class"] not in best or key < best[r["class"]][0]:
+            best[r["class"]] = (key, r["scope"])
+    assert sorted(best) == list(range(8))
+    assert built == [glass.RAGGED_SCOPES[best[k][1]] for k in range(8)]
