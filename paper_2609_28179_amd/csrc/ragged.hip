@@ -59,8 +59,7 @@ GLASS_DEV int class_of(int n) {
     return k < 0 ? 0 : (k > kClasses - 1 ? kClasses - 1 : k);
 }
 
-__global__ void __launch_bounds__(256) ragged_count(int count, const int32_t* __restrict__ nvec, int32_t* hist,
-                                                    int32_t* meta) {
+__global__ void __launch_bounds__(256) ragged_count(int count, const int32_t* __restrict__ nvec, int32_t* hist) {
     __shared__ int32_t h[kClasses];
     const int tid = threadIdx.x;
     if (tid < kClasses) h[tid] = 0;
@@ -352,7 +351,7 @@ int launch_posv_ragged(int count, const int32_t* n, const int32_t* nrhs, const i
     int32_t* hist = reinterpret_cast<int32_t*>(workspace);
     int32_t* meta = hist + (size_t)nchunks * kClasses;
     int32_t* perm = meta + 32;
-    hipLaunchKernelGGL(ragged_count, dim3(nchunks), dim3(256), 0, st, count, n, hist, meta);
+    hipLaunchKernelGGL(ragged_count, dim3(nchunks), dim3(256), 0, st, count, n, hist);
     hipLaunchKernelGGL(ragged_scan, dim3(1), dim3(kScanThreads), 0, st, nchunks, hist, meta, scopes);
     hipLaunchKernelGGL(ragged_scatter, dim3(nchunks), dim3(256), 0, st, count, n, hist, perm);
     // work items never outnumber problems: ceil(count / 4) four-wave blocks cover the list
