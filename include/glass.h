@@ -74,7 +74,8 @@ typedef enum {
     GLASS_SCOPE_SUBWAVE = 3    /* 64/SEG problems per wavefront, one per
                                   SEG-lane segment: SEG = 16 for n <= 16,
                                   32 for 16 < n <= 32 (POTRF, POTRS, POSV,
-                                  TRSV, the ragged solve); GEMM and GEMV
+                                  TRSV, the POSV adjoint, the ragged
+                                  solve); GEMM and GEMV
                                   with m, n, k <= 16 (SEG = 16, no
                                   transposes)                               */
 } glass_scope_t;
@@ -182,8 +183,8 @@ glass_status_t glass_se3_batched(glass_op_t op, int batch, const float* Ta,
  *   dA = -(dB X^T + X dB^T) / 2        [batch][n][n], symmetric
  * dA is the gradient with respect to a symmetric A (the factorization reads
  * A as symmetric).  dB may be G exactly (in place); dA must not overlap any
- * other argument.  Scopes: thread (n <= 16) and wave; the workgroup scope is
- * infeasible.  With force == NULL the placement is the table's POTRS entry
+ * other argument.  Scopes: thread (n <= 16), sub-wave (n <= 32) and wave;
+ * the workgroup scope is infeasible.  With force == NULL the placement is the table's POTRS entry
  * for (n, batch) when feasible, else wave / pack 1. */
 glass_status_t glass_posv_adjoint_batched(int n, int nrhs, int batch, const float* L,
                                           const float* X, const float* G, float* dB,

@@ -14,6 +14,11 @@
 //   wave    one problem per wavefront, the wave-scope substitutions of
 //           chol.hip; lane i accumulates row i of dA from v_readlane
 //           broadcasts of x_j and dB_j, rows leave through the 8-row LDS chunk.
+//   sub-wave  (n <= 32) 64 / SEG problems per wavefront on SEG-lane segments
+//           (SEG = 16 up to order 16, 32 above), the segment substitutions of
+//           the sub-wave Cholesky kernels; x_j and dB_j reach lane i by
+//           segment broadcasts, and dA leaves through the segments' LDS
+//           blocks as one contiguous copy of the wavefront's problems.
 #include "device_common.hpp"
 #include "glass_internal.hpp"
 #include "chol_device.hpp"
@@ -126,6 +131,60 @@ __global__ void __launch_bounds__(512) adjoint_wave(int n, int nrhs, int batch, 
     wave_chunks_desc<NB>(d, buf, dA + p * n * n, vec, n, lane, false, 0.f, 1.f);
 }
 
+template <int SEG, int NB, int J>
+struct SegDa {
+    // d[j] += dB_i x_j + x_i dB_j, x_j and dB_j broadcast from lane j of the segment
+    static GLASS_DEV void run(float (&d)[NB], float b, float x) {
+        const float xj = seg_bcast<SEG, J>(x), bj = seg_bcast<SEG, J>(b);
+        d[J] = sym_pair(d[J], b, xj, x, bj);
+        SegDa<SEG, NB, J + 1>::run(d, b, x);
+    }
+};
+template <int SEG, int NB>
+struct SegDa<SEG, NB, NB> {
+    static GLASS_DEV void run(float (&)[NB], float, float) {}
+};
+
+template <int SEG, int NB>
+__global__ void __launch_bounds__(512) adjoint_seg(int n, int nrhs, int batch, const float* __restrict__ L,
+                                                   const float* __restrict__ X, const float* __restrict__ G,
+                                                   float* __restrict__ dB, float* __restrict__ dA, int region) {
+    extern __shared__ float lds[];
+    constexpr int PPW = 64 / SEG;
+    const int w = wave_index(), lane = threadIdx.x & 63;
+    const int s = lane / SEG, i = lane % SEG;
+    const long long p0 = ((long long)blockIdx.x * (blockDim.x >> 6) + w) * PPW;
+    if (p0 >= batch) return;
+    const int np = (int)min((long long)PPW, (long long)batch - p0);
+    const bool row = s < np && i < n;
+    float* buf = lds + (size_t)w * region;
+    float* sb = buf + s * NB * (NB + 4);
+    const float* Lb = L + p0 * n * n;
+    float a[NB];
+    seg_load_rows<NB, true>(a, Lb, np, n, s, i);
+    const float myinv = row ? 1.0f / Lb[s * n * n + i * n + i] : 1.f;
+    seg_rows_to_lds<NB>(a, sb, i);
+    wave_sync();
+    const long long ob = (p0 + s) * n * nrhs;
+    float d[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) d[j] = 0.f;
+    for (int c = 0; c < nrhs; ++c) {
+        float acc[1] = {row ? G[ob + i * nrhs + c] : 0.f}, y[1] = {0.f};
+        SegFwd<SEG, NB, 0, 1>::run(a, acc, y, myinv);
+        SegBwd<SEG, NB, NB - 1, 1>::run(sb, i, y, myinv);
+        const float xc = row ? X[ob + i * nrhs + c] : 0.f;
+        if (row) dB[ob + i * nrhs + c] = y[0];
+        SegDa<SEG, NB, 0>::run(d, y[0], xc);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) d[j] *= -0.5f;
+    wave_sync();  // the segment blocks held L for the backward sweeps
+    seg_rows_to_lds<NB>(d, sb, i);
+    wave_sync();
+    seg_store_L<NB>(dA + p0 * n * n, buf, np, n, (n & 3) == 0 && aligned16(dA), lane);
+}
+
 inline int bucket8(int n) { return ((n + 7) / 8) * 8; }
 
 }  // namespace
@@ -153,6 +212,17 @@ int launch_posv_adjoint(const Shape& sh, const Geometry& g, int batch, const flo
         hipLaunchKernelGGL(adjoint_wave<NB>, grid, block, g.lds_bytes, st, n, r, batch, L, X, G, dB, dA, region); \
         break;
             CASE(8) CASE(16) CASE(24) CASE(32) CASE(40) CASE(48) CASE(56) CASE(64)
+#undef CASE
+        default: return (int)hipErrorInvalidValue;
+        }
+    } else if (g.scope == GLASS_SCOPE_SUBWAVE) {
+        const int region = (int)subwave_region_floats(n);
+        switch (bucket8(n)) {
+#define CASE(SEG, NB)                                                                                               \
+    case NB:                                                                                                        \
+        hipLaunchKernelGGL((adjoint_seg<SEG, NB>), grid, block, g.lds_bytes, st, n, r, batch, L, X, G, dB, dA, region); \
+        break;
+            CASE(16, 8) CASE(16, 16) CASE(32, 24) CASE(32, 32)
 #undef CASE
         default: return (int)hipErrorInvalidValue;
         }

@@ -127,7 +127,8 @@ inline size_t subwave_region_floats(int n) {
     return (size_t)(kWave / subwave_seg(n)) * nb * (nb + 4);
 }
 inline bool subwave_op(glass_op_t op) {
-    return op == GLASS_OP_POTRF || op == GLASS_OP_POSV || op == GLASS_OP_POTRS || op == GLASS_OP_TRSV;
+    return op == GLASS_OP_POTRF || op == GLASS_OP_POSV || op == GLASS_OP_POTRS || op == GLASS_OP_TRSV ||
+           op == GLASS_OP_POSV_ADJOINT;
 }
 
 // LDS floats of a thread-scope workgroup of `t` lanes.

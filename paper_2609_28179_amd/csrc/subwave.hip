@@ -19,78 +19,6 @@
 namespace glass {
 namespace {
 
-// Row i of segment s's problem (lane 16s + i or 32s + i) from the wavefront's
-// np adjacent problems starting at base.  MASK and the padding follow
-// rows_load_lower (identity rows for a factorization, zero rows otherwise;
-// a segment past np holds only padding rows).
-template <int NB, bool MASK>
-GLASS_DEV void seg_load_rows(float (&a)[NB], const float* base, int np, int n, int s, int i) {
-    const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(base, (uint32_t)(np * n * n) * 4u);
-    const bool row = s < np && i < n;
-    const int off = s * n * n + i * n;
-#pragma unroll
-    for (int t = 0; t < NB / 4; ++t) {
-        f4_t v = {0.f, 0.f, 0.f, 0.f};
-        if (row && 4 * t <= i) {
-            if (i * n + 4 * t + 4 <= n * n) {
-                v = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off * 4, t * 16, 0));
-            } else {  // last row of the problem: element-wise, never past the problem
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (4 * t + e < n)
-                        v[e] = __builtin_bit_cast(
-                            float, __builtin_amdgcn_raw_buffer_load_b32(rs, (off + 4 * t + e) * 4, 0, 0));
-            }
-        }
-        if (MASK) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) a[4 * t + e] = (4 * t + e <= i) ? v[e] : 0.f;
-        } else {
-            const bool dblk = !row && t == (i >> 2);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) a[4 * t + e] = (dblk && e == (i & 3)) ? 1.f : v[e];
-        }
-    }
-}
-
-// Rows of L (strict upper +0) into the segment's LDS block.
-template <int NB>
-GLASS_DEV void seg_rows_to_lds(const float (&a)[NB], float* sb, int i) {
-    if (i < NB) {
-#pragma unroll
-        for (int t = 0; t < NB / 4; ++t) {
-            f4_t v;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = a[4 * t + e];
-            *reinterpret_cast<f4_t*>(sb + i * (NB + 4) + 4 * t) = v;
-        }
-    }
-}
-
-// The wavefront's np problems of L (contiguous in global memory) from the
-// segment blocks: one flat, coalesced copy (16-byte stores when n % 4 == 0
-// and dst is 16-byte aligned, so four consecutive elements share a row).
-template <int NB>
-GLASS_DEV void seg_store_L(float* __restrict__ dst, const float* buf, int np, int n, bool vec, int lane) {
-    const int nn = n * n;
-    const FastDiv fnn = make_fastdiv((uint32_t)nn), fn = make_fastdiv((uint32_t)n);
-    if (vec) {
-        for (int q = lane; q < np * nn / 4; q += 64) {
-            const int g = 4 * q;
-            const int s = (int)fdiv((uint32_t)g, fnn), rem = g - s * nn;
-            const int i = (int)fdiv((uint32_t)rem, fn), j = rem - i * n;
-            reinterpret_cast<f4_t*>(dst)[q] =
-                *reinterpret_cast<const f4_t*>(buf + s * NB * (NB + 4) + i * (NB + 4) + j);
-        }
-        return;
-    }
-    for (int g = lane; g < np * nn; g += 64) {
-        const int s = (int)fdiv((uint32_t)g, fnn), rem = g - s * nn;
-        const int i = (int)fdiv((uint32_t)rem, fn), j = rem - i * n;
-        dst[g] = buf[s * NB * (NB + 4) + i * (NB + 4) + j];
-    }
-}
-
 // op: 0 POTRF, 1 POSV, 2 POTRS, 3 TRSV (trans selects forward 0 / backward 1).
 template <int SEG, int NB, int OP>
 __global__ void __launch_bounds__(512) chol_seg(int n, int nrhs, int trans, int batch, float* __restrict__ A,

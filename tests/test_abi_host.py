@@ -185,7 +185,8 @@ def test_subwave_feasibility(glass):
         assert g.glass_placement_feasible(g.OPS[op], 17, 1, g.SCOPE_SUBWAVE, 1) == 0
     for op in ("se3_compose", "se3_inverse"):
         assert g.glass_placement_feasible(g.OPS[op], 8, 1, g.SCOPE_SUBWAVE, 1) == 0
-    assert g.glass_placement_feasible(g.OP_POSV_ADJOINT, 8, 1, g.SCOPE_SUBWAVE, 1) == 0
+    assert g.glass_placement_feasible(g.OP_POSV_ADJOINT, 32, 1, g.SCOPE_SUBWAVE, 1) == 1
+    assert g.glass_placement_feasible(g.OP_POSV_ADJOINT, 33, 1, g.SCOPE_SUBWAVE, 1) == 0
     assert g.glass_placement_feasible(g.OP_POSV, 8, 1, 4, 1) == g.ERR_INVALID_VALUE
 
 

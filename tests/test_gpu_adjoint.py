@@ -18,7 +18,7 @@ def env():
     return glass, torch
 
 
-@pytest.mark.parametrize("scope", ["thread", "wave"])
+@pytest.mark.parametrize("scope", ["thread", "wave", "subwave"])
 @pytest.mark.parametrize("n,r,batch", [(1, 1, 5), (6, 1, 67), (12, 1, 1100), (12, 3, 70), (16, 2, 130),
                                        (17, 1, 33), (33, 4, 65), (64, 1, 40), (64, 8, 9)])
 def test_adjoint_parity(env, scope, n, r, batch):
