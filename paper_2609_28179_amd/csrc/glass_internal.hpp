@@ -260,6 +260,13 @@ int launch_posv_ragged(int count, const int32_t* n, const int32_t* nrhs, const i
 inline bool riccati_size_ok(int nx, int nu) {
     return nx >= 1 && nu >= 1 && nu <= 16 && nx <= 56 && nx + nu <= 64 && (nu <= 8 || nx <= 48);
 }
+// The matrix-core form of the fused gain (riccati_mfma) serves nx >=
+// kRiccatiMfmaMinNx (measured: the LDS-staged form is faster at nx = 4, the
+// matrix-core form from nx = 12 at every batch); its LDS per wavefront is one
+// 16 x 20 exchange block.
+constexpr int kRiccatiMfmaMinNx = 9;
+constexpr int kRiccatiMfmaRegionFloats = 16 * 20;
+inline bool riccati_uses_mfma(int nx) { return nx >= kRiccatiMfmaMinNx; }
 size_t riccati_region_floats(int nx, int nu);
 int launch_riccati(int nx, int nu, int batch, int pack, const float* A, const float* B, const float* P,
                    const float* R, float* K, int32_t* info, void* stream);

@@ -3,7 +3,9 @@
 // Sec. IV-E measures fused against a chain of separate launches).
 //
 // One wavefront per problem (wave scope, P problems per workgroup), every
-// intermediate on chip:
+// intermediate on chip, in one of two forms.
+//
+// riccati_wave (LDS-staged, nx < kRiccatiMfmaMinNx):
 //   1. P (nx x nx) and B (nx x nu) are staged into LDS with coalesced loads,
 //      rows padded with zeros to the 8-wide buckets NX8 / NU8;
 //   2. lane c (c < nu + nx) loads column c of X = [B | A] into VGPRs and
@@ -17,12 +19,128 @@
 //      T (forward and backward substitution with L read as broadcasts) and
 //      stores column c of K (K row-major nu x nx, so a row's stores are
 //      consecutive lanes).
+//
+// riccati_mfma (nx >= kRiccatiMfmaMinNx): every product on the matrix cores,
+// in the blocked layouts of chol_blk.hpp (nx padded to 16-row blocks; nu <= 16
+// is one block).  With B_k in accumulator layout (lane (q, r) holds B[16k+4q+c][r])
+// the products chain without data movement:
+//   PB_i = sum_k P_ik B_k                 P_ik loaded row-wise (T layout)
+//   S    = R + sum_i B_i^T PB_i           B_i's registers are the T layout of B_i^T
+//   T_j  = sum_i PB_i^T A_ij              PB_i's registers are the T layout of PB_i^T
+//                                         (B^T P = (P B)^T: P is symmetric)
+//   K_j  = L^{-T} L^{-1} T_j              S = L L^T factored as a diagonal block
+// S's padded diagonal (orders nu..15) is the identity, so the factorization
+// and the solve run on a full 16 x 16 block.
 #include "device_common.hpp"
 #include "glass_internal.hpp"
 #include "chol_device.hpp"
+#include "chol_blk.hpp"
 
 namespace glass {
 namespace {
+
+// One 16 x 16 block of a row-major [rows][ld] matrix in T layout (lane
+// (q, r): row r0 + r, columns c0 + 4q .. c0 + 4q + 3; zero outside rows x cols).
+GLASS_DEV f4_t load_t_block(__amdgpu_buffer_rsrc_t rs, int ld, int rows, int cols, int r0, int c0, bool vec, int q,
+                            int r) {
+    f4_t v = {0.f, 0.f, 0.f, 0.f};
+    const int R = r0 + r, C = c0 + 4 * q;
+    if (R < rows) {
+        if (vec && C + 4 <= cols) {
+            v = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, (R * ld + C) * 4, 0, 0));
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (C + e < cols)
+                    v[e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (R * ld + C + e) * 4, 0, 0));
+        }
+    }
+    return v;
+}
+
+// The same block in accumulator layout (lane (q, r): rows r0 + 4q .. r0 + 4q + 3,
+// column c0 + r).
+GLASS_DEV f4_t load_acc_block(const float* M, int ld, int rows, int cols, int r0, int c0, int q, int r) {
+    f4_t v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int R = r0 + 4 * q + e, C = c0 + r;
+        v[e] = (R < rows && C < cols) ? M[R * ld + C] : 0.f;
+    }
+    return v;
+}
+
+template <int NXB>
+__global__ void __launch_bounds__(512) riccati_mfma(int nx, int nu, int batch, const float* __restrict__ A,
+                                                    const float* __restrict__ B, const float* __restrict__ P,
+                                                    const float* __restrict__ R, float* __restrict__ K,
+                                                    int32_t* __restrict__ info) {
+    extern __shared__ float lds[];
+    const int w = wave_index(), lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
+    const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
+    if (p >= batch) return;
+    float* xs = lds + (size_t)w * kRiccatiMfmaRegionFloats;
+    const float* Ap = A + p * nx * nx;
+    const float* Bp = B + p * nx * nu;
+    const float* Pp = P + p * nx * nx;
+    const float* Rp = R + p * nu * nu;
+    f4_t Bb[NXB];
+#pragma unroll
+    for (int k = 0; k < NXB; ++k) Bb[k] = load_acc_block(Bp, nu, nx, nu, 16 * k, 0, q, r);
+    const __amdgpu_buffer_rsrc_t rp = buffer_rsrc(Pp, (uint32_t)(nx * nx) * 4u);
+    const bool vec = (nx & 3) == 0;
+    f4_t PB[NXB];
+#pragma unroll
+    for (int i = 0; i < NXB; ++i) {
+        f4_t acc = zero4();
+#pragma unroll
+        for (int k = 0; k < NXB; ++k) acc = mma(load_t_block(rp, nx, nx, nx, 16 * i, 16 * k, vec, q, r), Bb[k], acc);
+        PB[i] = acc;
+    }
+    // S = R + B^T P B in accumulator layout, identity on the padded diagonal
+    f4_t S = load_acc_block(Rp, nu, nu, nu, 0, 0, q, r);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if (4 * q + e == r && r >= nu) S[e] = 1.f;
+#pragma unroll
+    for (int i = 0; i < NXB; ++i) S = mma(Bb[i], PB[i], S);
+    // rows of S to the lanes: lane (q, r) holds row r of S after the exchange
+#pragma unroll
+    for (int e = 0; e < 4; ++e) xs[(4 * q + e) * kXS + r] = S[e];
+    wave_sync();
+    float a[16];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const f4_t v = *reinterpret_cast<const f4_t*>(xs + r * kXS + 4 * u);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a[4 * u + e] = v[e];
+    }
+    wave_sync();
+    int f = 0;
+    float myinv = 1.f;
+    SegStep<16, 16, 0>::run(a, f, myinv);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) a[c] = c <= r ? a[c] : 0.f;
+    if (info && lane == 0) info[p] = f;
+    if (f != 0) return;  // K is not written for an indefinite S
+    const f4_t linv = tri_inverse(a, myinv, q, r);  // L^{-1} in T layout
+    f4_t lt[4];
+    lt[0] = linv;
+    transpose_blocks<1>(lt, xs, q, r);  // lt[0]: L^{-T} in T layout
+    float* Kp = K + p * nu * nx;
+#pragma unroll
+    for (int j = 0; j < NXB; ++j) {
+        f4_t t = zero4();
+#pragma unroll
+        for (int i = 0; i < NXB; ++i) t = mma(PB[i], load_acc_block(Ap, nx, nx, nx, 16 * i, 16 * j, q, r), t);
+        const f4_t kj = mma(lt[0], mma(linv, t, zero4()), zero4());  // L^{-T} (L^{-1} T_j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = 4 * q + e, col = 16 * j + r;
+            if (row < nu && col < nx) Kp[row * nx + col] = kj[e];
+        }
+    }
+}
 
 template <int NX8, int NU8>
 __global__ void __launch_bounds__(512) riccati_wave(int nx, int nu, int batch, const float* __restrict__ A,
@@ -131,7 +249,10 @@ __global__ void __launch_bounds__(512) riccati_wave(int nx, int nu, int batch, c
 
 }  // namespace
 
+static_assert(kRiccatiMfmaRegionFloats == 16 * kXS, "one exchange block");
+
 size_t riccati_region_floats(int nx, int nu) {
+    if (riccati_uses_mfma(nx)) return kRiccatiMfmaRegionFloats;
     const int x8 = bucket8_host(nx), u8 = bucket8_host(nu);
     return (size_t)x8 * x8 + (size_t)x8 * u8 + (size_t)u8 * u8 + u8;
 }
@@ -143,6 +264,16 @@ int launch_riccati(int nx, int nu, int batch, int pack, const float* A, const fl
     const int region = (int)riccati_region_floats(nx, nu);
     dim3 grid((unsigned)((batch + pack - 1) / pack)), block(64 * pack);
     const size_t lds = sizeof(float) * (size_t)region * pack;
+    if (riccati_uses_mfma(nx)) {
+        switch ((nx + 15) / 16) {
+#define RM(NXB) \
+    case NXB: hipLaunchKernelGGL((riccati_mfma<NXB>), grid, block, lds, st, nx, nu, batch, A, B, P, R, K, info); break;
+            RM(1) RM(2) RM(3) RM(4)
+#undef RM
+        default: return (int)hipErrorInvalidValue;
+        }
+        return (int)hipGetLastError();
+    }
     const int x8 = bucket8_host(nx), u8 = bucket8_host(nu);
 #define RK(X8, U8)                                                                                          \
     if (x8 == X8 && u8 == U8) {                                                                             \

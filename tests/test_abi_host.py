@@ -88,10 +88,10 @@ def test_riccati_and_gemm_ex_validation_paths(glass):
                                         stream=S) == g.ERR_INFEASIBLE_PLACEMENT
     assert g.glass_riccati_feasible(12, 4, 3) == g.ERR_INVALID_VALUE
     assert g.glass_riccati_feasible(12, 4, 8) == 1
-    # (48, 16): 3344 floats a wavefront, so four fit the 64 KiB budget and eight do not
-    assert g.glass_riccati_feasible(48, 16, 4) == 1 and g.glass_riccati_feasible(48, 16, 8) == 0
-    assert g.glass_riccati_gain_batched(48, 16, 3, FAKE, FAKE, FAKE, FAKE, FAKE, force=("wave", 8), stream=S) \
-        == g.ERR_INFEASIBLE_PLACEMENT
+    # the matrix-core form (nx >= 9) stages one 16 x 20 block a wavefront and
+    # the LDS-staged form (nx <= 8) at most 464 floats: every pack fits
+    for nx, nu in ((48, 16), (56, 8), (8, 16), (1, 1)):
+        assert all(g.glass_riccati_feasible(nx, nu, p) == 1 for p in (1, 2, 4, 8)), (nx, nu)
 
 
 def test_mlp_validation_paths(glass):
