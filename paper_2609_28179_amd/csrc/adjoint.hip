@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(512) adjoint_thread(int nrhs, int batch, const
                                                       const float* __restrict__ X, const float* __restrict__ G,
                                                       float* __restrict__ dB, float* __restrict__ dA) {
     extern __shared__ float lds[];
-    constexpr int SZ = N * N, S = SZ | 1;
+    constexpr int SZ = N * N, S = thread_stride(SZ);
     const int nt = blockDim.x, tid = threadIdx.x;
     const long long p0 = (long long)blockIdx.x * nt;
     const int cnt = (int)min((long long)nt, (long long)batch - p0);

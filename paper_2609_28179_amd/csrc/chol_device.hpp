@@ -15,26 +15,55 @@ namespace glass {
 #define TI(i, j) ((i) * ((i) + 1) / 2 + (j))
 
 GLASS_DEV int thread_stage_q_dev(int threads, int elems) {
-    int s = elems | 1;
+    int s = thread_stride(elems);
     int q = kStagePassFloats / s;
     if (q < 1) q = 1;
     return q < threads ? q : threads;
 }
 
+// The lane's problem in LDS at src / dst, at the stride thread_stride(N * N)
+// (16-byte aligned for even N): even orders move whole 16-byte pieces (the
+// pieces wholly above the diagonal are not read), odd orders single floats.
 template <int N>
 GLASS_DEV void tri_load(float (&a)[N * (N + 1) / 2], const float* src) {
+    if constexpr (N % 2 == 0) {
 #pragma unroll
-    for (int i = 0; i < N; ++i)
+        for (int t = 0; t < N * N / 4; ++t) {
+            if (4 * t / N == (4 * t + 3) / N && 4 * t % N > 4 * t / N) continue;  // one row, wholly above
+            const f4_t v = *reinterpret_cast<const f4_t*>(src + 4 * t);
 #pragma unroll
-        for (int j = 0; j <= i; ++j) a[TI(i, j)] = src[i * N + j];
+            for (int e = 0; e < 4; ++e) {
+                const int g = 4 * t + e, gi = g / N, gj = g % N;
+                if (gj <= gi) a[TI(gi, gj)] = v[e];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j) a[TI(i, j)] = src[i * N + j];
+    }
 }
 
 template <int N>
 GLASS_DEV void tri_store_full(const float (&a)[N * (N + 1) / 2], float* dst) {
+    if constexpr (N % 2 == 0) {
 #pragma unroll
-    for (int i = 0; i < N; ++i)
+        for (int t = 0; t < N * N / 4; ++t) {
+            f4_t v;
 #pragma unroll
-        for (int j = 0; j < N; ++j) dst[i * N + j] = j <= i ? a[TI(i, j)] : 0.f;
+            for (int e = 0; e < 4; ++e) {
+                const int g = 4 * t + e, gi = g / N, gj = g % N;
+                v[e] = gj <= gi ? a[TI(gi, gj)] : 0.f;
+            }
+            *reinterpret_cast<f4_t*>(dst + 4 * t) = v;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int j = 0; j < N; ++j) dst[i * N + j] = j <= i ? a[TI(i, j)] : 0.f;
+    }
 }
 
 // Left-looking Cholesky of the lane's triangle; returns info.
@@ -89,12 +118,12 @@ GLASS_DEV void tri_bwd(const float (&a)[N * (N + 1) / 2], const float (&dinv)[N]
 template <int N>
 GLASS_DEV void thread_load_tri(float (&a)[N * (N + 1) / 2], const float* __restrict__ base, float* lds,
                                int cnt, int tid, int nt) {
-    constexpr int SZ = N * N, S = SZ | 1;
+    constexpr int SZ = N * N, S = thread_stride(SZ);
     const int Q = thread_stage_q_dev(nt, SZ);
     const FastDiv fd = make_fastdiv(SZ);
     for (int s = 0; s < cnt; s += Q) {
         const int qn = min(Q, cnt - s);
-        stage_in<(N <= 8 ? 8 : 4)>(lds, base + (size_t)s * SZ, qn * SZ, fd, S, tid, nt);
+        stage_in<ThreadU<N>::v>(lds, base + (size_t)s * SZ, qn * SZ, fd, S, tid, nt);
         __syncthreads();
         if (tid >= s && tid < s + qn) tri_load<N>(a, lds + (tid - s) * S);
         __syncthreads();
@@ -104,7 +133,7 @@ GLASS_DEV void thread_load_tri(float (&a)[N * (N + 1) / 2], const float* __restr
 template <int N>
 GLASS_DEV void thread_store_tri(const float (&a)[N * (N + 1) / 2], float* __restrict__ base, float* lds,
                                 int cnt, int tid, int nt) {
-    constexpr int SZ = N * N, S = SZ | 1;
+    constexpr int SZ = N * N, S = thread_stride(SZ);
     const int Q = thread_stage_q_dev(nt, SZ);
     const FastDiv fd = make_fastdiv(SZ);
     for (int s = 0; s < cnt; s += Q) {

@@ -56,6 +56,7 @@ GLASS_DEV float readlane(float v, int lane) {
 }
 
 typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef float f2_t __attribute__((ext_vector_type(2)));
 
 GLASS_DEV bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
@@ -104,6 +105,12 @@ GLASS_DEV __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, uint32_t bytes) {
 // wavefront keeps U KiB in flight: the staging of a batch span is bandwidth-,
 // not latency-bound.  The per-load offsets are scalar, so the loads in flight
 // cost only their data VGPRs.
+//
+// When src and dst are 16-byte aligned and every 16-byte piece lands whole
+// at a 16-byte-aligned LDS address (rows unpadded, or rows and stride both
+// multiples of 4 floats), each piece is one 16-byte LDS write: consecutive
+// lanes then fill consecutive bank groups.  Otherwise the piece is split
+// into four 4-byte writes, which conflict (lanes 16 bytes apart).
 template <int U>
 GLASS_DEV void stage_in(float* dst, const float* __restrict__ src, int len, FastDiv cols, int ldst, int tid,
                         int nt) {
@@ -112,12 +119,30 @@ GLASS_DEV void stage_in(float* dst, const float* __restrict__ src, int len, Fast
     const float* base_p = reinterpret_cast<const float*>(addr & ~(uintptr_t)15);
     const int n4 = (shift + len + 3) >> 2;
     const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(base_p, (uint32_t)n4 * 16u);
-    const int d = (int)cols.d;
+    const int d = (int)cols.d, pad = ldst - d;
+    const bool wide = shift == 0 && aligned16(dst) && (pad == 0 || ((d & 3) == 0 && (ldst & 3) == 0));
     for (int base = 0; base < n4; base += U * nt) {
         f4_t v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u)
             v[u] = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, tid * 16, (base + u * nt) * 16, 0));
+        if (wide) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int g = 4 * (base + u * nt + tid);
+                if (g < len) {
+                    const int off = pad == 0 ? g : g + (int)fdiv((uint32_t)g, cols) * pad;
+                    if (g + 4 <= len) {
+                        *reinterpret_cast<f4_t*>(dst + off) = v[u];
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (g + e < len) dst[off + e] = v[u][e];
+                    }
+                }
+            }
+            continue;
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int q = base + u * nt + tid;
@@ -147,10 +172,72 @@ struct WaveU {
     static constexpr int v = NB * NB <= 512 ? 2 : NB * NB <= 1024 ? 4 : NB * NB <= 2048 ? 8 : 16;
 };
 
+// Loads per lane of stage_in for the thread scope at order N: the whole
+// pass in one round of loads up to order 8 (N * N / 4 pieces per lane).
+template <int N>
+struct ThreadU {
+    static constexpr int v = N * N <= 64 ? (N * N + 3) / 4 : 8;
+};
+
+// A lane's own row of L floats in LDS at p, whose float offset from a
+// 16-byte boundary is a multiple of AL (4, 2 or 1): 16-, 8- or 4-byte
+// accesses, the widest the alignment and length allow.  Used on the thread
+// scope's staged problems, whose stride (thread_stride) makes the wide
+// accesses of a wavefront's lanes fall on distinct bank groups.
+template <int L, int AL>
+GLASS_DEV void lds_row_get(float* v, const float* p) {
+    if constexpr (AL % 4 == 0 && L % 4 == 0) {
+#pragma unroll
+        for (int t = 0; t < L / 4; ++t) {
+            const f4_t x = *reinterpret_cast<const f4_t*>(p + 4 * t);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[4 * t + e] = x[e];
+        }
+    } else if constexpr (AL % 2 == 0 && L % 2 == 0) {
+#pragma unroll
+        for (int t = 0; t < L / 2; ++t) {
+            const f2_t x = *reinterpret_cast<const f2_t*>(p + 2 * t);
+            v[2 * t] = x[0];
+            v[2 * t + 1] = x[1];
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < L; ++t) v[t] = p[t];
+    }
+}
+
+template <int L, int AL>
+GLASS_DEV void lds_row_put(float* p, const float* v) {
+    if constexpr (AL % 4 == 0 && L % 4 == 0) {
+#pragma unroll
+        for (int t = 0; t < L / 4; ++t)
+            *reinterpret_cast<f4_t*>(p + 4 * t) = f4_t{v[4 * t], v[4 * t + 1], v[4 * t + 2], v[4 * t + 3]};
+    } else if constexpr (AL % 2 == 0 && L % 2 == 0) {
+#pragma unroll
+        for (int t = 0; t < L / 2; ++t) *reinterpret_cast<f2_t*>(p + 2 * t) = f2_t{v[2 * t], v[2 * t + 1]};
+    } else {
+#pragma unroll
+        for (int t = 0; t < L; ++t) p[t] = v[t];
+    }
+}
+
 // Inverse of stage_in: dst[g] = src_lds[(g / cols) * ldst + g % cols], with
-// 16-byte stores when dst is 16-byte aligned.
+// 16-byte stores when dst is 16-byte aligned (and 16-byte LDS reads under
+// the same condition as stage_in's 16-byte writes).
 GLASS_DEV void stage_out(float* __restrict__ dst, const float* src, int len, FastDiv cols, int ldst, int tid,
                          int nt) {
+    const int d = (int)cols.d, pad = ldst - d;
+    if (aligned16(dst) && aligned16(src) && (pad == 0 || ((d & 3) == 0 && (ldst & 3) == 0))) {
+        const int len4 = len >> 2;
+        f4_t* d4 = reinterpret_cast<f4_t*>(dst);
+        for (int q = tid; q < len4; q += nt) {
+            const int g = 4 * q;
+            d4[q] = *reinterpret_cast<const f4_t*>(src + (pad == 0 ? g : g + (int)fdiv((uint32_t)g, cols) * pad));
+        }
+        const int g = (len4 << 2) + tid;
+        if (g < len) dst[g] = src[g + (int)fdiv((uint32_t)g, cols) * pad];
+        return;
+    }
     if (aligned16(dst)) {
         const int len4 = len >> 2;
         f4_t* d4 = reinterpret_cast<f4_t*>(dst);
@@ -171,7 +258,22 @@ GLASS_DEV void stage_out_beta(float* __restrict__ dst, const float* src, int len
         stage_out(dst, src, len, cols, ldst, tid, nt);
         return;
     }
-    const int pad = ldst - (int)cols.d;
+    const int d = (int)cols.d, pad = ldst - d;
+    if (aligned16(dst) && aligned16(src) && (pad == 0 || ((d & 3) == 0 && (ldst & 3) == 0))) {
+        const int len4 = len >> 2;
+        f4_t* d4 = reinterpret_cast<f4_t*>(dst);
+        for (int q = tid; q < len4; q += nt) {
+            const int g = 4 * q;
+            const f4_t s = *reinterpret_cast<const f4_t*>(src + (pad == 0 ? g : g + (int)fdiv((uint32_t)g, cols) * pad));
+            f4_t o = d4[q];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] = fmaf(beta, o[e], s[e]);
+            d4[q] = o;
+        }
+        const int g = (len4 << 2) + tid;
+        if (g < len) dst[g] = fmaf(beta, dst[g], src[g + (int)fdiv((uint32_t)g, cols) * pad]);
+        return;
+    }
     for (int g = tid; g < len; g += nt) dst[g] = fmaf(beta, dst[g], src[g + (int)fdiv((uint32_t)g, cols) * pad]);
 }
 

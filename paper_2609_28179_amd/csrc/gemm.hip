@@ -24,7 +24,7 @@ namespace {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int stage_q(int threads, int elems) {
-    int s = elems | 1;
+    int s = thread_stride(elems);
     int q = kStagePassFloats / s;
     if (q < 1) q = 1;
     return q < threads ? q : threads;
@@ -35,7 +35,9 @@ template <int N>
 __global__ void __launch_bounds__(512) gemm_thread(int batch, float alpha, const float* __restrict__ A,
                                                    const float* __restrict__ B, float beta, float* __restrict__ C) {
     extern __shared__ float lds[];
-    constexpr int SZ = N * N, S = SZ | 1;
+    // problems at the stride thread_stride(SZ); each lane moves its own rows
+    // with the widest LDS accesses their alignment allows (RA floats)
+    constexpr int SZ = N * N, S = thread_stride(SZ), RA = N % 4 == 0 ? 4 : N % 2 == 0 ? 2 : 1;
     const int nt = blockDim.x, tid = threadIdx.x;
     const long long p0 = (long long)blockIdx.x * nt;
     const int cnt = (int)min((long long)nt, (long long)batch - p0);
@@ -44,31 +46,27 @@ __global__ void __launch_bounds__(512) gemm_thread(int batch, float alpha, const
     const int Q = stage_q(nt, SZ);
     for (int s = 0; s < cnt; s += Q) {
         const int qn = min(Q, cnt - s);
-        stage_in<(N <= 8 ? 8 : 4)>(lds, B + (p0 + s) * SZ, qn * SZ, fd, S, tid, nt);
+        stage_in<ThreadU<N>::v>(lds, B + (p0 + s) * SZ, qn * SZ, fd, S, tid, nt);
         __syncthreads();
-        if (tid >= s && tid < s + qn) {
-            const float* src = lds + (tid - s) * S;
-#pragma unroll
-            for (int e = 0; e < SZ; ++e) b[e] = src[e];
-        }
+        if (tid >= s && tid < s + qn) lds_row_get<SZ, (S % 4 == 0 ? 4 : 1)>(b, lds + (tid - s) * S);
         __syncthreads();
     }
-    stage_in<(N <= 8 ? 8 : 4)>(lds, A + p0 * SZ, cnt * SZ, fd, S, tid, nt);
+    stage_in<ThreadU<N>::v>(lds, A + p0 * SZ, cnt * SZ, fd, S, tid, nt);
     __syncthreads();
     if (tid < cnt) {
         float* a = lds + tid * S;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            float ar[N];
-#pragma unroll
-            for (int k = 0; k < N; ++k) ar[k] = a[i * N + k];
+            float ar[N], cr[N];
+            lds_row_get<N, RA>(ar, a + i * N);
 #pragma unroll
             for (int j = 0; j < N; ++j) {
                 float c = 0.f;
 #pragma unroll
                 for (int k = 0; k < N; ++k) c = fmaf(ar[k], b[k * N + j], c);
-                a[i * N + j] = alpha * c;
+                cr[j] = alpha * c;
             }
+            lds_row_put<N, RA>(a + i * N, cr);
         }
     }
     __syncthreads();

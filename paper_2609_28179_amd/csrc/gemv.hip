@@ -13,7 +13,7 @@ namespace glass {
 namespace {
 
 __device__ __forceinline__ int stage_q(int threads, int elems) {
-    int s = elems | 1;
+    int s = thread_stride(elems);
     int q = kStagePassFloats / s;
     if (q < 1) q = 1;
     return q < threads ? q : threads;
@@ -23,7 +23,9 @@ template <int N>
 __global__ void __launch_bounds__(512) gemv_thread(int batch, float alpha, const float* __restrict__ A,
                                                    const float* __restrict__ x, float beta, float* __restrict__ y) {
     extern __shared__ float lds[];
-    constexpr int SZ = N * N, S = SZ | 1, SV = N | 1;
+    // A at the stride thread_stride(SZ), rows read with the widest LDS
+    // accesses their alignment allows (RA floats)
+    constexpr int SZ = N * N, S = thread_stride(SZ), SV = N | 1, RA = N % 4 == 0 ? 4 : N % 2 == 0 ? 2 : 1;
     const int nt = blockDim.x, tid = threadIdx.x;
     const long long p0 = (long long)blockIdx.x * nt;
     const int cnt = (int)min((long long)nt, (long long)batch - p0);
@@ -41,15 +43,17 @@ __global__ void __launch_bounds__(512) gemv_thread(int batch, float alpha, const
     const FastDiv fa = make_fastdiv(SZ);
     for (int s = 0; s < cnt; s += Q) {
         const int qn = min(Q, cnt - s);
-        stage_in<(N <= 8 ? 8 : 4)>(lds, A + (p0 + s) * SZ, qn * SZ, fa, S, tid, nt);
+        stage_in<ThreadU<N>::v>(lds, A + (p0 + s) * SZ, qn * SZ, fa, S, tid, nt);
         __syncthreads();
         if (tid >= s && tid < s + qn) {
             const float* a = lds + (tid - s) * S;
 #pragma unroll
             for (int i = 0; i < N; ++i) {
+                float ar[N];
+                lds_row_get<N, RA>(ar, a + i * N);
                 float acc = 0.f;
 #pragma unroll
-                for (int j = 0; j < N; ++j) acc = fmaf(a[i * N + j], xr[j], acc);
+                for (int j = 0; j < N; ++j) acc = fmaf(ar[j], xr[j], acc);
                 ys[tid * SV + i] = alpha * acc;
             }
         }

@@ -17,8 +17,20 @@ constexpr size_t kLdsBudgetBytes = 65536;  // fixed per-workgroup LDS budget
 constexpr int kThreadMaxN = 16;            // thread scope: problem in one lane's VGPRs
 constexpr int kThreadGemmMaxN = 12;        // thread GEMM holds all of B in VGPRs
 constexpr int kStagePassFloats = 8192;     // thread scope: floats staged per LDS pass
+constexpr int kSe3Stride = 20;             // thread-scope LDS stride of one 4x4 transform (thread_stride(16))
 
 inline int odd_up(int x) { return x | 1; }
+
+// LDS stride (floats) of one staged thread-scope problem of sz floats.  Odd
+// sizes are unpadded: the staging is then a straight 16-byte copy, and lanes
+// reading their own problems element by element at an odd stride hit
+// distinct banks.  A multiple of 4 gets a stride of 4 x an odd number (sz or
+// sz + 4): every problem stays 16-byte aligned, the staging still writes
+// whole 16-byte pieces, and lanes reading their problems with 16-byte (or
+// 8-byte) accesses hit distinct bank groups.  Other sizes get sz + 1.
+constexpr int thread_stride(int sz) {
+    return (sz & 1) ? sz : (sz & 3) ? sz + 1 : ((sz >> 2) & 1) ? sz : sz + 4;
+}
 inline int round4(int x) { return (x + 3) & ~3; }
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
@@ -32,7 +44,7 @@ inline int wg_scope_threads(int n) {
 
 // Problems per LDS staging pass of the thread scope (see thread kernels).
 inline int thread_stage_q(int threads, int elems) {
-    int s = odd_up(elems);
+    int s = thread_stride(elems);
     int q = kStagePassFloats / s;
     if (q < 1) q = 1;
     return q < threads ? q : threads;
@@ -134,7 +146,7 @@ inline bool subwave_op(glass_op_t op) {
 // LDS floats of a thread-scope workgroup of `t` lanes.
 inline size_t thread_lds_floats(const Shape& s, int t) {
     const int n = s.n;
-    const int sz = odd_up(n * n);
+    const int sz = thread_stride(n * n);
     const size_t pass = (size_t)thread_stage_q(t, n * n) * sz;
     switch (s.op) {
     case GLASS_OP_POTRF:
@@ -153,9 +165,9 @@ inline size_t thread_lds_floats(const Shape& s, int t) {
     case GLASS_OP_GEMM:
         return (size_t)t * sz;
     case GLASS_OP_SE3_COMPOSE:
-        return 2 * (size_t)t * 17;
+        return 2 * (size_t)t * kSe3Stride;
     case GLASS_OP_SE3_INVERSE:
-        return (size_t)t * 17;
+        return (size_t)t * kSe3Stride;
     case GLASS_OP_POSV_ADJOINT:
         return pass + 2 * (size_t)t * odd_up(n * s.nrhs);
     }

@@ -12,7 +12,10 @@
 namespace glass {
 namespace {
 
-constexpr int kS = 17;  // LDS stride of one staged transform (odd)
+// LDS stride of one staged transform: 16-byte aligned, and 4 x an odd number
+// so the lanes' 16-byte row accesses fall on distinct bank groups.
+constexpr int kS = kSe3Stride;
+static_assert(kS == thread_stride(16), "transform stride");
 
 GLASS_DEV void compose_regs(const float (&a)[12], const float (&b)[12], float (&o)[12]) {
 #pragma unroll
@@ -54,22 +57,22 @@ __global__ void __launch_bounds__(512) se3_thread(int inverse, int batch, const 
     __syncthreads();
     if (tid < cnt) {
         float a[12], o[12];
-#pragma unroll
-        for (int e = 0; e < 12; ++e) a[e] = sa[tid * kS + e];
+        lds_row_get<12, 4>(a, sa + tid * kS);
         if (inverse) {
             inverse_regs(a, o);
         } else {
             float b[12];
-#pragma unroll
-            for (int e = 0; e < 12; ++e) b[e] = sb[tid * kS + e];
+            lds_row_get<12, 4>(b, sb + tid * kS);
             compose_regs(a, b, o);
         }
+        float w[16];
 #pragma unroll
-        for (int e = 0; e < 12; ++e) sa[tid * kS + e] = o[e];
-        sa[tid * kS + 12] = 0.f;
-        sa[tid * kS + 13] = 0.f;
-        sa[tid * kS + 14] = 0.f;
-        sa[tid * kS + 15] = 1.f;
+        for (int e = 0; e < 12; ++e) w[e] = o[e];
+        w[12] = 0.f;
+        w[13] = 0.f;
+        w[14] = 0.f;
+        w[15] = 1.f;
+        lds_row_put<16, 4>(sa + tid * kS, w);
     }
     __syncthreads();
     stage_out(Tout + p0 * 16, sa, cnt * 16, f16, kS, tid, nt);
