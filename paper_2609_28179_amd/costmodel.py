@@ -47,7 +47,7 @@ FEATURE_OPS = ("gemm", "gemv", "potrf", "potrs", "posv", "trsv", "se3_compose", 
 D = 15
 HIDDEN = 64
 TOP_K = 3
-STEPS = 10000
+STEPS = 2000
 LR = 1e-3   # chosen by leave-one-order-out cross-validation on the training sweep
 SEED = 0
 
