@@ -29,6 +29,10 @@ def normwise(got, ref):
 
 
 def guarded(torch, arr_np, dev, pad=64):
+    return _guarded(torch, arr_np, dev, pad)
+
+
+def _guarded(torch, arr_np, dev, pad):
     """Device copy of arr with NaN guard bands of `pad` floats on each side.
     Returns (full_buffer, view); pad keeps 256-byte alignment."""
     flat = np.ascontiguousarray(arr_np).reshape(-1)
@@ -44,14 +48,20 @@ def guards_intact(full, pad=64):
 
 
 def run_case(glass, torch, op, n, batch, scope, pack, nrhs=1, trans=0, seed_extra=0, dev="cuda:0",
-             case=None, check_guards=True):
+             case=None, check_guards=True, shift=0):
     """Run one case on the GPU and on the oracle.  Returns a dict with 'err'
-    (max normwise error), 'status', and bit-exact flags where they apply."""
+    (max normwise error), 'status', and bit-exact flags where they apply.
+    shift > 0 starts every operand `shift` floats past a 256-byte boundary
+    (4-byte aligned only; the contract allows it)."""
     if case is None:
         case = inputs.make_case(op, n, batch, cfg=100, nrhs=nrhs, extra=seed_extra)
     force = (scope, pack)
     out = {"status": None}
     bufs = []
+    pad = 64 + shift
+
+    def guarded(torch, arr_np, dev):
+        return _guarded(torch, arr_np, dev, pad)
 
     def g(name):
         full, view = guarded(torch, case[name], dev)
@@ -132,5 +142,5 @@ def run_case(glass, torch, op, n, batch, scope, pack, nrhs=1, trans=0, seed_extr
     else:
         raise ValueError(op)
     if check_guards:
-        out["guards"] = all(guards_intact(b) for b in bufs)
+        out["guards"] = all(guards_intact(b, pad) for b in bufs)
     return out

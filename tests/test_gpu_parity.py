@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 OPS_N = ("gemm", "gemv", "potrf", "potrs", "posv", "trsv")
 N_WIDE = (1, 2, 3, 4, 5, 6, 7, 8, 9, 12, 15, 16, 17, 20, 24, 31, 32, 33, 48, 63, 64)
-N_THREAD = (1, 2, 3, 4, 5, 6, 7, 8, 11, 12, 13, 16)
+N_THREAD = (1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 16)
 N_PACKS = (3, 6, 16, 33, 64)
 BATCHES = (1, 67, 1100)
 
@@ -137,3 +137,24 @@ def test_bit_identical_across_packs(env, op, scope):
             outs.append(res["out"])
         for o in outs[1:]:
             assert np.array_equal(o.view(np.uint32), outs[0].view(np.uint32)), f"{op} n={n} {scope}"
+
+
+# operands 4, 8 and 12 bytes past a 16-byte boundary: every staging and
+# store path that widens to 16 bytes must fall back (contract: 4-byte aligned)
+N_SHIFT = {"thread": (3, 4, 6, 7, 8, 10, 16), "wave": (3, 8, 20, 25, 32, 64), "workgroup": (3, 16, 33),
+           "subwave": (4, 7, 12, 16, 24, 32)}
+
+
+@pytest.mark.parametrize("scope", ["thread", "wave", "workgroup", "subwave"])
+@pytest.mark.parametrize("op", OPS_N + ("se3_compose", "se3_inverse"))
+def test_parity_unaligned_operands(env, op, scope):
+    glass, torch = env
+    fails = []
+    for n in ((4,) if op.startswith("se3") else N_SHIFT[scope]):
+        if glass.glass_placement_feasible(glass.OPS[op], n, 1, glass.SCOPES[scope], 1) != 1:
+            continue
+        for shift in (1, 2, 3):
+            label = f"{op} n={n} batch=67 {scope}/P=1 shift={shift}"
+            _say(label)
+            _check(run_case(glass, torch, op, n, 67, scope, 1, shift=shift), label, fails)
+    assert not fails, "\n".join(fails[:40])
