@@ -36,6 +36,7 @@ DEFAULT_SWEEP = os.path.join(PKG, "tuning", "sweep_gfx950.jsonl")
 DEFAULT_INC = os.path.join(PKG, "csrc", "glass_table_gfx950.inc")
 OP_ORDER = ("gemm", "gemv", "potrf", "potrs", "posv", "trsv", "se3_compose", "se3_inverse")
 MARGIN = 1.05
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E spec peak
 
 
 def _git_hash():
@@ -178,16 +179,26 @@ def summary(args):
         ratios.append(fixed / c["median_us"])
         gaps.append(worst / c["median_us"])
         ab = timing.alg_bytes(op, n) * b
+        # the attainable time is the larger of the HBM time at the spec peak
+        # and the measured launch floor; the cell is bound by that one
+        t_hbm = ab / (HBM_PEAK_GBPS * 1e3)
+        floor = meta["floor_us"] if meta else 0.0
+        bound = "HBM" if t_hbm >= floor else "launch"
         lines.append(f"| {op} | {n} | {b} | {'TWGS'[c['winner'][0]]}{c['winner'][1]} | {c['median_us']:.2f} | "
                      f"{fixed:.2f} | {fixed / c['median_us']:.2f} | {worst / c['median_us']:.1f} | "
-                     f"{ab / (c['median_us'] * 1e-6) / 1e9:.0f} | {len(c['margin'])} |")
+                     f"{ab / (c['median_us'] * 1e-6) / 1e9:.0f} | {100 * t_hbm / c['median_us']:.1f} | "
+                     f"{100 * max(t_hbm, floor) / c['median_us']:.0f} | {bound} | {len(c['margin'])} |")
     g = lambda v: float(np.exp(np.mean(np.log(v))))
     head = [f"floor {meta['floor_us']:.2f} us/launch, copy {meta['copy_gbps']:.0f} GB/s" if meta else "",
             f"cells {len(ch)}; tuned / fixed-wave(P=1) speedup: geomean {g(ratios):.2f}x, max {max(ratios):.1f}x; "
             f"best/worst placement gap: median {np.median(gaps):.1f}x, max {max(gaps):.1f}x",
             "",
-            "| op | n | batch | tuned | tuned us | wave/P1 us | speedup | worst/best | alg GB/s | margin set |",
-            "|---|---|---|---|---|---|---|---|---|---|"]
+            "Columns: % HBM = algorithmic bytes at the 8 TB/s spec peak over the tuned time; % attainable = "
+            "max(that HBM time, launch floor) over the tuned time; bound = whichever of the two is larger.",
+            "",
+            "| op | n | batch | tuned | tuned us | wave/P1 us | speedup | worst/best | alg GB/s | % HBM | "
+            "% attainable | bound | margin set |",
+            "|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
     text = "\n".join(head + lines) + "\n"
     if args.out:
         with open(args.out, "w") as f:

@@ -56,3 +56,30 @@ def test_ragged_table_is_the_ragged_sweep_argmin():
             best[r["class"]] = (key, r["scope"])
     assert sorted(best) == list(range(8))
     assert built == [glass.RAGGED_SCOPES[best[k][1]] for k in range(8)]
+
+
+def test_table_choice_is_stable_across_half_sweeps():
+    """The pin of the table choice itself: a re-measurement must pick a
+    placement inside the first measurement's margin set (within 5 % of its
+    best).  Every placement of a cell was timed in the same 20 paired,
+    shuffled rounds, so the even and the odd rounds are two independent
+    half-sweeps; each half's winner must be within the margin of the other
+    half's best.  Cells faster than 3 launch floors (a few microseconds,
+    where a 10-sample median moves by a few tenths of a microsecond) get
+    twice the margin."""
+    import numpy as np
+    meta = json.loads(open(autotune.DEFAULT_SWEEP).readline())
+    by_cell = {}
+    for r in _records():
+        by_cell.setdefault((r["op"], r["n"], r["batch"]), {})[(r["scope"], r["pack"])] = np.array(r["samples_us"])
+    bad = []
+    for cell, samples in by_cell.items():
+        halves = [{pl: float(np.median(s[sl])) for pl, s in samples.items()} for sl in (slice(0, None, 2),
+                                                                                         slice(1, None, 2))]
+        for a, b in ((0, 1), (1, 0)):
+            win = min(halves[a], key=lambda pl: (halves[a][pl], pl))
+            best = min(halves[b].values())
+            margin = autotune.MARGIN if best >= 3 * meta["floor_us"] else 2 * autotune.MARGIN - 1
+            if halves[b][win] > best * margin:
+                bad.append((cell, win, round(halves[b][win] / best, 3)))
+    assert not bad, bad
