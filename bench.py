@@ -228,7 +228,8 @@ def main():
         extras = {"posv_small": workloads.posv_small(glass, torch),
                   "ragged": workloads.ragged(glass, torch),
                   "adjoint": workloads.adjoint(glass, torch),
-                  "riccati_gain": workloads.riccati_gain(glass, torch)}
+                  "riccati_gain": workloads.riccati_gain(glass, torch),
+                  "batch1_latency": workloads.batch1_latency(glass, torch)}
         log(f"workloads ({time.time() - t0:.1f} s): " + json.dumps(extras))
 
     cpu = None

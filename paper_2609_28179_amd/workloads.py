@@ -1,10 +1,11 @@
 """Timings of the workloads beside the placement-sweep step: the plain small
-POSV, the ragged batch against per-size launches, and the Cholesky-solve
-adjoint.  Each returns a small dict for the benchmark's JSON line.
+POSV, the ragged batch against per-size launches, the Cholesky-solve
+adjoint, the LQR gain, and single-problem latency.  Each returns a small
+dict for the benchmark's JSON line.
 
-All timings are device-side: HIP graphs replayed between two events, inputs
-resident in HBM, destructive inputs restored from a pristine copy outside the
-events.
+All timings but the single-problem latency are device-side: HIP graphs
+replayed between two events, inputs resident in HBM, destructive inputs
+restored from a pristine copy outside the events.
 """
 from __future__ import annotations
 
@@ -157,4 +158,41 @@ def riccati_gain(glass, torch, cells=((12, 4, 64), (32, 8, 65536)), rounds=20):
         out.append({"workload": f"riccati_gain nx={nx} nu={nu} batch={batch}", "fused_us": round(fu[0], 2),
                     "fused_pack": fu[1], "unfused_us": round(un, 2), "fused_speedup": round(un / fu[0], 3),
                     "fused_gbps": round(riccati.alg_bytes(nx, nu) * batch / (fu[0] * 1e-6) / 1e9, 1)})
+    return out
+
+
+def batch1_latency(glass, torch, cells=(("posv", 6), ("posv", 32), ("posv", 64), ("gemm", 64), ("trsv", 64),
+                                        ("se3_compose", 4)), reps=200):
+    """One problem per call at the table's placement, each call synchronized
+    on its own: the host round trip (enqueue to completion, what a control
+    loop that waits on every solve sees) and the device time of the launch
+    between two events, medians over `reps` calls.  The sweep's batch-1
+    cells time back-to-back launches instead, so they hide the round trip."""
+    import time
+    dev = torch.device("cuda:0")
+    out = {}
+    for op, n in cells:
+        bufs = timing.make_set(torch, op, n, 1, dev, seed=11)
+        pristine = {k: bufs[k].clone() for k in timing.DESTRUCTIVE.get(op, ())}
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        host, devt = [], []
+        for i in range(reps + 10):
+            for k, v in pristine.items():
+                bufs[k].copy_(v)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ev0.record()
+            st = timing.launch(glass, op, n, 1, bufs, None)
+            ev1.record()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            if st != 0:
+                raise RuntimeError(f"{op} n={n}: status {st}")
+            if i >= 10:
+                host.append((t1 - t0) * 1e6)
+                devt.append(ev0.elapsed_time(ev1) * 1e3)
+        p = glass.glass_query_placement(glass.OPS[op], n, 1)
+        out[f"{op} n={n}"] = {"table": f"{glass.SCOPE_NAMES[p.scope]}/P={p.pack}",
+                              "host_round_trip_us": round(_median_us(host), 2),
+                              "device_us": round(_median_us(devt), 2)}
     return out
