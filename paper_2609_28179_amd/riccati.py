@@ -5,8 +5,12 @@ and solve primitives or by a fused ``riccati_gain``; Sec. IV-E measures the
 two and finds that the winner flips with the batch size, making composition
 granularity one more measured placement.  Here:
 
-  fused    one launch of glass_riccati_gain_batched (wave scope, every
-           intermediate in VGPRs / LDS), pack P in {1, 2, 4, 8};
+  fused    one launch of glass_riccati_gain_batched, one problem per
+           wavefront, every intermediate in VGPRs / LDS, pack P in
+           {1, 2, 4, 8}: for nx >= 9 every product runs on the matrix
+           cores in 16 x 16 tiles and S = R + B^T P B is factored as one
+           diagonal tile; below, P and B are staged in LDS and the
+           products read them as broadcasts;
   unfused  the chain of library calls, each its own launch at the table's
            placement:  PB = P B (GEMM);  S = R (device copy);
            S += B^T PB (GEMM, transposed A);  PA = P A (GEMM);
