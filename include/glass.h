@@ -29,8 +29,10 @@
  *   - Placement: `force == NULL` looks the call up in the built-in gfx950
  *     table (the paper's bare call); if the tabulated placement is infeasible
  *     for this exact call (e.g. nrhs or a rectangular GEMM exceeds what that
- *     scope supports) the call falls back to wavefront scope, pack 1, which is
- *     feasible for every supported shape.  `force != NULL` runs exactly that
+ *     scope supports) the call takes the first feasible of: the tabulated
+ *     scope at pack 1, sub-wave, wavefront, workgroup scope, each at pack 1
+ *     (wavefront / pack 1 is feasible for every supported shape).
+ *     `force != NULL` runs exactly that
  *     placement (only its `scope` and `pack` fields are read) or returns
  *     GLASS_ERR_INFEASIBLE_PLACEMENT without enqueuing anything.
  *   - Thread safety: stateless apart from a per-process, read-only device

@@ -51,8 +51,11 @@ bool valid_force(const glass_placement_t* f) {
     return f->pack == 1 || f->pack == 2 || f->pack == 4 || f->pack == 8;
 }
 
-// Resolve the placement of a validated call: forced, else table, else the
-// wavefront / pack-1 fallback.
+// Resolve the placement of a validated call: forced, else the table's
+// placement, else (the table is keyed by order and batch only, so nrhs or a
+// rectangular GEMM can exceed what its placement supports) the first
+// feasible of: the table's scope at pack 1, sub-wave, wavefront, workgroup,
+// each at pack 1.  Wavefront / pack 1 runs every supported shape.
 glass_status_t resolve(const Shape& s, long long batch, const glass_placement_t* force, Geometry* g) {
     if (force) {
         if (!make_geometry(s, force->scope, force->pack, batch, g)) return GLASS_ERR_INFEASIBLE_PLACEMENT;
@@ -66,6 +69,8 @@ glass_status_t resolve(const Shape& s, long long batch, const glass_placement_t*
     int scope, pack;
     table_lookup(s.op, order, batch, &scope, &pack);
     if (make_geometry(s, scope, pack, batch, g)) return GLASS_OK;
+    if (pack != 1 && make_geometry(s, scope, 1, batch, g)) return GLASS_OK;
+    if (make_geometry(s, GLASS_SCOPE_SUBWAVE, 1, batch, g)) return GLASS_OK;
     if (make_geometry(s, GLASS_SCOPE_WAVE, 1, batch, g)) return GLASS_OK;
     if (make_geometry(s, GLASS_SCOPE_WORKGROUP, 1, batch, g)) return GLASS_OK;
     return GLASS_ERR_INFEASIBLE_PLACEMENT;
