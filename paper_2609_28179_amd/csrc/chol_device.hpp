@@ -242,9 +242,9 @@ GLASS_DEV float writelane(float v, float old) {
 // updates the rest of its row in VGPRs (a[K] -= l_iJ * l_KJ, one v_fmac each).
 template <int NB, int J, int K>
 struct WaveUpd {
-    static GLASS_DEV void run(float (&a)[NB], const float (&R)[4], float nv) {
-        fmac_bcast<K % 16>(a[K], R[K / 16], nv);
-        WaveUpd<NB, J, K + 1>::run(a, R, nv);
+    static GLASS_DEV void run(float (&a)[NB], const float (&R)[4], float m) {
+        fnmac_bcast<K % 16>(a[K], R[K / 16], m);
+        WaveUpd<NB, J, K + 1>::run(a, R, m);
     }
 };
 template <int NB, int J>
@@ -252,24 +252,32 @@ struct WaveUpd<NB, J, NB> {
     static GLASS_DEV void run(float (&)[NB], const float (&)[4], float) {}
 };
 
+// A step does not test its pivot: 1/L_JJ = rsq(d) is kept per lane, and rsq
+// is not finite exactly when !(d > 0) (+inf at +0, -inf at -0, NaN below 0
+// and at NaN, finite and positive for every positive finite d, +0 at +inf),
+// so the first non-finite lane after the last step is info - 1.
 template <int NB, int J>
 struct WaveStep {
     static GLASS_DEV void run(float (&a)[NB], int lane, int& info, float& myinv) {
         const float d = readlane(a[J], J);
-        if (!(d > 0.f) && info == 0) info = J + 1;
         const float inv = rsq(d);
-        const float v = a[J] * inv;  // in lane J, a[J] is the pivot itself: v = sqrt(d)
+        float v = a[J] * inv;  // in lane J, a[J] is the pivot itself: v = sqrt(d)
         myinv = lane_select<J>(myinv, inv);
-        a[J] = v;
         float R[4];
-        replicate_rows<(NB + 15) / 16>(v, R);
-        WaveUpd<NB, J, J + 1>::run(a, R, -v);
+        if ((NB + 15) / 16 == 1) {
+            asm volatile("s_nop 1" : "+v"(v));  // wait states before the DPP reads of v
+            R[0] = R[1] = R[2] = R[3] = v;
+        } else {
+            replicate_rows<(NB + 15) / 16>(v, R);
+        }
+        a[J] = v;
+        WaveUpd<NB, J, J + 1>::run(a, R, v);
         WaveStep<NB, J + 1>::run(a, lane, info, myinv);
     }
 };
 template <int NB>
 struct WaveStep<NB, NB> {
-    static GLASS_DEV void run(float (&)[NB], int, int&, float&) {}
+    static GLASS_DEV void run(float (&)[NB], int, int& info, float& myinv) { info = first_nonfinite<64>(myinv); }
 };
 
 // Factor the rows in place (identity rows past the order); returns info, sets
@@ -495,7 +503,7 @@ template <int SEG, int NB, int J>
 struct SegStep {
     static GLASS_DEV void run(float (&a)[NB], int& info, float& myinv) {
         float R[4];
-        float d, nv;
+        float d, m;
         if (SEG == 16) {
             d = seg_bcast<SEG, J>(a[J]);
         } else {
@@ -504,25 +512,28 @@ struct SegStep {
                          : "=v"(d)
                          : "v"(R[J / 16]), "n"(J % 16));
         }
-        if (!(d > 0.f) && info == 0) info = J + 1;
         const float inv = rsq(d);
         myinv = seg_select<SEG, J>(myinv, inv);
         if (SEG == 16) {
-            const float v = a[J] * inv;  // in lane J of the segment, a[J] is the pivot itself
+            float v = a[J] * inv;  // in lane J of the segment, a[J] is the pivot itself
+            asm volatile("s_nop 1" : "+v"(v));  // wait states before the DPP reads of v
             a[J] = v;
-            replicate_rows<1>(v, R);
-            nv = -v;
+            R[0] = R[1] = R[2] = R[3] = v;
+            m = v;
         } else {
-            nv = -(a[J] * (inv * inv));
+            m = a[J] * (inv * inv);
             a[J] *= inv;
         }
-        WaveUpd<NB, J, J + 1>::run(a, R, nv);
+        WaveUpd<NB, J, J + 1>::run(a, R, m);
         SegStep<SEG, NB, J + 1>::run(a, info, myinv);
     }
 };
+// The pivots are tested once, after the last step, as in WaveStep: myinv of
+// a segment's lane i is 1 / L_ii (1 past the order), not finite exactly for
+// the failed pivots.
 template <int SEG, int NB>
 struct SegStep<SEG, NB, NB> {
-    static GLASS_DEV void run(float (&)[NB], int&, float&) {}
+    static GLASS_DEV void run(float (&)[NB], int& info, float& myinv) { info = first_nonfinite<SEG>(myinv); }
 };
 
 template <int SEG, int NB, int K, int RG>

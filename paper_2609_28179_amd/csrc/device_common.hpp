@@ -342,4 +342,28 @@ GLASS_DEV void fmac_bcast(float& acc, float src, float m) {
                  : "v"(src), "v"(m), "n"(C));
 }
 
+// acc -= bcast_c(src) * m: the same op with the negate modifier on m.
+template <int C>
+GLASS_DEV void fnmac_bcast(float& acc, float src, float m) {
+    asm volatile("v_fmac_f32_dpp %0, %1, -%2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                 : "+v"(acc)
+                 : "v"(src), "v"(m), "n"(C));
+}
+
+// 1 + the position within its group of `width` lanes (16, 32 or 64) of the
+// first lane whose v is not finite, 0 if there is none; every lane of a
+// group gets its group's value.  Lanes the wave does not execute count as
+// finite.
+template <int W>
+GLASS_DEV int first_nonfinite(float v) {
+    const unsigned long long m = __ballot(!__builtin_isfinite(v));
+    if constexpr (W == 64) {
+        return m ? __ffsll((long long)m) : 0;
+    } else {
+        const int shift = (int)(__lane_id() & ~(W - 1));
+        const unsigned int bits = (unsigned int)(m >> shift) & (unsigned int)((1ull << W) - 1);
+        return bits ? __ffs(bits) : 0;
+    }
+}
+
 }  // namespace glass
