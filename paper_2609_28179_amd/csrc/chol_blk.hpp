@@ -136,10 +136,21 @@ struct InvStep<16> {
     static GLASS_DEV void run(float (&)[4], const float (&)[16]) {}
 };
 
+// -(bcast_K(s) * a): the broadcast folded into the multiply, the negation
+// its source modifier; s_nop 1 gives the DPP read of s its wait states.
+template <int K>
+GLASS_DEV float neg_mul_bcast(float s, float a) {
+    float r;
+    asm volatile("s_nop 1\n\tv_mul_f32_dpp %0, %1, -%2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                 : "=v"(r)
+                 : "v"(s), "v"(a), "n"(K));
+    return r;
+}
+
 template <int K>
 struct InvCoef {
     static GLASS_DEV void run(const float (&a)[16], float myinv, float (&m)[16]) {
-        m[K] = seg_select<16, K>(-(a[K] * seg_bcast<16, K>(myinv)), 0.f);
+        m[K] = seg_select<16, K>(neg_mul_bcast<K>(myinv, a[K]), 0.f);
         InvCoef<K + 1>::run(a, myinv, m);
     }
 };

@@ -87,3 +87,60 @@ def test_planted_failures(env, op, scope):
         if not (guards_intact(Af) and guards_intact(Bf)):
             fails.append(f"{label}: guard band written")
     assert not fails, "\n".join(fails)
+
+
+# a pivot that is exactly zero in any precision: in [[4,2,0],[2,1,3],[0,3,5]]
+# l_21 = 1 exactly and the second pivot is 1 - 1 = 0, so info = 2 (leading
+# minors 4, 0, -36); placed at offset o inside the identity, info = o + 2
+ZERO_PIVOT_BLOCK = np.array([[4.0, 2.0, 0.0], [2.0, 1.0, 3.0], [0.0, 3.0, 5.0]])
+
+
+@pytest.mark.parametrize("scope", ["thread", "wave", "workgroup", "subwave"])
+@pytest.mark.parametrize("op", ["potrf", "posv"])
+def test_exact_zero_pivot(env, op, scope):
+    glass, torch = env
+    fails = []
+    for n in (3, 8, 16, 24, 32, 40, 64):
+        if glass.glass_placement_feasible(glass.OPS[op], n, 1, glass.SCOPES[scope], 1) != 1:
+            continue
+        for o in sorted({0, n - 3, min(17, n - 3)}):
+            label = f"{op} n={n} {scope} zero pivot at {o + 1}"
+            print(label, flush=True)
+            sys.stdout.flush()
+            rng = np.random.default_rng(2000 + n + o)
+            batch = 5
+            A = inputs.spd(rng, batch, n)
+            B = inputs.uniform(rng, (batch, n, 1))
+            Z = np.eye(n)
+            Z[o:o + 3, o:o + 3] = ZERO_PIVOT_BLOCK
+            A[2] = Z.astype(np.float32)
+            want = np.zeros(batch, np.int32)
+            want[2] = o + 2
+            if op == "potrf":
+                L_ref, info_ref = oracle.potrf(A)
+            else:
+                L_ref, X_ref, info_ref = oracle.posv(A, B)
+            assert np.array_equal(info_ref, want), "oracle must report the exact zero pivot"
+            Af, Ad = guarded(torch, A, "cuda:0")
+            Bf, Bd = guarded(torch, B, "cuda:0")
+            info = torch.full((batch,), -7, dtype=torch.int32, device="cuda:0")
+            if op == "potrf":
+                st = glass.glass_potrf_batched(n, batch, Ad, info, (scope, 1))
+            else:
+                st = glass.glass_posv_batched(n, 1, batch, Ad, Bd, info, (scope, 1))
+            torch.cuda.synchronize()
+            if st != 0:
+                fails.append(f"{label}: status {st}")
+                continue
+            got = info.cpu().numpy()
+            if not np.array_equal(got, want):
+                fails.append(f"{label}: info {got.tolist()} vs {want.tolist()}")
+            ok = want == 0
+            err = normwise(np.tril(Ad.cpu().numpy())[ok], L_ref[ok]).max()
+            if op == "posv":
+                err = max(err, normwise(Bd.cpu().numpy()[ok], X_ref[ok]).max())
+            if not err <= TOL:
+                fails.append(f"{label}: healthy problems err {err:.3e}")
+            if not (guards_intact(Af) and guards_intact(Bf)):
+                fails.append(f"{label}: guard band written")
+    assert not fails, "\n".join(fails)
