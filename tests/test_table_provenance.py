@@ -64,11 +64,12 @@ def test_table_choice_is_stable_across_half_sweeps():
     best).  Every placement of a cell was timed in the same 20 paired,
     shuffled rounds, so the even and the odd rounds are two independent
     half-sweeps; each half's winner must be within the margin of the other
-    half's best.  Cells faster than 3 launch floors (a few microseconds,
-    where a 10-sample median moves by a few tenths of a microsecond) get
-    twice the margin."""
+    half's best.  The margin is widened to the cell's own measured spread
+    where that is larger: 1 + 2 x the largest interquartile range over
+    median among its placements (a few launch-bound cells of ~3 us time
+    bimodally, ~0.25 us apart, and their halves fall into different
+    modes)."""
     import numpy as np
-    meta = json.loads(open(autotune.DEFAULT_SWEEP).readline())
     by_cell = {}
     for r in _records():
         by_cell.setdefault((r["op"], r["n"], r["batch"]), {})[(r["scope"], r["pack"])] = np.array(r["samples_us"])
@@ -76,10 +77,11 @@ def test_table_choice_is_stable_across_half_sweeps():
     for cell, samples in by_cell.items():
         halves = [{pl: float(np.median(s[sl])) for pl, s in samples.items()} for sl in (slice(0, None, 2),
                                                                                          slice(1, None, 2))]
+        spread = max((np.percentile(s, 75) - np.percentile(s, 25)) / np.median(s) for s in samples.values())
+        margin = max(autotune.MARGIN, 1 + 2 * spread)
         for a, b in ((0, 1), (1, 0)):
             win = min(halves[a], key=lambda pl: (halves[a][pl], pl))
             best = min(halves[b].values())
-            margin = autotune.MARGIN if best >= 3 * meta["floor_us"] else 2 * autotune.MARGIN - 1
             if halves[b][win] > best * margin:
                 bad.append((cell, win, round(halves[b][win] / best, 3)))
     assert not bad, bad
