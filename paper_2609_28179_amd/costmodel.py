@@ -47,8 +47,8 @@ FEATURE_OPS = ("gemm", "gemv", "potrf", "potrs", "posv", "trsv", "se3_compose", 
 D = 15
 HIDDEN = 64
 TOP_K = 3
-STEPS = 2000
-LR = 1e-3   # chosen by leave-one-order-out cross-validation on the training sweep
+STEPS = 5000
+LR = 3e-3   # chosen by leave-one-order-out cross-validation on the training sweep
 SEED = 0
 
 
