@@ -69,9 +69,33 @@ def cpu_baseline(cells, sets, shared, sample_cap, min_seconds, torch):
     t_est /= passes
     scope = "every problem of the step" if sampled == total else \
         f"the first min(batch, {sample_cap}) problems of each cell, time scaled to the full batch"
-    return {"value": total / t_est, "unit": "solves/s", "cores": oracle.num_threads(), "kind": "oracle",
+    # the same oracle on one thread, over the first min(batch, 1024) problems
+    # of each cell, time scaled to the full batch
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        t_one, spent_one = 0.0, 0.0
+        for op, batch, m, h in host:
+            m1 = min(m, 1024)
+            t0 = time.perf_counter()
+            calls[op]({k: v[:m1] for k, v in h.items()})
+            dt = time.perf_counter() - t0
+            spent_one += dt
+            t_one += dt * batch / m1
+    finally:
+        oracle.set_num_threads(threads)
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": total / t_est, "unit": "solves/s", "cores": threads, "kind": "oracle",
             "sample": f"FP64 C oracle (OpenMP) on {scope} ({len(cells)} cells, {sampled} of {total} problems), "
-                      f"{passes} passes, {spent:.1f} s of oracle time; {t_est:.2f} s per full step"}
+                      f"{passes} passes, {spent:.1f} s of oracle time; {t_est:.2f} s per full step",
+            "single_thread_value": total / t_one,
+            "single_thread_sample": f"one thread, first min(batch, 1024) problems of each cell, {spent_one:.1f} s",
+            "host_cpu": cpu_model}
 
 
 def main():
