@@ -536,14 +536,33 @@ struct SegStep<SEG, NB, NB> {
     static GLASS_DEV void run(float (&)[NB], int& info, float& myinv) { info = first_nonfinite<SEG>(myinv); }
 };
 
+// acc -= L_iK * x_K with x_K = bcast_K(t): the broadcast is the FMA's DPP
+// operand (its source t is given the wait states a DPP read needs first; t
+// is passed by reference so the caller's later reads use the same register
+// and no copy is made).
+template <int SEG, int K>
+GLASS_DEV void seg_fnmac(float& acc, float& t, float lik) {
+    if (SEG == 16) {
+        asm volatile("s_nop 1" : "+v"(t));
+        fnmac_bcast<K>(acc, t, lik);
+    } else {
+        float R[4];
+        replicate_rows<2>(t, R);  // ends with the wait states a DPP read needs
+        fnmac_bcast<K % 16>(acc, R[K / 16], lik);
+    }
+}
+
+// Forward substitution L y = b, one unknown per step: lane K of the segment
+// holds t = acc * (1 / L_KK) = y_K, which every lane subtracts through the
+// broadcast and lane K keeps (its own t, no broadcast needed).
 template <int SEG, int NB, int K, int RG>
 struct SegFwd {
     static GLASS_DEV void run(const float (&a)[NB], float (&acc)[RG], float (&y)[RG], float myinv) {
 #pragma unroll
         for (int c = 0; c < RG; ++c) {
-            const float yk = seg_bcast<SEG, K>(acc[c] * myinv);
-            acc[c] = fmaf(-a[K], yk, acc[c]);
-            y[c] = seg_select<SEG, K>(y[c], yk);
+            float t = acc[c] * myinv;
+            seg_fnmac<SEG, K>(acc[c], t, a[K]);
+            y[c] = seg_select<SEG, K>(y[c], t);
         }
         SegFwd<SEG, NB, K + 1, RG>::run(a, acc, y, myinv);
     }
@@ -561,8 +580,10 @@ struct SegBwd {
         const float lki = i < K ? sb[K * (NB + 4) + i] : 0.f;
 #pragma unroll
         for (int c = 0; c < RG; ++c) {
-            const float xk = seg_bcast<SEG, K>(acc[c] * myinv);
-            acc[c] = seg_select<SEG, K>(fmaf(-lki, xk, acc[c]), xk);
+            float t = acc[c] * myinv;  // x_K in lane K
+            float u = acc[c];
+            seg_fnmac<SEG, K>(u, t, lki);
+            acc[c] = seg_select<SEG, K>(u, t);
         }
         SegBwd<SEG, NB, K - 1, RG>::run(sb, i, acc, myinv);
     }
