@@ -48,7 +48,7 @@ D = 15
 HIDDEN = 64
 TOP_K = 3
 STEPS = 5000
-LR = 3e-3   # chosen by leave-one-order-out cross-validation on the training sweep
+LR = 1e-3   # chosen by leave-one-order-out cross-validation on the training sweep
 SEED = 0
 
 
