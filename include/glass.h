@@ -266,7 +266,7 @@ const char* glass_hip_error_name(int code);
  * predicts log run time from placement features, trained by the kernels
  * below (the paper chooses placements by measurement only, Sec. III-A /
  * Sec. IV-A; the model proposes placements for unmeasured shapes and the
- * measured search stays the judge and the fallback).
+ * measured search still decides among its proposals and is the fallback).
  * params: FP32 flat vector of glass_mlp_num_params(d) floats laid out as
  * W1[64][d], b1[64], W2[64][64], b2[64], w3[64], b3.  X [N][d] row-major,
  * y / t [N].  All pointers are DEVICE pointers; 1 <= d <= 32 (else

@@ -201,7 +201,7 @@ def pick(model, glass, torch, op, n, batch, k=TOP_K, device="cuda:0", rounds=10)
 
 # --------------------------------------------------------------- evaluation
 def evaluate(model_ranks: dict, table_picks: dict, heldout_recs, k=TOP_K):
-    """Judge the model's proposals with exhaustive measurements.
+    """Score the model's proposals against exhaustive measurements.
 
     model_ranks[(op, n, batch)] = placements in predicted order;
     table_picks[(op, n, batch)] = the placement the static table dispatches

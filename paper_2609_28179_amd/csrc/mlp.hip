@@ -3,7 +3,7 @@
 // of a placement from (op, n, batch, scope, pack) features.  The paper picks
 // placements by measurement only (Sec. III-A, Sec. IV-A); this model proposes
 // placements for shapes that were not measured, with measured search as the
-// fallback and the judge of its picks.
+// fallback and as what decides among its picks.
 //
 // Parameter vector (flat): W1 [64][d], b1 [64], W2 [64][64], b2 [64],
 // w3 [64], b3 [1].  One wavefront works on a group of samples; lane j owns
