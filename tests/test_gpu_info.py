@@ -144,3 +144,58 @@ def test_exact_zero_pivot(env, op, scope):
             if not (guards_intact(Af) and guards_intact(Bf)):
                 fails.append(f"{label}: guard band written")
     assert not fails, "\n".join(fails)
+
+
+@pytest.mark.parametrize("scope", ["thread", "wave", "workgroup", "subwave"])
+@pytest.mark.parametrize("op", ["potrf", "posv"])
+def test_nonfinite_pivots(env, op, scope):
+    """info follows !(pivot > 0) exactly for non-finite pivots too: a NaN
+    pivot fails (info = k + 1), a +inf pivot does not (info = 0; the
+    factor of that problem is not compared).  The row kernels test the
+    pivot through 1 / L_kk = rsq(d), which is non-finite exactly for the
+    failing pivots, +0 at +inf."""
+    glass, torch = env
+    fails = []
+    for n in (3, 8, 16, 24, 32, 40, 64):
+        if glass.glass_placement_feasible(glass.OPS[op], n, 1, glass.SCOPES[scope], 1) != 1:
+            continue
+        label = f"{op} n={n} {scope} non-finite pivots"
+        print(label, flush=True)
+        sys.stdout.flush()
+        k = min(5, n - 1)
+        rng = np.random.default_rng(3000 + n)
+        batch = 5
+        A = inputs.spd(rng, batch, n)
+        B = inputs.uniform(rng, (batch, n, 1))
+        A[1, k, k] = np.float32(np.nan)
+        A[3, k, k] = np.float32(np.inf)
+        want = np.array([0, k + 1, 0, 0, 0], np.int32)
+        with np.errstate(invalid="ignore", over="ignore", divide="ignore"):
+            if op == "potrf":
+                L_ref, info_ref = oracle.potrf(A)
+            else:
+                L_ref, X_ref, info_ref = oracle.posv(A, B)
+        assert np.array_equal(info_ref, want), ("oracle", info_ref)
+        Af, Ad = guarded(torch, A, "cuda:0")
+        Bf, Bd = guarded(torch, B, "cuda:0")
+        info = torch.full((batch,), -7, dtype=torch.int32, device="cuda:0")
+        if op == "potrf":
+            st = glass.glass_potrf_batched(n, batch, Ad, info, (scope, 1))
+        else:
+            st = glass.glass_posv_batched(n, 1, batch, Ad, Bd, info, (scope, 1))
+        torch.cuda.synchronize()
+        if st != 0:
+            fails.append(f"{label}: status {st}")
+            continue
+        got = info.cpu().numpy()
+        if not np.array_equal(got, want):
+            fails.append(f"{label}: info {got.tolist()} vs {want.tolist()}")
+        ok = np.array([True, False, True, False, True])
+        err = normwise(np.tril(Ad.cpu().numpy())[ok], L_ref[ok]).max()
+        if op == "posv":
+            err = max(err, normwise(Bd.cpu().numpy()[ok], X_ref[ok]).max())
+        if not err <= TOL:
+            fails.append(f"{label}: healthy problems err {err:.3e}")
+        if not (guards_intact(Af) and guards_intact(Bf)):
+            fails.append(f"{label}: guard band written")
+    assert not fails, "\n".join(fails)
