@@ -11,6 +11,11 @@ template <int NBLK, int OP, bool FULL>
 __global__ void __launch_bounds__(512) chol_blk(int n, int nrhs, int trans, int batch, float* __restrict__ A,
                                                 float* __restrict__ B, int32_t* __restrict__ info) {
     extern __shared__ float lds[];
+    // POTRF on whole 16 x 16 tiles above order 32 (n = 48, 64) is write-bound
+    // and runs 1.5-3 % faster at 4 waves per SIMD than at the 5-7 its
+    // registers allow (at n = 40 the extra waves pay instead): reserving VGPRs
+    // up to v103 makes the allocation 104 registers, which caps the occupancy.
+    if (OP == 0 && FULL && NBLK >= 3) asm volatile("" ::: "v103");
     const int w = wave_index(), lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
