@@ -19,6 +19,9 @@
 //           the sub-wave Cholesky kernels; x_j and dB_j reach lane i by
 //           segment broadcasts, and dA leaves through the segments' LDS
 //           blocks as one contiguous copy of the wavefront's problems.
+// dB may be G itself (in place): at every scope an element of G is read
+// before the same lane (or, at thread scope, the same workgroup after a
+// barrier) writes that element of dB, so neither pointer is __restrict__.
 #include "device_common.hpp"
 #include "glass_internal.hpp"
 #include "chol_device.hpp"
@@ -37,8 +40,8 @@ GLASS_DEV float sym_pair(float acc, float p, float q, float r, float s) {
 
 template <int N>
 __global__ void __launch_bounds__(512) adjoint_thread(int nrhs, int batch, const float* __restrict__ L,
-                                                      const float* __restrict__ X, const float* __restrict__ G,
-                                                      float* __restrict__ dB, float* __restrict__ dA) {
+                                                      const float* __restrict__ X, const float* G,
+                                                      float* dB, float* __restrict__ dA) {
     extern __shared__ float lds[];
     constexpr int SZ = N * N, S = thread_stride(SZ);
     const int nt = blockDim.x, tid = threadIdx.x;
@@ -98,8 +101,8 @@ __global__ void __launch_bounds__(512) adjoint_thread(int nrhs, int batch, const
 
 template <int NB>
 __global__ void __launch_bounds__(512) adjoint_wave(int n, int nrhs, int batch, const float* __restrict__ L,
-                                                    const float* __restrict__ X, const float* __restrict__ G,
-                                                    float* __restrict__ dB, float* __restrict__ dA, int region) {
+                                                    const float* __restrict__ X, const float* G,
+                                                    float* dB, float* __restrict__ dA, int region) {
     extern __shared__ float lds[];
     const int w = wave_index(), lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
@@ -147,8 +150,8 @@ struct SegDa<SEG, NB, NB> {
 
 template <int SEG, int NB>
 __global__ void __launch_bounds__(512) adjoint_seg(int n, int nrhs, int batch, const float* __restrict__ L,
-                                                   const float* __restrict__ X, const float* __restrict__ G,
-                                                   float* __restrict__ dB, float* __restrict__ dA, int region) {
+                                                   const float* __restrict__ X, const float* G,
+                                                   float* dB, float* __restrict__ dA, int region) {
     extern __shared__ float lds[];
     constexpr int PPW = 64 / SEG;
     const int w = wave_index(), lane = threadIdx.x & 63;

@@ -16,6 +16,9 @@ fresh valid input per launch of a destructive op):
                                (LAPACK, through numpy), rounded to float32; a
                                random uniform triangle would have condition
                                numbers near 1e19 at n = 64
+  conditioned SPD (tests)     : 2^s Q diag(lam) Q^T, lam log-spaced over
+                               [1, kappa], Q Haar orthogonal (QR of a Gaussian
+                               matrix), mirrored, rounded to float32
   SE(3) transforms            : R from a Hamilton unit quaternion (w, x, y, z)
                                q = normalize(N(0, 1)^4) (uniform on S^3),
                                t iid uniform[-1, 1]^3, last row (0, 0, 0, 1)
@@ -64,6 +67,33 @@ def lower_factor(rng: np.random.Generator, batch: int, n: int) -> np.ndarray:
     return np.tril(L).astype(np.float32)
 
 
+def spd_conditioned64(rng: np.random.Generator, batch: int, n: int, kappa: float, scale_exp: int = 0) -> np.ndarray:
+    """float64 SPD A = 2^scale_exp Q diag(lam) Q^T with lam log-spaced over
+    [1, kappa] (condition number kappa) and Q the orthogonal factor of a
+    Gaussian matrix (column signs fixed by R's diagonal, so Q is Haar
+    distributed); lower triangle mirrored (exact symmetry)."""
+    G = rng.standard_normal(size=(batch, n, n))
+    Q, R = np.linalg.qr(G)
+    Q = Q * np.sign(np.diagonal(R, axis1=1, axis2=2))[:, None, :]
+    lam = np.logspace(0.0, np.log10(kappa), n) if n > 1 else np.ones(1)
+    A = np.matmul(Q * lam[None, None, :], np.swapaxes(Q, 1, 2))
+    il = np.tril_indices(n, -1)
+    A[:, il[1], il[0]] = A[:, il[0], il[1]]
+    return A * (2.0 ** scale_exp)
+
+
+def spd_conditioned(rng: np.random.Generator, batch: int, n: int, kappa: float, scale_exp: int = 0) -> np.ndarray:
+    return spd_conditioned64(rng, batch, n, kappa, scale_exp).astype(np.float32)
+
+
+def lower_factor_conditioned(rng: np.random.Generator, batch: int, n: int, kappa: float,
+                             scale_exp: int = 0) -> np.ndarray:
+    """The float64 Cholesky factor of ``spd_conditioned64`` (condition number
+    sqrt(kappa)), rounded to float32."""
+    L = np.linalg.cholesky(spd_conditioned64(rng, batch, n, kappa, scale_exp))
+    return np.tril(L).astype(np.float32)
+
+
 def rotations64(rng: np.random.Generator, batch: int) -> np.ndarray:
     q = rng.standard_normal(size=(batch, 4))
     q /= np.linalg.norm(q, axis=1, keepdims=True)
@@ -90,9 +120,24 @@ def se3(rng: np.random.Generator, batch: int) -> np.ndarray:
 
 
 # ---------------------------------------------------------------- problem sets
-def make_case(op: str, n: int, batch: int, cfg: int = 1, nrhs: int = 1, extra: int = 0) -> dict:
-    """Inputs of one (op, n, batch) cell as float32 numpy arrays."""
+def make_case(op: str, n: int, batch: int, cfg: int = 1, nrhs: int = 1, extra: int = 0,
+              kappa: float | None = None, scale_exp: int = 0) -> dict:
+    """Inputs of one (op, n, batch) cell as float32 numpy arrays.  With
+    ``kappa`` the SPD matrices (and the factors derived from them) come from
+    ``spd_conditioned`` with that condition number and scale 2^scale_exp."""
     rng = rng_for(cfg, op, n, batch, extra)
+    if kappa is not None:
+        if op in ("potrf", "posv"):
+            out = {"A": spd_conditioned(rng, batch, n, kappa, scale_exp)}
+            if op == "posv":
+                out["B"] = uniform(rng, (batch, n, nrhs))
+            return out
+        if op in ("potrs", "trsv"):
+            L = lower_factor_conditioned(rng, batch, n, kappa, scale_exp)
+            if op == "potrs":
+                return {"L": L, "B": uniform(rng, (batch, n, nrhs))}
+            return {"L": L, "x": uniform(rng, (batch, n))}
+        raise ValueError(f"no conditioned recipe for {op}")
     if op == "gemm":
         return {"A": uniform(rng, (batch, n, n)), "B": uniform(rng, (batch, n, n))}
     if op == "gemv":

@@ -36,6 +36,54 @@ def test_oracle_ragged_matches_per_problem_solve():
         assert np.max(np.abs(got - x)) <= 1e-10
 
 
+def test_oracle_ragged_every_problem_against_numpy():
+    """Every problem of a ragged batch (all nine orders, 1..8 right-hand
+    sides): the packed L is the lower Cholesky factor (numpy.linalg.cholesky,
+    LAPACK) with a +0 strict upper part, and the packed X solves A X = B
+    (numpy.linalg.solve, LU), so the oracle's packing and unpacking are
+    pinned on every offset, not only on a few problems."""
+    case = inputs.make_ragged(300, seed=11)
+    n, r, offA, offB = case["n"], case["nrhs"], case["offA"], case["offB"]
+    A_out, B_out, info = oracle.posv_ragged(n, r, offA, offB, case["A"], case["B"])
+    assert (info == 0).all()
+    assert A_out.shape == case["A"].shape and B_out.shape == case["B"].shape
+    assert set(np.unique(n)) == set(inputs.RAGGED_SIZES)
+    for i in range(len(n)):
+        ni, ri = int(n[i]), int(r[i])
+        A = case["A"][offA[i]:offA[i] + ni * ni].reshape(ni, ni).astype(np.float64)
+        b = case["B"][offB[i]:offB[i] + ni * ri].reshape(ni, ri).astype(np.float64)
+        L = A_out[offA[i]:offA[i] + ni * ni].reshape(ni, ni)
+        X = B_out[offB[i]:offB[i] + ni * ri].reshape(ni, ri)
+        iu = np.triu_indices(ni, 1)
+        assert (L[iu] == 0).all() and not np.signbit(L[iu]).any(), i
+        Lnp = np.linalg.cholesky(A)
+        assert np.max(np.abs(L - Lnp)) <= 1e-12 * np.max(np.abs(Lnp)), i
+        Xnp = np.linalg.solve(A, b)
+        assert np.max(np.abs(X - Xnp)) <= 1e-11 * max(1.0, np.max(np.abs(Xnp))), i
+
+
+def test_oracle_ragged_info_and_untouched_neighbours():
+    """A planted indefinite problem reports its own 1-based failing column
+    (Sylvester: the leading minor of order k+1 turns negative) and leaves the
+    other problems' results as in a clean run."""
+    case = inputs.make_ragged(30, seed=12)
+    n, r, offA, offB = case["n"], case["nrhs"], case["offA"], case["offB"]
+    clean = oracle.posv_ragged(n, r, offA, offB, case["A"], case["B"])
+    A = case["A"].copy()
+    bad, k = 4, 2
+    nb = int(n[bad])
+    A[offA[bad] + k * nb + k] = -100.0
+    A_out, B_out, info = oracle.posv_ragged(n, r, offA, offB, A, case["B"])
+    assert info[bad] == k + 1
+    assert (np.delete(info, bad) == 0).all()
+    for i in range(len(n)):
+        if i == bad:
+            continue
+        sa = slice(offA[i], offA[i] + int(n[i]) ** 2)
+        sb = slice(offB[i], offB[i] + int(n[i]) * int(r[i]))
+        assert np.array_equal(A_out[sa], clean[0][sa]) and np.array_equal(B_out[sb], clean[1][sb])
+
+
 def test_ragged_validation_without_device():
     from paper_2609_28179_amd import glass
     F = 0x10000
