@@ -37,6 +37,8 @@
  *     GLASS_ERR_INFEASIBLE_PLACEMENT without enqueuing anything.
  *   - Thread safety: stateless apart from a per-process, read-only device
  *     property cache; calls may be made concurrently from several threads.
+ *     The one exception is glass_posv_ragged_noalloc, whose calls on one
+ *     device share a static workspace and must not overlap in time.
  */
 #ifndef GLASS_H_
 #define GLASS_H_
@@ -225,6 +227,27 @@ glass_status_t glass_posv_ragged(int count, const int32_t* n, const int32_t* nrh
                                  float* B, int32_t* info, void* workspace,
                                  size_t workspace_bytes, const int32_t* class_scope,
                                  void* stream);
+
+/* glass_posv_ragged without a caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results, errors and
+ * launches as glass_posv_ragged; the workspace is a static device array of
+ * the library (about 4 MiB per device, allocated when the library's code
+ * object is loaded and held until the process ends), so the call allocates
+ * nothing.  count > glass_posv_ragged_noalloc_max_count() (1,048,576) ->
+ * GLASS_ERR_UNSUPPORTED, before anything is enqueued.  The calling thread's
+ * current device must be the device of `stream`.  Every call on one device
+ * shares that device's array: calls on one stream are ordered and safe, but
+ * calls that overlap in time on one device (other streams, other threads)
+ * race and give undefined results.  The class-sorted permutation is not
+ * returned. */
+glass_status_t glass_posv_ragged_noalloc(int count, const int32_t* n, const int32_t* nrhs,
+                                         const int64_t* offA, const int64_t* offB, float* A,
+                                         float* B, int32_t* info, const int32_t* class_scope,
+                                         void* stream);
+
+/* The largest count glass_posv_ragged_noalloc accepts. */
+int glass_posv_ragged_noalloc_max_count(void);
 
 /* Provenance of the built-in per-class ragged placement table. */
 const char* glass_ragged_table_provenance(void);

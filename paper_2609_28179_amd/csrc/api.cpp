@@ -239,6 +239,32 @@ glass_status_t glass_posv_ragged(int count, const int32_t* n, const int32_t* nrh
     return launched(launch_posv_ragged(count, n, nrhs, offA, offB, A, B, info, workspace, sc, stream));
 }
 
+glass_status_t glass_posv_ragged_noalloc(int count, const int32_t* n, const int32_t* nrhs, const int64_t* offA,
+                                         const int64_t* offB, float* A, float* B, int32_t* info,
+                                         const int32_t* class_scope, void* stream) {
+    if (count < 0) return GLASS_ERR_INVALID_VALUE;
+    if (count > kRaggedNoAllocMaxCount) return GLASS_ERR_UNSUPPORTED;
+    RaggedScopes sc{};
+    for (int k = 0; k < 8; ++k) {
+        const int s = class_scope ? class_scope[k] : kRaggedScope[k];
+        if (s != GLASS_SCOPE_THREAD && s != GLASS_SCOPE_WAVE && s != GLASS_SCOPE_SUBWAVE)
+            return GLASS_ERR_INVALID_VALUE;
+        if ((s == GLASS_SCOPE_THREAD && k > 0) || (s == GLASS_SCOPE_SUBWAVE && k > 2))
+            return GLASS_ERR_INFEASIBLE_PLACEMENT;
+        sc.s[k] = s;
+    }
+    if (count == 0) return GLASS_OK;
+    if (!n || !nrhs || !offA || !offB || !A || !B || !info) return GLASS_ERR_INVALID_VALUE;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    const int err = ragged_noalloc_workspace(&ws, &ws_bytes);
+    if (err != 0) return launched(err);
+    if (ws_bytes < ragged_workspace_bytes(count)) return GLASS_ERR_UNSUPPORTED;
+    return launched(launch_posv_ragged(count, n, nrhs, offA, offB, A, B, info, ws, sc, stream));
+}
+
+int glass_posv_ragged_noalloc_max_count(void) { return kRaggedNoAllocMaxCount; }
+
 glass_status_t glass_riccati_gain_batched(int nx, int nu, int batch, const float* A, const float* B, const float* P,
                                           const float* R, float* K, int32_t* info, const glass_placement_t* force,
                                           void* stream) {

@@ -264,6 +264,11 @@ struct RaggedScopes {
     int32_t s[8];
 };
 size_t ragged_workspace_bytes(int count);
+// No-allocation form of the ragged solve: the largest count it takes, and the
+// calling thread's current device's address and size of its static workspace
+// (returns hipSuccess or the runtime's error code).
+constexpr int kRaggedNoAllocMaxCount = 1 << 20;
+int ragged_noalloc_workspace(void** ptr, size_t* bytes);
 int launch_posv_ragged(int count, const int32_t* n, const int32_t* nrhs, const int64_t* offA, const int64_t* offB,
                        float* A, float* B, int32_t* info, void* workspace, const RaggedScopes& scopes,
                        void* stream);

@@ -25,6 +25,9 @@
 //                      scope, or one problem), in two launches: the classes
 //                      above order 24 (the blocked routines need more
 //                      registers), then the rest at the smaller allocation.
+#include <atomic>
+#include <mutex>
+
 #include "device_common.hpp"
 #include "glass_internal.hpp"
 #include "chol_device.hpp"
@@ -340,6 +343,47 @@ __global__ void __launch_bounds__(256, 3) ragged_solve(const int32_t* __restrict
 size_t ragged_workspace_bytes(int count) {
     const int nchunks = (count + kChunk - 1) / kChunk;
     return sizeof(int32_t) * ((size_t)nchunks * kClasses + 32 + (size_t)count);
+}
+
+// ------------------------------------------------------- no-allocation form --
+// Workspace of the ragged solve for callers that cannot allocate: a static
+// device array sized for kRaggedNoAllocMaxCount problems (about 4 MiB), one
+// copy per device that the library runs on, kept until the process ends.
+// Host code never passes `scratch` itself (on the host it is only a stand-in
+// for the symbol); it passes the device address hipGetSymbolAddress returns,
+// looked up once per device with that device current.  Every call on a
+// device shares its copy; the planning kernels rewrite every word they read
+// (histograms, class metadata, permutation), so nothing needs clearing.
+namespace {
+constexpr size_t kNoAllocWords =
+    (size_t)((kRaggedNoAllocMaxCount + kChunk - 1) / kChunk) * kClasses + 32 + (size_t)kRaggedNoAllocMaxCount;
+static __device__ __align__(256) int32_t scratch[kNoAllocWords];
+
+constexpr int kMaxDevices = 64;
+std::atomic<void*> g_scratch_ptr[kMaxDevices];
+std::mutex g_scratch_mu;
+}  // namespace
+
+int ragged_noalloc_workspace(void** ptr, size_t* bytes) {
+    static_assert(sizeof(scratch) == kNoAllocWords * sizeof(int32_t), "scratch size");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    if (dev < 0 || dev >= kMaxDevices) return (int)hipErrorInvalidDevice;
+    void* p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        p = g_scratch_ptr[dev].load(std::memory_order_relaxed);
+        if (!p) {
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return (int)e;
+            if (!p) return (int)hipErrorInvalidSymbol;
+            g_scratch_ptr[dev].store(p, std::memory_order_release);
+        }
+    }
+    *ptr = p;
+    *bytes = sizeof(scratch);
+    return 0;
 }
 
 int launch_posv_ragged(int count, const int32_t* n, const int32_t* nrhs, const int64_t* offA, const int64_t* offB,

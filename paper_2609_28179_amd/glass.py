@@ -69,6 +69,8 @@ _SIGS = {
     "glass_se3_batched": [_i, _i, _p, _p, _p, _PP, _p],
     "glass_posv_adjoint_batched": [_i, _i, _i, _p, _p, _p, _p, _p, _PP, _p],
     "glass_posv_ragged": [_i, _p, _p, _p, _p, _p, _p, _p, _p, ctypes.c_size_t, _p, _p],
+    "glass_posv_ragged_noalloc": [_i, _p, _p, _p, _p, _p, _p, _p, _p, _p],
+    "glass_posv_ragged_noalloc_max_count": [],
     "glass_posv_ragged_workspace_size": [_i],
     "glass_posv_ragged_perm_offset": [_i],
     "glass_riccati_gain_batched": [_i, _i, _i, _p, _p, _p, _p, _p, _p, _PP, _p],
@@ -177,6 +179,19 @@ def glass_posv_ragged(count, n, nrhs, offA, offB, A, B, info, workspace, workspa
         cs = (ctypes.c_int32 * 8)(*vals)
     return _lib.glass_posv_ragged(count, _ptr(n), _ptr(nrhs), _ptr(offA), _ptr(offB), _ptr(A), _ptr(B), _ptr(info),
                                   _ptr(workspace), workspace_bytes, cs, _stream(stream))
+
+
+def glass_posv_ragged_noalloc(count, n, nrhs, offA, offB, A, B, info, class_scope=None, stream=None) -> int:
+    cs = None
+    if class_scope is not None:
+        vals = [RAGGED_SCOPES[v] if isinstance(v, str) else int(v) for v in class_scope]
+        cs = (ctypes.c_int32 * 8)(*vals)
+    return _lib.glass_posv_ragged_noalloc(count, _ptr(n), _ptr(nrhs), _ptr(offA), _ptr(offB), _ptr(A), _ptr(B),
+                                          _ptr(info), cs, _stream(stream))
+
+
+def glass_posv_ragged_noalloc_max_count() -> int:
+    return _lib.glass_posv_ragged_noalloc_max_count()
 
 
 def glass_posv_ragged_workspace_size(count) -> int:

@@ -106,3 +106,23 @@ def test_ragged_validation_without_device():
     assert glass.glass_posv_ragged(10, F, F, F, F, F, F, F, F, w, class_scope=bad, stream=0) == \
         glass.ERR_INFEASIBLE_PLACEMENT
     assert glass.glass_ragged_table_provenance().startswith("gfx950")
+
+
+def test_ragged_noalloc_validation_without_device():
+    """Argument errors of the no-allocation ragged call are found on the host
+    before any device call (none is made here)."""
+    from paper_2609_28179_amd import glass
+    F = 0x10000
+    mx = glass.glass_posv_ragged_noalloc_max_count()
+    assert mx == 1 << 20
+    assert glass.glass_posv_ragged_noalloc(0, None, None, None, None, None, None, None, stream=0) == glass.OK
+    assert glass.glass_posv_ragged_noalloc(-1, F, F, F, F, F, F, F, stream=0) == glass.ERR_INVALID_VALUE
+    assert glass.glass_posv_ragged_noalloc(mx + 1, F, F, F, F, F, F, F, stream=0) == glass.ERR_UNSUPPORTED
+    assert glass.glass_posv_ragged_noalloc(10, F, F, F, F, F, F, None, stream=0) == glass.ERR_INVALID_VALUE
+    assert glass.glass_posv_ragged_noalloc(10, None, F, F, F, F, F, F, stream=0) == glass.ERR_INVALID_VALUE
+    bad = ["wave"] * 8
+    bad[1] = "thread"
+    assert glass.glass_posv_ragged_noalloc(10, F, F, F, F, F, F, F, class_scope=bad, stream=0) == \
+        glass.ERR_INFEASIBLE_PLACEMENT
+    assert glass.glass_posv_ragged_noalloc(10, F, F, F, F, F, F, F, class_scope=[9] * 8, stream=0) == \
+        glass.ERR_INVALID_VALUE
