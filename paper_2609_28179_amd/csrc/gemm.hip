@@ -271,6 +271,88 @@ GLASS_DEV void mfma_problem(int m, int n, int k, float alpha, const float* __res
     }
 }
 
+// The A fragments of row block `it` (all TB k-blocks), zero outside m x k.
+template <int TB, bool VEC, bool TA>
+GLASS_DEV void mfma_a_rows(float (&af)[TB][4], int m, int k, const float* __restrict__ Ag, int it, int q, int r) {
+    const int MT = (m + 15) >> 4, KT = (k + 15) >> 4;
+    const int i = it * 16 + r;
+#pragma unroll
+    for (int kb = 0; kb < TB; ++kb) {
+        const int k0 = kb * 16 + 4 * q;
+        const bool in = it < MT && kb < KT && i < m;
+        if (TA) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) af[kb][c] = (in && k0 + c < k) ? Ag[(k0 + c) * m + i] : 0.f;
+        } else if (VEC) {
+            floatx4 v = {0.f, 0.f, 0.f, 0.f};
+            if (in && k0 < k) v = *reinterpret_cast<const floatx4*>(Ag + i * k + k0);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) af[kb][c] = v[c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) af[kb][c] = (in && k0 + c < k) ? Ag[i * k + k0 + c] : 0.f;
+        }
+    }
+}
+
+// Wave scope with a staged output at TB = 4 (orders 49..64): the B fragments
+// of every column tile stay in VGPRs while A streams in by 16-row block,
+// each block's fragments loaded before the previous block's products.  A
+// block's products then run while the next block's loads are in flight and
+// its stores overlap them; holding one A block at a time (two with the
+// prefetch) instead of all four keeps the wave within 128 VGPRs, i.e. four
+// waves per SIMD, so 4096 problems run in one round of waves.
+template <int TB, bool VEC, bool TA, bool TBT>
+GLASS_DEV void mfma_problem_rows(int m, int n, int k, float alpha, const float* __restrict__ Ag,
+                                 const float* __restrict__ Bg, float beta, float* __restrict__ Cg, int lane,
+                                 float* stg) {
+    const int q = lane >> 4, r = lane & 15;
+    const int MT = (m + 15) >> 4, NT = (n + 15) >> 4, KT = (k + 15) >> 4;
+    float af[2][TB][4];
+    mfma_a_rows<TB, VEC, TA>(af[0], m, k, Ag, 0, q, r);
+    float bf[TB][TB][4];
+#pragma unroll
+    for (int jj = 0; jj < TB; ++jj) {
+        const int j = jj * 16 + r;
+#pragma unroll
+        for (int kb = 0; kb < TB; ++kb)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int kk = kb * 16 + 4 * q + c;
+                bf[jj][kb][c] = (kb < KT && kk < k && j < n) ? (TBT ? Bg[j * k + kk] : Bg[kk * n + j]) : 0.f;
+            }
+    }
+#pragma unroll
+    for (int it = 0; it < TB; ++it) {
+        if (it + 1 < TB) mfma_a_rows<TB, VEC, TA>(af[(it + 1) & 1], m, k, Ag, it + 1, q, r);
+        if (it < MT) {
+            floatx4 acc[TB];
+#pragma unroll
+            for (int jj = 0; jj < TB; ++jj) {
+                acc[jj] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kb = 0; kb < TB; ++kb) {
+                    if (kb < KT) {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            acc[jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[it & 1][kb][c], bf[jj][kb][c], acc[jj],
+                                                                           0, 0, 0);
+                    }
+                }
+            }
+#pragma unroll
+            for (int jj = 0; jj < TB; ++jj)
+                if (jj < NT) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) stg[(4 * q + e) * kGemmStageStride + jj * 16 + r] = acc[jj][e];
+                }
+            wave_sync();
+            mfma_store_block<TB, TA, TBT>(m, n, alpha, beta, Cg, stg, it, lane);
+            wave_sync();
+        }
+    }
+}
+
 template <int TB, bool VEC, bool TA = false, bool TBT = false, bool STG = false>
 __global__ void __launch_bounds__(512) gemm_mfma_wave(int m, int n, int k, int batch, float alpha,
                                                       const float* __restrict__ A, const float* __restrict__ B,
@@ -279,8 +361,12 @@ __global__ void __launch_bounds__(512) gemm_mfma_wave(int m, int n, int k, int b
     const int w = wave_index(), lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
-    mfma_problem<TB, VEC, TB, TA, TBT, STG>(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lane,
-                                            0, 1, lds + (size_t)w * 16 * kGemmStageStride);
+    if constexpr (STG && TB == 4)
+        mfma_problem_rows<TB, VEC, TA, TBT>(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n, lane,
+                                            lds + (size_t)w * 16 * kGemmStageStride);
+    else
+        mfma_problem<TB, VEC, TB, TA, TBT, STG>(m, n, k, alpha, A + p * m * k, B + p * k * n, beta, C + p * m * n,
+                                                lane, 0, 1, lds + (size_t)w * 16 * kGemmStageStride);
 }
 
 template <int TB, bool VEC, bool TA = false, bool TBT = false>
