@@ -287,6 +287,191 @@ struct BwdBlk<NBLK, -1> {
                               int, int) {}
 };
 
+// --------------------------------------------- one right-hand side, no inverses
+// A single right-hand side (TRSV; POTRS with nrhs = 1) gains nothing from the
+// matrix cores: an MFMA product spends 15 of its 16 columns on padding, and
+// the 16 x 16 diagonal-block inverses cost more VALU than the substitution
+// itself.  This path keeps L in T layout and runs everything on VALU:
+//   R form: a 16-vector of block row k with lane (q, r) holding v[r] in
+//           every one of the four 16-lane rows q;
+//   diagonal block: plain substitution on its rows (forward) or columns
+//           (backward) in row-per-lane form, one DPP step per unknown:
+//           s += bcast_K(s) * m_K with m_K = -L_rK / L_KK (forward) or
+//           -L_Kr / L_KK (backward), zero in lane K, then x = s / L_rr;
+//   off-diagonal blocks: a lane's four T-layout entries times the matching
+//           four unknowns, summed across the four rows q (two permlane
+//           swaps) for L_kj x_j, or across the 16 lanes of a row (four DPP
+//           steps) for L_ik^T x_i.
+// Pending products are accumulated as soon as a block of x is known
+// (right-looking), so only one partial sum per later block stays live.
+
+// acc += bcast_K(acc) * m with the two wait states the DPP read of a
+// just-written acc needs.
+template <int K>
+GLASS_DEV void fmac_self_bcast_w(float& acc, float m) {
+    asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
+                 : "+v"(acc)
+                 : "v"(m), "n"(K));
+}
+
+template <int K, int DIR>
+struct DiagSub {
+    static GLASS_DEV void run(float& s, const float (&m)[16]) {
+        fmac_self_bcast_w<K>(s, m[K]);
+        DiagSub<K + DIR, DIR>::run(s, m);
+    }
+};
+template <>
+struct DiagSub<16, 1> {
+    static GLASS_DEV void run(float&, const float (&)[16]) {}
+};
+template <>
+struct DiagSub<-1, -1> {
+    static GLASS_DEV void run(float&, const float (&)[16]) {}
+};
+
+// v summed over the four 16-lane rows (lanes r, r + 16, r + 32, r + 48), in
+// every lane: each v_permlane*_swap exchanges half of v with half of a copy,
+// and the VALU write of the copy gets its two wait states before the swap.
+GLASS_DEV float sum_rows4(float v) {
+    float t;
+    asm volatile(
+        "v_mov_b32 %1, %0\n"
+        "s_nop 1\n"
+        "v_permlane32_swap_b32 %0, %1\n"
+        "v_add_f32 %0, %0, %1\n"
+        "v_mov_b32 %1, %0\n"
+        "s_nop 1\n"
+        "v_permlane16_swap_b32 %0, %1\n"
+        "v_add_f32 %0, %0, %1\n"
+        : "+v"(v), "=&v"(t));
+    return v;
+}
+
+// Each of z[0..3] summed over the 16 lanes of its row, in every lane of the
+// row (quad swaps, then the half-row and row mirrors).  The four registers
+// take turns, so every DPP read is three instructions after the write of its
+// source; the leading s_nop covers the caller's last writes.
+GLASS_DEV void sum_row16(float (&z)[4]) {
+    asm volatile(
+        "s_nop 1\n"
+        "v_add_f32_dpp %0, %0, %0 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %1, %1, %1 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %2, %2, %2 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %3, %3, %3 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %0, %0, %0 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %1, %1, %1 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %2, %2, %2 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %3, %3, %3 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %0, %0, %0 row_half_mirror row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %1, %1, %1 row_half_mirror row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %2, %2, %2 row_half_mirror row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %3, %3, %3 row_half_mirror row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %0, %0, %0 row_mirror row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %1, %1, %1 row_mirror row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %2, %2, %2 row_mirror row_mask:0xf bank_mask:0xf\n"
+        "v_add_f32_dpp %3, %3, %3 row_mirror row_mask:0xf bank_mask:0xf\n"
+        : "+v"(z[0]), "+v"(z[1]), "+v"(z[2]), "+v"(z[3]));
+}
+
+// xc[c] = v[4 q + c] of an R-form v (lane (q, 4 q + c) holds it).
+GLASS_DEV void r_to_c(float v, float (&xc)[4], int q) {
+    const int vi = __float_as_int(v);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) xc[c] = __int_as_float(__builtin_amdgcn_ds_bpermute((20 * q + c) * 4, vi));
+}
+
+// R form of w with w[4 q + c] = z[c] in every lane of row q: lane (q', r')
+// takes z[r' % 4] from lane r' % 4 of row r' / 4.
+GLASS_DEV float c_to_r(const float (&z)[4], int r) {
+    const int c = r & 3;
+    const float w = c == 0 ? z[0] : c == 1 ? z[1] : c == 2 ? z[2] : z[3];
+    return __int_as_float(__builtin_amdgcn_ds_bpermute((16 * (r >> 2) + c) * 4, __float_as_int(w)));
+}
+
+// Diagonal block k of L (T layout) transposed through LDS: lane (q, r)
+// receives column r (col[j] = L_kk[j][r]); returns L_kk[r][r].
+GLASS_DEV float diag_cols(const f4_t& t, float (&col)[16], float* xs, int q, int r) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) xs[(4 * q + c) * kXS + r] = t[c];
+    wave_sync();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const f4_t v = *reinterpret_cast<const f4_t*>(xs + r * kXS + 4 * u);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) col[4 * u + e] = v[e];
+    }
+    const float d = xs[r * kXS + r];
+    wave_sync();
+    return d;
+}
+
+// L x = b (FWD) and / or L^T x = b (BWD) for one right-hand side bg[0..n)
+// (unit stride), in place; T: L in T layout (diagonal blocks with a zero
+// strict upper part, identity rows past n).
+template <int NBLK, bool FULL, bool FWD, bool BWD>
+GLASS_DEV void blk_solve1(const f4_t (&T)[NBLK * (NBLK + 1) / 2], float* bg, int n, float* xs, int q, int r) {
+    float x[NBLK];
+#pragma unroll
+    for (int k = 0; k < NBLK; ++k) {
+        const int R = 16 * k + r;
+        x[k] = (FULL || R < n) ? bg[R] : 0.f;
+    }
+    if (FWD) {
+        float p[NBLK];  // pending sum_j L_kj x_j of block row k, split over the rows q
+#pragma unroll
+        for (int k = 0; k < NBLK; ++k) p[k] = 0.f;
+#pragma unroll
+        for (int k = 0; k < NBLK; ++k) {
+            float s = k > 0 ? x[k] - sum_rows4(p[k]) : x[k];
+            float a[16], m[16];
+            const float myinv = 1.0f / diag_rows(T[BI(k, k)], a, xs, q, r);
+            InvCoef<0>::run(a, myinv, m);
+            DiagSub<0, 1>::run(s, m);
+            x[k] = s * myinv;
+            if (k + 1 < NBLK) {
+                float xc[4];
+                r_to_c(x[k], xc, q);
+#pragma unroll
+                for (int i = k + 1; i < NBLK; ++i)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) p[i] = fmaf(T[BI(i, k)][c], xc[c], p[i]);
+            }
+        }
+    }
+    if (BWD) {
+        float z[NBLK][4];  // pending sum_i L_ik^T x_i of block column k, split over the lanes of a row
+#pragma unroll
+        for (int k = 0; k < NBLK; ++k)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) z[k][c] = 0.f;
+#pragma unroll
+        for (int k = NBLK - 1; k >= 0; --k) {
+            float s = x[k];
+            if (k + 1 < NBLK) {
+                sum_row16(z[k]);
+                s -= c_to_r(z[k], r);
+            }
+            float col[16], m[16];
+            const float myinv = 1.0f / diag_cols(T[BI(k, k)], col, xs, q, r);
+            InvCoef<0>::run(col, myinv, m);
+            DiagSub<15, -1>::run(s, m);
+            x[k] = s * myinv;
+#pragma unroll
+            for (int j = 0; j < k; ++j)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) z[j][c] = fmaf(T[BI(k, j)][c], x[k], z[j][c]);
+        }
+    }
+    if (q == 0) {
+#pragma unroll
+        for (int k = 0; k < NBLK; ++k) {
+            const int R = 16 * k + r;
+            if (FULL || R < n) bg[R] = x[k];
+        }
+    }
+}
+
 // One problem: factor (POTRF, POSV) or take L as given (POTRS, TRSV), then
 // solve.  op: 0 POTRF, 1 POSV, 2 POTRS, 3 TRSV (trans: 0 forward, 1 backward);
 // Ag is A (L for the solves), Bg the problem's [n][nr] right-hand sides (nr =
