@@ -353,6 +353,94 @@ GLASS_DEV void mfma_problem_rows(int m, int n, int k, float alpha, const float* 
     }
 }
 
+// Whole tiles (m = n = k = N = 16 TB, no transposes, every operand 16-byte
+// aligned), the schedule of mfma_problem_rows with every bound known at
+// compile time: fragments come from buffer loads at a per-lane offset plus a
+// scalar block offset plus an immediate, with no guards and no 64-bit
+// address arithmetic, and the staged rows leave as 16-byte buffer stores.
+//   A block it, k-block kb: lane (q, r) reads row 16 it + r, columns
+//     16 kb + 4 q .. + 3: byte r*4N + 16 q + it*64N + 64 kb;
+//   B k-block kb, tile jj, step c: row 16 kb + 4 q + c, column 16 jj + r:
+//     byte 16N q + 4 r + kb*64N + c*4N + 64 jj.
+template <int TB>
+GLASS_DEV void full_a_rows(float (&af)[TB][4], __amdgpu_buffer_rsrc_t ra, int lane_off, int it) {
+    constexpr int N = 16 * TB;
+#pragma unroll
+    for (int kb = 0; kb < TB; ++kb) {
+        const f4_t v = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(ra, lane_off + 64 * kb,
+                                                                                        it * 64 * N, 0));
+#pragma unroll
+        for (int c = 0; c < 4; ++c) af[kb][c] = v[c];
+    }
+}
+
+template <int TB>
+__global__ void __launch_bounds__(512) gemm_mfma_wave_full(int batch, float alpha, const float* __restrict__ A,
+                                                           const float* __restrict__ B, float beta,
+                                                           float* __restrict__ C) {
+    constexpr int N = 16 * TB;
+    constexpr uint32_t PB = 4u * N * N;  // bytes per problem and operand
+    extern __shared__ float lds[];
+    const int w = wave_index(), lane = threadIdx.x & 63, q = lane >> 4, r = lane & 15;
+    const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
+    if (p >= batch) return;
+    float* stg = lds + (size_t)w * 16 * kGemmStageStride;
+    const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(A + p * N * N, PB);
+    const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(B + p * N * N, PB);
+    const __amdgpu_buffer_rsrc_t rc = buffer_rsrc(C + p * N * N, PB);
+    const int a_off = r * 4 * N + 16 * q, b_off = 16 * N * q + 4 * r;
+    float af[2][TB][4];
+    full_a_rows<TB>(af[0], ra, a_off, 0);
+    float bf[TB][TB][4];
+#pragma unroll
+    for (int jj = 0; jj < TB; ++jj)
+#pragma unroll
+        for (int kb = 0; kb < TB; ++kb)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                bf[jj][kb][c] = __builtin_bit_cast(
+                    float, __builtin_amdgcn_raw_buffer_load_b32(rb, b_off + c * 4 * N + 64 * jj, kb * 64 * N, 0));
+#pragma unroll
+    for (int it = 0; it < TB; ++it) {
+        if (it + 1 < TB) full_a_rows<TB>(af[(it + 1) & 1], ra, a_off, it + 1);
+        floatx4 acc[TB];
+#pragma unroll
+        for (int jj = 0; jj < TB; ++jj) {
+            acc[jj] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < TB; ++kb)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    acc[jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[it & 1][kb][c], bf[jj][kb][c], acc[jj], 0, 0, 0);
+        }
+#pragma unroll
+        for (int jj = 0; jj < TB; ++jj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) stg[(4 * q + e) * kGemmStageStride + jj * 16 + r] = acc[jj][e];
+        wave_sync();
+        // 16 rows of N floats = 4N 16-byte pieces, N / 16 per lane; piece g is
+        // row g / (N/4), column piece g % (N/4)
+#pragma unroll
+        for (int u = 0; u < N / 16; ++u) {
+            const int g = lane + 64 * u, rr = g / (N / 4), c4 = g % (N / 4);
+            const f4_t v = *reinterpret_cast<const f4_t*>(stg + rr * kGemmStageStride + 4 * c4);
+            const int off = (rr * N + 4 * c4) * 4;
+            f4_t out;
+            if (beta != 0.f) {
+                const f4_t c0 = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rc, off, it * 64 * N, 0));
+#pragma unroll
+                for (int e = 0; e < 4; ++e) out[e] = fmaf(beta, c0[e], alpha * v[e]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) out[e] = alpha * v[e];
+            }
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, out),
+                                                   rc, off, it * 64 * N, 0);
+        }
+        wave_sync();
+    }
+}
+
 template <int TB, bool VEC, bool TA = false, bool TBT = false, bool STG = false>
 __global__ void __launch_bounds__(512) gemm_mfma_wave(int m, int n, int k, int batch, float alpha,
                                                       const float* __restrict__ A, const float* __restrict__ B,
@@ -404,6 +492,21 @@ int launch_gemm_t(const Shape& sh, const Geometry& g, int batch, float alpha, co
     const int tb = (mx + 15) / 16;
     const bool vec = !TA && (k % 4 == 0) && ((uintptr_t)A % 16 == 0);
     if (g.scope == GLASS_SCOPE_WAVE) {
+        if (!TA && !TBT && m == n && n == k && (n == 32 || n == 48 || n == 64) && (uintptr_t)A % 16 == 0 &&
+            (uintptr_t)B % 16 == 0 && (uintptr_t)C % 16 == 0) {
+            switch (n) {
+            case 32:
+                hipLaunchKernelGGL(gemm_mfma_wave_full<2>, grid, block, g.lds_bytes, st, batch, alpha, A, B, beta, C);
+                break;
+            case 48:
+                hipLaunchKernelGGL(gemm_mfma_wave_full<3>, grid, block, g.lds_bytes, st, batch, alpha, A, B, beta, C);
+                break;
+            default:
+                hipLaunchKernelGGL(gemm_mfma_wave_full<4>, grid, block, g.lds_bytes, st, batch, alpha, A, B, beta, C);
+                break;
+            }
+            return (int)hipGetLastError();
+        }
         // staged full-row stores when C rows are whole 16-byte units
         const bool stg = (n % 4 == 0) && ((uintptr_t)C % 16 == 0);
 #define X(TB)                                                                                                   \
