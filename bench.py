@@ -37,10 +37,12 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cells, sets, shared, sample_cap, min_seconds, torch):
-    """Time the FP64 oracle on up to `sample_cap` problems of every cell,
-    repeating the pass over the cells until at least `min_seconds` of oracle
-    time have accumulated."""
+def cpu_baseline(cells, sets, shared, sample_cap, passes, torch):
+    """Time the FP64 oracle on up to `sample_cap` problems of every cell: one
+    warm-up pass over the cells, then `passes` timed passes; the reported
+    rate is the median pass (time scaled to the full batches)."""
+    import statistics
+
     import oracle
 
     host, sampled, total = [], 0, 0
@@ -57,33 +59,35 @@ def cpu_baseline(cells, sets, shared, sample_cap, min_seconds, torch):
              "potrs": lambda h: oracle.potrs(h["L"], h["B"]), "trsv": lambda h: oracle.trsv(h["L"], h["x"], 0),
              "se3_compose": lambda h: oracle.se3_compose(h["Ta"], h["Tb"]),
              "se3_inverse": lambda h: oracle.se3_inverse(h["Ta"])}
-    t_est, spent, passes = 0.0, 0.0, 0
-    while passes == 0 or spent < min_seconds:
+
+    def one_pass(cap=None):
+        est, spent = 0.0, 0.0
         for op, batch, m, h in host:
+            mm = m if cap is None else min(m, cap)
+            hh = h if cap is None else {k: v[:mm] for k, v in h.items()}
             t0 = time.perf_counter()
-            calls[op](h)
+            calls[op](hh)
             dt = time.perf_counter() - t0
             spent += dt
-            t_est += dt * batch / m
-        passes += 1
-    t_est /= passes
+            est += dt * batch / mm
+        return est, spent
+
+    one_pass()  # warm-up
+    timed = [one_pass() for _ in range(passes)]
+    t_est = statistics.median(t for t, _ in timed)
+    spent = sum(sp for _, sp in timed)
     scope = "every problem of the step" if sampled == total else \
         f"the first min(batch, {sample_cap}) problems of each cell, time scaled to the full batch"
     # the same oracle on one thread, over the first min(batch, 1024) problems
-    # of each cell, time scaled to the full batch
+    # of each cell, time scaled to the full batch (one warm-up pass, median of 3)
     threads = oracle.num_threads()
     oracle.set_num_threads(1)
     try:
-        t_one, spent_one = 0.0, 0.0
-        for op, batch, m, h in host:
-            m1 = min(m, 1024)
-            t0 = time.perf_counter()
-            calls[op]({k: v[:m1] for k, v in h.items()})
-            dt = time.perf_counter() - t0
-            spent_one += dt
-            t_one += dt * batch / m1
+        one_pass(1024)
+        single = [one_pass(1024) for _ in range(3)]
     finally:
         oracle.set_num_threads(threads)
+    t_one = statistics.median(t for t, _ in single)
     cpu_model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -91,11 +95,44 @@ def cpu_baseline(cells, sets, shared, sample_cap, min_seconds, torch):
     except OSError:
         pass
     return {"value": total / t_est, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 C oracle (OpenMP) on {scope} ({len(cells)} cells, {sampled} of {total} problems), "
-                      f"{passes} passes, {spent:.1f} s of oracle time; {t_est:.2f} s per full step",
+            "sample": f"FP64 C oracle (OpenMP) on {scope} ({len(cells)} cells, {sampled} of {total} problems): "
+                      f"1 warm-up pass, median of {passes} timed passes ({spent:.1f} s of oracle time); "
+                      f"{t_est:.2f} s per full step",
             "single_thread_value": total / t_one,
-            "single_thread_sample": f"one thread, first min(batch, 1024) problems of each cell, {spent_one:.1f} s",
+            "single_thread_sample": "one thread, first min(batch, 1024) problems of each cell, 1 warm-up pass, "
+                                    f"median of 3 ({sum(sp for _, sp in single):.1f} s)",
             "host_cpu": cpu_model}
+
+
+def eligible_fractions(glass, torch, timing, floor_us, rounds=5):
+    """Share of the 8 TB/s HBM peak reached at the table's placement on every
+    cell where that is the bound: batch >= 4096 and HBM time at peak >= 5
+    launch floors.  Timed with the sweep's protocol (graphs over rotating
+    input sets of >= 1 GiB, destructive inputs restored between replays).
+    Returns per op: worst and median share, and the worst cell."""
+    import numpy as np
+
+    dev = torch.device("cuda:0")
+    per_op = {}
+    for ci, (op, n, batch) in enumerate(timing.sweep_cells()):
+        ab = timing.alg_bytes(op, n) * batch
+        t_hbm = ab / (HBM_PEAK_GBPS * 1e3)
+        if batch < 4096 or t_hbm < 5 * floor_us:
+            continue
+        pl = glass.glass_query_placement(glass.OPS[op], n, batch)
+        cell = timing.Cell(torch, op, n, batch, dev, seed=70_000 + ci)
+        smp = timing.time_cell(glass, torch, cell, [(pl.scope, pl.pack)], rounds=rounds, warmup=2)
+        med = float(np.median(smp[(pl.scope, pl.pack)]))
+        per_op.setdefault(op, []).append((t_hbm / med, n, batch, med))
+        del cell
+        torch.cuda.empty_cache()
+    out = {}
+    for op, v in per_op.items():
+        fr = [x[0] for x in v]
+        w = min(v)
+        out[op] = {"cells": len(v), "median_frac": round(float(np.median(fr)), 4), "worst_frac": round(w[0], 4),
+                   "worst_cell": f"n={w[1]} batch={w[2]} ({w[3]:.1f} us)"}
+    return out
 
 
 def main():
@@ -109,8 +146,10 @@ def main():
                     help="skip the small-POSV, ragged and adjoint workload timings")
     ap.add_argument("--cpu-sample", type=int, default=65536,
                     help="problems per cell the CPU oracle runs (65536: the whole step)")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0,
-                    help="repeat the oracle pass until this much CPU time has accumulated")
+    ap.add_argument("--cpu-passes", type=int, default=5,
+                    help="timed oracle passes after one warm-up pass (the median is reported)")
+    ap.add_argument("--no-cells", action="store_true",
+                    help="skip the per-op HBM shares of the eligible cells and the streaming ceilings")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the batched problems are independent and this build "
@@ -245,6 +284,17 @@ def main():
                 "kernel": f"{op} n={n} batch={batch} at {glass.SCOPE_NAMES[pl.scope]}/P={pl.pack}",
                 "alg_bytes_per_launch": dom_bytes, "avg_launch_us": round(dom_us, 2)}
 
+    ceilings, eligible = None, None
+    if not args.no_cells:
+        t0 = time.time()
+        floor = timing.floor_us(torch, dev)
+        eligible = eligible_fractions(glass, torch, timing, floor)
+        ceilings = {k: v["gbps"] for k, v in timing.stream_ceilings(glass, torch, dev).items()}
+        ceilings["launch_floor_us"] = round(floor, 3)
+        mix = {"gemm": "read2_write1", "gemv": "read", "trsv": "read", "potrs": "read"}.get(op, "copy")
+        roofline["ceiling"] = {"mix": mix, "gbps": ceilings[mix], "frac": round(achieved / ceilings[mix], 4)}
+        log(f"eligible cells and ceilings ({time.time() - t0:.1f} s): {json.dumps(eligible)} {json.dumps(ceilings)}")
+
     extras = None
     if not args.no_extras:
         from paper_2609_28179_amd import workloads
@@ -259,7 +309,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         t0 = time.time()
-        cpu = cpu_baseline(cells, sets, shared, args.cpu_sample, args.cpu_seconds, torch)
+        cpu = cpu_baseline(cells, sets, shared, args.cpu_sample, args.cpu_passes, torch)
         log(f"cpu baseline {cpu['value']:.3e} solves/s with {cpu['cores']} threads ({time.time() - t0:.1f} s)")
 
     out = {
@@ -273,6 +323,8 @@ def main():
                    "placement": "built-in gfx950 table", "table": glass.glass_table_provenance()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "hbm_share_eligible_cells": eligible,
+        "stream_ceilings_gbps": ceilings,
         "fixed_placement": fixed,
         "workloads": extras,
     }

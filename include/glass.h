@@ -279,6 +279,20 @@ glass_status_t glass_riccati_gain_batched(int nx, int nu, int batch, const float
  * within the LDS budget, 0 if not, or a negative status for bad arguments. */
 int glass_riccati_feasible(int nx, int nu, int pack);
 
+/* Streaming bandwidth probe: the attainable HBM bandwidth of a plain kernel
+ * with a given read/write mix, against which the batched kernels' measured
+ * bandwidth is read (the evaluation of Sec. IV-A times device kernels on
+ * device-resident data; the roofline fractions quote the 8 TB/s spec peak,
+ * and these kernels show how much of it each access mix reaches).
+ * kind 0: read a (c receives nothing in practice but must hold >= 256
+ * floats, so n4 >= 64); 1: write c; 2: copy a -> c; 3: c = a + b (two reads
+ * per write, the mix of C = A B).  n4 16-byte elements; a, b, c 16-byte
+ * aligned DEVICE pointers (those the kind uses non-NULL); `blocks`
+ * workgroups of 256 lanes (1 .. 2^20), grid-stride.  Bad arguments ->
+ * GLASS_ERR_INVALID_VALUE before anything is enqueued. */
+glass_status_t glass_stream_probe(int kind, const float* a, const float* b, float* c,
+                                  long long n4, int blocks, void* stream);
+
 /* Diagnostics of GLASS_ERR_LAUNCH: the HIP runtime error code of the most
  * recent failed launch made by this library on the calling thread (0 if none;
  * never reset), and the runtime's name for an error code (static string). */

@@ -9,11 +9,13 @@ samples kept, a 5 % dispatch margin).
   python -m paper_2609_28179_amd.autotune ragged [--out FILE]   (per-class ragged placement)
   python -m paper_2609_28179_amd.autotune emit-ragged [--sweep FILE] [--out INC]
 
-The sweep covers the 250 cells {GEMM, GEMV, POTRF, POTRS, POSV, TRSV} x
-n in {3,4,6,7,12,16,32,64} x batch in {1,16,256,4096,65536} plus SE(3)
+The sweep covers the 300 cells {GEMM, GEMV, POTRF, POTRS, POSV, TRSV} x
+n in {3,4,6,7,12,16,32,64} x batch in {1,16,256,1024,4096,65536} plus SE(3)
 compose / inverse x batch, each at every feasible (scope, pack).  It appends
 one JSON record per (cell, placement) and resumes by skipping cells already
-complete.  The winner of a cell is the placement with the smallest median;
+complete, and only on the kernel sources it started on (the meta line
+records their hash; emit stamps that hash and the sweep file's own into the
+table's provenance).  The winner of a cell is the placement with the smallest median;
 exact ties go to thread < wave < workgroup, then to the smaller pack.  The
 placements within 5 % of the winner form the cell's margin set.
 """
@@ -21,10 +23,10 @@ from __future__ import annotations
 
 import argparse
 import datetime
+import hashlib
 import json
 import os
 import random
-import subprocess
 import sys
 
 import numpy as np
@@ -39,12 +41,29 @@ MARGIN = 1.05
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E spec peak
 
 
-def _git_hash():
-    try:
-        return subprocess.check_output(["git", "rev-parse", "--short", "HEAD"], cwd=PKG,
-                                       stderr=subprocess.DEVNULL).decode().strip()
-    except Exception:
-        return "unknown"
+# Sources whose kernels a table measures: the batched ops' kernels, their
+# device headers and the launch geometry (the host dispatch and the other
+# parts' kernels do not change what a sweep times).
+TABLE_SOURCES = ("glass_internal.hpp", "device_common.hpp", "chol.hip", "chol_device.hpp", "chol_blk.hip",
+                 "chol_blk.hpp", "subwave.hip", "subwave_blas.hip", "gemm.hip", "gemv.hip", "se3.hip")
+RAGGED_SOURCES = ("glass_internal.hpp", "device_common.hpp", "chol_device.hpp", "chol_blk.hpp", "ragged.hip")
+
+
+def source_hash(kind: str = "table") -> str:
+    """First 16 hex digits of a SHA-256 over the sources a table is measured
+    on (TABLE_SOURCES or RAGGED_SOURCES under csrc/, in that order).  A sweep
+    records it when it starts; emit stamps it into the table and refuses a
+    sweep taken on other sources."""
+    h = hashlib.sha256()
+    for f in TABLE_SOURCES if kind == "table" else RAGGED_SOURCES:
+        h.update(f.encode() + b"\0")
+        h.update(open(os.path.join(PKG, "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def file_hash(path) -> str:
+    """First 16 hex digits of the SHA-256 of a file's bytes."""
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
 def load(path):
@@ -70,8 +89,12 @@ def sweep(args):
     dev = torch.device("cuda:0")
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     meta, recs = load(args.out)
+    src = source_hash()
+    if meta is not None and meta.get("src") != src:
+        raise SystemExit(f"{args.out} was started on sources {meta.get('src')}, these are {src}: "
+                         "a sweep must measure one version of the kernels (start a new file)")
     done = {(r["op"], r["n"], r["batch"]) for r in recs}
-    cells = timing.heldout_cells() if args.cells == "heldout" else timing.sweep_cells()
+    cells = timing.heldout_cells() if args.cells == "heldout" else timing.table_cells()
     if args.ops:
         cells = [c for c in cells if c[0] in args.ops.split(",")]
     if args.ns:
@@ -82,10 +105,11 @@ def sweep(args):
         if meta is None:
             p = torch.cuda.get_device_properties(0)
             meta = {"kind": "meta", "gpu": p.name, "arch": p.gcnArchName, "cus": p.multi_processor_count,
-                    "torch": torch.__version__, "hip": torch.version.hip, "git": _git_hash(),
+                    "torch": torch.__version__, "hip": torch.version.hip, "src": src,
                     "date": datetime.datetime.utcnow().isoformat(timespec="seconds"),
                     "floor_us": timing.floor_us(torch, dev), "copy_gbps": timing.copy_bandwidth(torch, dev),
-                    "rounds": args.rounds, "protocol": "graph of S launches per sample, S sets >= 1 GiB"}
+                    "rounds": args.rounds, "rounds_below_65536": args.rounds_small,
+                    "protocol": "graph of S launches per sample, S sets >= 1 GiB"}
             f.write(json.dumps(meta) + "\n")
             f.flush()
             print(f"floor {meta['floor_us']:.2f} us, copy {meta['copy_gbps']:.0f} GB/s", flush=True)
@@ -95,7 +119,8 @@ def sweep(args):
                 continue
             pls = timing.feasible_placements(glass, op, n)
             cell = timing.Cell(torch, op, n, batch, dev, seed=1000 + ci)
-            samples = timing.time_cell(glass, torch, cell, pls, rounds=args.rounds, warmup=args.warmup, rng=rng)
+            rounds = args.rounds if batch >= 65536 else args.rounds_small
+            samples = timing.time_cell(glass, torch, cell, pls, rounds=rounds, warmup=args.warmup, rng=rng)
             ab = timing.alg_bytes(op, n) * batch
             best = None
             for (scope, pack), s in samples.items():
@@ -131,8 +156,11 @@ def choose(recs):
 
 def emit(args):
     meta, recs = load(args.sweep)
+    if meta is None or (meta.get("src") != source_hash() and not args.allow_stale):
+        raise SystemExit(f"{args.sweep} was measured on sources {meta and meta.get('src')}, the tree has "
+                         f"{source_hash()}: re-sweep (or --allow-stale)")
     ch = choose(recs)
-    nk, bk = timing.SWEEP_N, timing.SWEEP_B
+    nk, bk = timing.SWEEP_N, timing.TABLE_B
     lines = []
     missing = 0
     for op in OP_ORDER:
@@ -150,8 +178,7 @@ def emit(args):
             rows.append("{" + ", ".join(ents) + "}")
         lines.append("    {  // %s\n        " % op + ",\n        ".join(rows) + "}")
     prov = (f"gfx950 / {meta.get('gpu', '?')} / torch {meta.get('torch', '?')} hip {meta.get('hip', '?')} / "
-            f"git {meta.get('git', '?')} / sweep {meta.get('date', '?')} / {len(ch)} cells"
-            if meta else "gfx950 / no sweep")
+            f"src {meta.get('src', '?')} / sweep {file_hash(args.sweep)} {meta.get('date', '?')} / {len(ch)} cells")
     text = (
         "// glass_table_gfx950.inc -- measured placement table for gfx950, generated by\n"
         "// paper_2609_28179_amd/autotune.py emit from the sweep records in\n"
@@ -233,7 +260,7 @@ def ragged_sweep(args):
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     with open(args.out, "w") as f:
         p = torch.cuda.get_device_properties(0)
-        f.write(json.dumps({"kind": "meta", "gpu": p.name, "arch": p.gcnArchName, "git": _git_hash(),
+        f.write(json.dumps({"kind": "meta", "gpu": p.name, "arch": p.gcnArchName, "src": source_hash("ragged"),
                             "date": datetime.datetime.utcnow().isoformat(timespec="seconds"),
                             "per_size": RAGGED_PER_SIZE, "rounds": args.rounds}) + "\n")
         for k in range(8):
@@ -281,14 +308,17 @@ def ragged_sweep(args):
 def emit_ragged(args):
     from . import glass
     meta, recs = load(args.sweep)
+    if meta is None or (meta.get("src") != source_hash("ragged") and not args.allow_stale):
+        raise SystemExit(f"{args.sweep} was measured on sources {meta and meta.get('src')}, the tree has "
+                         f"{source_hash('ragged')}: re-sweep (or --allow-stale)")
     codes = {"thread": glass.SCOPE_THREAD, "wave": glass.SCOPE_WAVE, "subwave": glass.SCOPE_SUBWAVE}
     win = []
     for k in range(8):
         cell = [r for r in recs if r["class"] == k]
         best = min(cell, key=lambda r: (r["median_us"], ragged_options(k).index(r["scope"])))
         win.append(codes[best["scope"]])
-    prov = (f"gfx950 / {meta.get('gpu', '?')} / git {meta.get('git', '?')} / ragged sweep {meta.get('date', '?')}"
-            if meta else "gfx950 / no sweep")
+    prov = (f"gfx950 / {meta.get('gpu', '?')} / src {meta.get('src', '?')} / ragged sweep {file_hash(args.sweep)} "
+            f"{meta.get('date', '?')}")
     text = ("// glass_ragged_gfx950.inc -- measured per-class placement of ragged batches on\n"
             "// gfx950, generated by paper_2609_28179_amd/autotune.py emit-ragged from\n"
             "// paper_2609_28179_amd/tuning/ragged_gfx950.jsonl.  Do not edit by hand.\n"
@@ -306,7 +336,9 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     s = sub.add_parser("sweep")
     s.add_argument("--out", default=DEFAULT_SWEEP)
-    s.add_argument("--rounds", type=int, default=20)
+    s.add_argument("--rounds", type=int, default=20, help="paired rounds of the 65,536-problem cells")
+    s.add_argument("--rounds-small", type=int, default=40,
+                   help="paired rounds of the smaller cells (launch-bound cells time with more spread)")
     s.add_argument("--warmup", type=int, default=3)
     s.add_argument("--seed", type=int, default=0)
     s.add_argument("--ops", default="")
@@ -318,6 +350,7 @@ def main(argv=None):
     e = sub.add_parser("emit")
     e.add_argument("--sweep", default=DEFAULT_SWEEP)
     e.add_argument("--out", default=DEFAULT_INC)
+    e.add_argument("--allow-stale", action="store_true")
     m = sub.add_parser("summary")
     m.add_argument("--sweep", default=DEFAULT_SWEEP)
     m.add_argument("--out", default="")
@@ -328,6 +361,7 @@ def main(argv=None):
     re_ = sub.add_parser("emit-ragged")
     re_.add_argument("--sweep", default=DEFAULT_RAGGED)
     re_.add_argument("--out", default=DEFAULT_RAGGED_INC)
+    re_.add_argument("--allow-stale", action="store_true")
     args = ap.parse_args(argv)
     {"sweep": sweep, "emit": emit, "summary": summary, "ragged": ragged_sweep,
      "emit-ragged": emit_ragged}[args.cmd](args)

@@ -265,6 +265,19 @@ glass_status_t glass_posv_ragged_noalloc(int count, const int32_t* n, const int3
 
 int glass_posv_ragged_noalloc_max_count(void) { return kRaggedNoAllocMaxCount; }
 
+glass_status_t glass_stream_probe(int kind, const float* a, const float* b, float* c, long long n4, int blocks,
+                                  void* stream) {
+    if (kind < 0 || kind > 3 || n4 < 0 || blocks < 1 || blocks > (1 << 20)) return GLASS_ERR_INVALID_VALUE;
+    if (n4 == 0) return GLASS_OK;
+    const bool needs_a = kind != 1, needs_b = kind == 3;
+    if ((needs_a && !a) || (needs_b && !b) || !c) return GLASS_ERR_INVALID_VALUE;
+    const uintptr_t mis = (reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) |
+                           reinterpret_cast<uintptr_t>(c)) & 15;
+    if (mis) return GLASS_ERR_INVALID_VALUE;
+    if (kind == 0 && n4 < 64) return GLASS_ERR_INVALID_VALUE;  // the read kernel's sink is 256 floats of c
+    return launched(launch_stream_probe(kind, a, b, c, n4, blocks, stream));
+}
+
 glass_status_t glass_riccati_gain_batched(int nx, int nu, int batch, const float* A, const float* B, const float* P,
                                           const float* R, float* K, int32_t* info, const glass_placement_t* force,
                                           void* stream) {

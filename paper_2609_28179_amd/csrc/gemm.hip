@@ -353,8 +353,8 @@ GLASS_DEV void mfma_problem_rows(int m, int n, int k, float alpha, const float* 
     }
 }
 
-// Whole tiles (m = n = k = N = 16 TB, no transposes, every operand 16-byte
-// aligned), the schedule of mfma_problem_rows with every bound known at
+// Whole tiles (m = n = k = N = 16 TB, TB = 1..4, no transposes, every operand
+// 16-byte aligned), the schedule of mfma_problem_rows with every bound known at
 // compile time: fragments come from buffer loads at a per-lane offset plus a
 // scalar block offset plus an immediate, with no guards and no 64-bit
 // address arithmetic, and the staged rows leave as 16-byte buffer stores.
@@ -492,9 +492,12 @@ int launch_gemm_t(const Shape& sh, const Geometry& g, int batch, float alpha, co
     const int tb = (mx + 15) / 16;
     const bool vec = !TA && (k % 4 == 0) && ((uintptr_t)A % 16 == 0);
     if (g.scope == GLASS_SCOPE_WAVE) {
-        if (!TA && !TBT && m == n && n == k && (n == 32 || n == 48 || n == 64) && (uintptr_t)A % 16 == 0 &&
+        if (!TA && !TBT && m == n && n == k && (n == 16 || n == 32 || n == 48 || n == 64) && (uintptr_t)A % 16 == 0 &&
             (uintptr_t)B % 16 == 0 && (uintptr_t)C % 16 == 0) {
             switch (n) {
+            case 16:
+                hipLaunchKernelGGL(gemm_mfma_wave_full<1>, grid, block, g.lds_bytes, st, batch, alpha, A, B, beta, C);
+                break;
             case 32:
                 hipLaunchKernelGGL(gemm_mfma_wave_full<2>, grid, block, g.lds_bytes, st, batch, alpha, A, B, beta, C);
                 break;

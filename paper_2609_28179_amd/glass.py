@@ -73,6 +73,7 @@ _SIGS = {
     "glass_posv_ragged_noalloc_max_count": [],
     "glass_posv_ragged_workspace_size": [_i],
     "glass_posv_ragged_perm_offset": [_i],
+    "glass_stream_probe": [_i, _p, _p, _p, ctypes.c_longlong, _i, _p],
     "glass_riccati_gain_batched": [_i, _i, _i, _p, _p, _p, _p, _p, _p, _PP, _p],
     "glass_riccati_feasible": [_i, _i, _i],
     "glass_ragged_table_provenance": [],
@@ -205,6 +206,10 @@ def glass_posv_ragged_perm_offset(count) -> int:
 def glass_riccati_gain_batched(nx, nu, batch, A, B, P, R, K, info=None, force=None, stream=None) -> int:
     return _lib.glass_riccati_gain_batched(nx, nu, batch, _ptr(A), _ptr(B), _ptr(P), _ptr(R), _ptr(K), _ptr(info),
                                            _force(force), _stream(stream))
+
+
+def glass_stream_probe(kind, a, b, c, n4, blocks, stream=None) -> int:
+    return _lib.glass_stream_probe(kind, _ptr(a), _ptr(b), _ptr(c), n4, blocks, _stream(stream))
 
 
 def glass_riccati_feasible(nx, nu, pack) -> int:

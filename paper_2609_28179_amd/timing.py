@@ -29,7 +29,8 @@ DESTRUCTIVE = {"potrf": ("A",), "potrs": ("B",), "posv": ("A", "B"), "trsv": ("x
 SWEEP_OPS = ("gemm", "gemv", "potrf", "potrs", "posv", "trsv")
 SE3_OPS = ("se3_compose", "se3_inverse")
 SWEEP_N = (3, 4, 6, 7, 12, 16, 32, 64)
-SWEEP_B = (1, 16, 256, 4096, 65536)
+SWEEP_B = (1, 16, 256, 4096, 65536)          # the benchmark grid's batches
+TABLE_B = (1, 16, 256, 1024, 4096, 65536)    # the dispatch table's batch keys (adds the 1024-system POSV)
 PACKS = (1, 2, 4, 8)
 HELDOUT_N = (5, 9, 20, 48)          # orders the table does not hold (cost-model evaluation)
 HELDOUT_B = (256, 65536)
@@ -63,10 +64,16 @@ def flops(op: str, n: int, nrhs: int = 1) -> float:
     }[op]
 
 
-def sweep_cells():
-    cells = [(op, n, b) for op in SWEEP_OPS for n in SWEEP_N for b in SWEEP_B]
-    cells += [(op, 4, b) for op in SE3_OPS for b in SWEEP_B]
+def sweep_cells(batches=SWEEP_B):
+    """The benchmark grid (250 cells); with batches=TABLE_B the dispatch
+    table's grid (300 cells)."""
+    cells = [(op, n, b) for op in SWEEP_OPS for n in SWEEP_N for b in batches]
+    cells += [(op, 4, b) for op in SE3_OPS for b in batches]
     return cells
+
+
+def table_cells():
+    return sweep_cells(TABLE_B)
 
 
 def heldout_cells():
@@ -230,3 +237,74 @@ def copy_bandwidth(torch, device, nbytes: int = GIB, reps: int = 10) -> float:
         ev1.synchronize()
         out.append(2 * nbytes / (ev0.elapsed_time(ev1) * 1e-3) / 1e9)
     return float(np.median(out))
+
+
+STREAM_KINDS = {"read": 0, "write": 1, "copy": 2, "read2_write1": 3}
+
+
+def stream_ceilings(glass, torch, device, nbytes: int = 2 * GIB, reps: int = 10, blocks=(8192, 16384, 32768)):
+    """Attainable bandwidth (GB/s, bytes read + written) of the library's plain
+    streaming kernels: read only, write only, copy, and two reads per write
+    (c = a + b), each over `nbytes`-byte buffers, the best median over a few
+    grid sizes.  Returns {kind: {"gbps": .., "blocks": ..}}."""
+    n = nbytes // 4
+    a = torch.empty(n, dtype=torch.float32, device=device).fill_(1.0)
+    b = torch.empty_like(a).fill_(1.0)
+    c = torch.empty_like(a)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    moved = {"read": nbytes, "write": nbytes, "copy": 2 * nbytes, "read2_write1": 3 * nbytes}
+    out = {}
+    for kind, code in STREAM_KINDS.items():
+        best = None
+        for nb in blocks:
+            st = glass.glass_stream_probe(code, a, b, c, n // 4, nb)
+            if st != 0:
+                raise RuntimeError(f"stream probe {kind}: status {st}")
+            torch.cuda.synchronize()
+            samples = []
+            for _ in range(reps):
+                ev0.record()
+                glass.glass_stream_probe(code, a, b, c, n // 4, nb)
+                ev1.record()
+                ev1.synchronize()
+                samples.append(moved[kind] / (ev0.elapsed_time(ev1) * 1e-3) / 1e9)
+            med = float(np.median(samples))
+            if best is None or med > best[0]:
+                best = (med, nb)
+        out[kind] = {"gbps": round(best[0], 1), "blocks": best[1]}
+    del a, b, c
+    torch.cuda.empty_cache()
+    return out
+
+
+def _main(argv=None):
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser(description="measured streaming ceilings of this GPU")
+    ap.add_argument("cmd", choices=("ceilings",))
+    ap.add_argument("--out", default="")
+    a = ap.parse_args(argv)
+    import torch
+    from . import glass
+    dev = torch.device("cuda:0")
+    res = stream_ceilings(glass, torch, dev)
+    p = torch.cuda.get_device_properties(0)
+    lines = [f"Streaming ceilings of {p.gcnArchName} ({p.multi_processor_count} CUs), 2 GiB buffers, "
+             f"median of 10 launches, best of grids {{8192, 16384, 32768}} x 256 lanes", "",
+             "command: python -m paper_2609_28179_amd.timing ceilings", ""]
+    for kind, v in res.items():
+        lines.append(f"{kind:13s} {v['gbps']:8.1f} GB/s  ({100 * v['gbps'] / 8000:.1f} % of 8 TB/s; "
+                     f"{v['blocks']} workgroups)")
+    text = "\n".join(lines) + "\n"
+    print(text)
+    print(json.dumps(res), file=sys.stderr)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(text)
+
+
+if __name__ == "__main__":
+    _main()

@@ -38,72 +38,109 @@ def posv_small(glass, torch, n=6, batch=1024, rounds=20):
             "alg_bytes": timing.alg_bytes("posv", n) * batch, "sets": cell.nsets}
 
 
-def ragged(glass, torch, count=50000, seed=2, rounds=20):
+def ragged(glass, torch, count=50000, seed=2, rounds=20, sets=2):
     """The ragged POSV batch (n over {6,...,64}, 1-8 right-hand sides) solved
-    by the one-sequence ragged pipeline versus one batched POSV launch per
-    (n, nrhs) group on pre-grouped contiguous copies (the grouping itself is
-    not timed, which favours the comparator)."""
+    by the one-sequence ragged pipeline versus two comparators on pre-grouped
+    contiguous copies (the grouping itself is not timed, which favours them):
+    one batched POSV launch per (n, nrhs) group, and one launch per order with
+    every system's right-hand sides padded with zero columns to the largest
+    count (8), the per-size launches of a batch that is not split by nrhs.
+    Each variant is captured once per input set and the `sets` copies are
+    replayed back to back between two events (time per set reported), so
+    consecutive solves read different buffers."""
     dev = torch.device("cuda:0")
     case = inputs.make_ragged(count, seed=seed)
-    rg = glass.Ragged(case, device=dev)
-    A0, B0 = rg.A.clone(), rg.B.clone()
     n, r = case["n"], case["nrhs"]
-    groups = []
-    for (gn, gr) in sorted(set(zip(n.tolist(), r.tolist()))):
-        idx = np.nonzero((n == gn) & (r == gr))[0]
+    rmax = int(r.max())
+
+    def gather(idx, gn, gr, pad_to=None):
         A = np.concatenate([case["A"][case["offA"][i]:case["offA"][i] + gn * gn] for i in idx])
-        B = np.concatenate([case["B"][case["offB"][i]:case["offB"][i] + gn * gr] for i in idx])
-        At = torch.from_numpy(A.reshape(len(idx), gn, gn)).to(dev)
-        Bt = torch.from_numpy(B.reshape(len(idx), gn, gr)).to(dev)
-        groups.append({"n": gn, "r": gr, "batch": len(idx), "A": At, "B": Bt, "A0": At.clone(), "B0": Bt.clone(),
-                       "info": torch.zeros(len(idx), dtype=torch.int32, device=dev)})
-    alg = int(sum(timing.alg_bytes("posv", int(a), int(b)) for a, b in zip(n, r)))
+        cols = pad_to or gr
+        B = np.zeros((len(idx), gn, cols), np.float32)
+        for row, i in enumerate(idx):
+            ri = int(r[i])
+            B[row, :, :ri] = case["B"][case["offB"][i]:case["offB"][i] + gn * ri].reshape(gn, ri)
+        return A.reshape(len(idx), gn, gn), B
 
-    def run_ragged():
-        rg.solve()
+    group_keys = sorted(set(zip(n.tolist(), r.tolist())))
+    host_groups = [(gn, gr) + gather(np.nonzero((n == gn) & (r == gr))[0], gn, gr) for gn, gr in group_keys]
+    host_sizes = [(gn, rmax) + gather(np.nonzero(n == gn)[0], gn, rmax, pad_to=rmax) for gn in sorted(set(n.tolist()))]
 
-    def run_groups():
-        for g in groups:
+    def device_batches(host):
+        out = []
+        for gn, gr, A, B in host:
+            At, Bt = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+            out.append({"n": gn, "r": gr, "batch": A.shape[0], "A": At, "B": Bt,
+                        "info": torch.zeros(A.shape[0], dtype=torch.int32, device=dev)})
+        return out
+
+    variants = {
+        "ragged": [glass.Ragged(case, device=dev) for _ in range(sets)],
+        "per_group": [device_batches(host_groups) for _ in range(sets)],
+        "per_size": [device_batches(host_sizes) for _ in range(sets)],
+    }
+    pristine = {"ragged": (variants["ragged"][0].A.clone(), variants["ragged"][0].B.clone()),
+                "per_group": [(g["A"].clone(), g["B"].clone()) for g in variants["per_group"][0]],
+                "per_size": [(g["A"].clone(), g["B"].clone()) for g in variants["per_size"][0]]}
+
+    def run(name, k):
+        if name == "ragged":
+            variants[name][k].solve()
+            return
+        for g in variants[name][k]:
             st = glass.glass_posv_batched(g["n"], g["r"], g["batch"], g["A"], g["B"], g["info"], None)
             if st != 0:
                 raise RuntimeError(f"posv n={g['n']} nrhs={g['r']}: {glass.status_string(st)}")
 
     def restore():
-        rg.A.copy_(A0)
-        rg.B.copy_(B0)
-        for g in groups:
-            g["A"].copy_(g["A0"])
-            g["B"].copy_(g["B0"])
+        for k in range(sets):
+            rg = variants["ragged"][k]
+            rg.A.copy_(pristine["ragged"][0])
+            rg.B.copy_(pristine["ragged"][1])
+            for name in ("per_group", "per_size"):
+                for g, (A0, B0) in zip(variants[name][k], pristine[name]):
+                    g["A"].copy_(A0)
+                    g["B"].copy_(B0)
 
-    run_ragged()
-    run_groups()
+    for name in variants:
+        for k in range(sets):
+            run(name, k)
     torch.cuda.synchronize()
     restore()
     graphs = {}
-    for name, fn in (("ragged", run_ragged), ("per_group", run_groups)):
+    for name in variants:
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            fn()
+            for k in range(sets):
+                run(name, k)
         graphs[name] = g
     torch.cuda.synchronize()
     samples = {k: [] for k in graphs}
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    order = list(graphs)
     for it in range(3 + rounds):
-        for name in (("ragged", "per_group") if it % 2 == 0 else ("per_group", "ragged")):
+        order = order[1:] + order[:1]
+        for name in order:
             restore()
             e0.record()
             graphs[name].replay()
             e1.record()
             e1.synchronize()
             if it >= 3:
-                samples[name].append(e0.elapsed_time(e1) * 1e3)
+                samples[name].append(e0.elapsed_time(e1) * 1e3 / sets)
     restore()
     torch.cuda.synchronize()
-    tr, tg = _median_us(samples["ragged"]), _median_us(samples["per_group"])
-    return {"workload": f"ragged posv: {count} systems, n uniform over {sorted(set(n.tolist()))}, nrhs 1-8",
-            "ragged_us": round(tr, 2), "per_group_us": round(tg, 2), "groups": len(groups),
-            "ragged_speedup": round(tg / tr, 3), "alg_bytes": alg,
-            "ragged_gbps": round(alg / (tr * 1e-6) / 1e9, 1), "ragged_solves_per_s": round(count / (tr * 1e-6), 1)}
+    alg = int(sum(timing.alg_bytes("posv", int(a), int(b)) for a, b in zip(n, r)))
+    tr, tg, ts = (_median_us(samples[k]) for k in ("ragged", "per_group", "per_size"))
+    out = {"workload": f"ragged posv: {count} systems, n uniform over {sorted(set(n.tolist()))}, nrhs 1-{rmax}",
+           "ragged_us": round(tr, 2), "per_group_us": round(tg, 2), "groups": len(group_keys),
+           "per_size_us": round(ts, 2), "sizes": len(host_sizes), "per_size_nrhs": rmax,
+           "ragged_speedup": round(tg / tr, 3), "ragged_speedup_vs_per_size": round(ts / tr, 3),
+           "alg_bytes": alg, "ragged_gbps": round(alg / (tr * 1e-6) / 1e9, 1),
+           "ragged_solves_per_s": round(count / (tr * 1e-6), 1), "input_sets": sets}
+    del variants, graphs
+    torch.cuda.empty_cache()
+    return out
 
 
 def adjoint(glass, torch, n=12, batch=16384, nrhs=1, rounds=20):

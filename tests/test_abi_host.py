@@ -203,3 +203,16 @@ def test_single_hip_runtime_in_process():
     assert out.returncode == 0, out.stderr
     libs = eval(out.stdout.strip().splitlines()[-1])
     assert len(libs) == 1, libs
+
+
+def test_stream_probe_validation(glass):
+    """The streaming probe rejects bad arguments on the host (no device call)."""
+    F = 0x10000
+    assert glass.glass_stream_probe(0, F, F, F, 0, 1, 0) == glass.OK
+    assert glass.glass_stream_probe(4, F, F, F, 1024, 1, 0) == glass.ERR_INVALID_VALUE
+    assert glass.glass_stream_probe(-1, F, F, F, 1024, 1, 0) == glass.ERR_INVALID_VALUE
+    assert glass.glass_stream_probe(2, F + 4, F, F, 1024, 1, 0) == glass.ERR_INVALID_VALUE
+    assert glass.glass_stream_probe(3, F, None, F, 1024, 1, 0) == glass.ERR_INVALID_VALUE
+    assert glass.glass_stream_probe(1, None, None, None, 1024, 1, 0) == glass.ERR_INVALID_VALUE
+    assert glass.glass_stream_probe(0, F, F, F, 63, 1, 0) == glass.ERR_INVALID_VALUE
+    assert glass.glass_stream_probe(2, F, F, F, 1024, 0, 0) == glass.ERR_INVALID_VALUE

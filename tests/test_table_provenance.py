@@ -1,8 +1,12 @@
 """Host check of the committed dispatch table against the committed sweep it
 was generated from: every entry is the argmin-of-medians placement of its
-cell (ties to the smaller scope, then pack), and no tuned entry is slower
-than the fixed wave/P=1 placement measured in the same paired rounds.  No
-GPU: this reads the JSONL records and the generated header only."""
+cell (ties to the smaller scope, then pack), no tuned entry is slower than
+the fixed wave/P=1 placement measured in the same paired rounds, the table
+names the hash of the kernel sources the sweep measured (which must be the
+sources in the tree) and the hash of the sweep file, and a re-measurement
+(the other half of the paired rounds) lands in the 5 % margin set.  No GPU:
+this reads the JSONL records, the generated headers and the library's
+provenance strings only."""
 import json
 import os
 
@@ -27,7 +31,7 @@ def test_table_is_the_sweep_argmin():
     recs = _records()
     ch = autotune.choose(recs)
     table = pref.load_table(INC)
-    cells = timing.sweep_cells()
+    cells = timing.table_cells()
     assert set(ch) == set(cells), "the sweep must cover every table cell"
     for (op, n, b) in cells:
         want = tuple(ch[(op, n, b)]["winner"])
@@ -58,17 +62,37 @@ def test_ragged_table_is_the_ragged_sweep_argmin():
     assert built == [glass.RAGGED_SCOPES[best[k][1]] for k in range(8)]
 
 
+def _meta(path):
+    for line in open(path):
+        r = json.loads(line)
+        if r.get("kind") == "meta":
+            return r
+    raise AssertionError(f"no meta line in {path}")
+
+
+def test_provenance_names_the_sources_and_the_sweep():
+    """The built tables carry the hash of the kernel sources their sweeps
+    measured and the hash of the sweep files; both must match the tree."""
+    for prov, sweep, kind in ((glass.glass_table_provenance(), autotune.DEFAULT_SWEEP, "table"),
+                              (glass.glass_ragged_table_provenance(), autotune.DEFAULT_RAGGED, "ragged")):
+        src = autotune.source_hash(kind)
+        assert _meta(sweep).get("src") == src, f"{sweep} was measured on other {kind} sources than the tree's"
+        assert f"src {src} " in prov, (prov, src)
+        assert f"sweep {autotune.file_hash(sweep)} " in prov, (prov, sweep)
+
+
+# Cells whose halves disagree by more than the 5 % margin, each with the
+# reason (none at present; an entry needs its measured spread stated).
+HALF_SWEEP_EXCEPTIONS = {}
+
+
 def test_table_choice_is_stable_across_half_sweeps():
-    """The pin of the table choice itself: a re-measurement must pick a
-    placement inside the first measurement's margin set (within 5 % of its
-    best).  Every placement of a cell was timed in the same 20 paired,
-    shuffled rounds, so the even and the odd rounds are two independent
-    half-sweeps; each half's winner must be within the margin of the other
-    half's best.  The margin is widened to the cell's own measured spread
-    where that is larger: 1 + 2 x the largest interquartile range over
-    median among its placements (a few launch-bound cells of ~3 us time
-    bimodally, ~0.25 us apart, and their halves fall into different
-    modes)."""
+    """The pin of the table choice itself (the 5 % dispatch margin of
+    Sec. IV-A): a re-measurement must pick a placement inside the first
+    measurement's margin set.  Every placement of a cell was timed in the
+    same paired, shuffled rounds, so the even and the odd rounds are two
+    independent half-sweeps; each half's winner must lie within 5 % of the
+    other half's best."""
     import numpy as np
     by_cell = {}
     for r in _records():
@@ -77,11 +101,9 @@ def test_table_choice_is_stable_across_half_sweeps():
     for cell, samples in by_cell.items():
         halves = [{pl: float(np.median(s[sl])) for pl, s in samples.items()} for sl in (slice(0, None, 2),
                                                                                          slice(1, None, 2))]
-        spread = max((np.percentile(s, 75) - np.percentile(s, 25)) / np.median(s) for s in samples.values())
-        margin = max(autotune.MARGIN, 1 + 2 * spread)
         for a, b in ((0, 1), (1, 0)):
             win = min(halves[a], key=lambda pl: (halves[a][pl], pl))
             best = min(halves[b].values())
-            if halves[b][win] > best * margin:
+            if halves[b][win] > best * autotune.MARGIN and cell not in HALF_SWEEP_EXCEPTIONS:
                 bad.append((cell, win, round(halves[b][win] / best, 3)))
     assert not bad, bad
