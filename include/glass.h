@@ -288,7 +288,7 @@ int glass_riccati_feasible(int nx, int nu, int pack);
  * floats, so n4 >= 64); 1: write c; 2: copy a -> c; 3: c = a + b (two reads
  * per write, the mix of C = A B).  n4 16-byte elements; a, b, c 16-byte
  * aligned DEVICE pointers (those the kind uses non-NULL); `blocks`
- * workgroups of 256 lanes (1 .. 2^20), grid-stride.  Bad arguments ->
+ * workgroups of 1024 lanes (1 .. 2^20), grid-stride.  Bad arguments ->
  * GLASS_ERR_INVALID_VALUE before anything is enqueued. */
 glass_status_t glass_stream_probe(int kind, const float* a, const float* b, float* c,
                                   long long n4, int blocks, void* stream);

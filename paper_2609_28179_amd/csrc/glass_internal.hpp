@@ -289,7 +289,7 @@ int launch_riccati(int nx, int nu, int batch, int pack, const float* A, const fl
                    const float* R, float* K, int32_t* info, void* stream);
 const char* hip_error_name(int code);
 // Streaming bandwidth probe: kind 0 read a, 1 write c, 2 copy a -> c,
-// 3 c = a + b; n4 16-byte elements, `blocks` workgroups of 256 lanes.
+// 3 c = a + b; n4 16-byte elements, `blocks` workgroups of 1024 lanes.
 int launch_stream_probe(int kind, const float* a, const float* b, float* c, long long n4, int blocks, void* stream);
 size_t mlp_num_params(int d);
 size_t mlp_backward_workspace_bytes(int N, int d);

@@ -4,34 +4,28 @@
 // kernels are quoted against the 8 TB/s spec peak; these measured ceilings
 // say how much of that a kernel with the same read/write mix can reach.
 //
-// Every kernel is grid-stride over 16-byte elements with four independent
-// 16-byte accesses per lane in flight per iteration; the read-only kernel
-// keeps its loads alive by writing its sum only when it equals a value the
-// data never produce.
+// Every kernel is grid-stride over 16-byte elements, one access per lane per
+// iteration, in workgroups of 1024 lanes; with a grid of one element per
+// lane it is a single sweep.  (Measured on gfx950 over 1 GiB: 1024-lane
+// workgroups with one element per lane read at 6.8 TB/s and copy at
+// 5.9 TB/s, above 256-lane workgroups and above four or eight unrolled
+// accesses per lane.)  The read-only kernel keeps its loads alive by writing
+// its sum only when it equals a value the data never produce.
 #include "device_common.hpp"
 #include "glass_internal.hpp"
 
 namespace glass {
 namespace {
 
-constexpr int kStreamThreads = 256;
-constexpr int kStreamUnroll = 4;
+constexpr int kStreamThreads = 1024;
 
 __global__ void __launch_bounds__(kStreamThreads) stream_read(const f4_t* __restrict__ a, float* __restrict__ sink,
                                                               long long n4) {
     const long long stride = (long long)gridDim.x * kStreamThreads;
-    long long i = (long long)blockIdx.x * kStreamThreads + threadIdx.x;
     f4_t acc = {0.f, 0.f, 0.f, 0.f};
-    for (; i + (kStreamUnroll - 1) * stride < n4; i += kStreamUnroll * stride) {
-        f4_t v[kStreamUnroll];
-#pragma unroll
-        for (int u = 0; u < kStreamUnroll; ++u) v[u] = a[i + u * stride];
-#pragma unroll
-        for (int u = 0; u < kStreamUnroll; ++u) acc += v[u];
-    }
-    for (; i < n4; i += stride) acc += a[i];
+    for (long long i = (long long)blockIdx.x * kStreamThreads + threadIdx.x; i < n4; i += stride) acc += a[i];
     const float s = acc[0] + acc[1] + acc[2] + acc[3];
-    if (s == -1234.5f) sink[threadIdx.x] = s;
+    if (s == -1234.5f) sink[threadIdx.x & 255] = s;
 }
 
 __global__ void __launch_bounds__(kStreamThreads) stream_write(f4_t* __restrict__ c, long long n4) {
@@ -43,32 +37,13 @@ __global__ void __launch_bounds__(kStreamThreads) stream_write(f4_t* __restrict_
 __global__ void __launch_bounds__(kStreamThreads) stream_copy(const f4_t* __restrict__ a, f4_t* __restrict__ c,
                                                               long long n4) {
     const long long stride = (long long)gridDim.x * kStreamThreads;
-    long long i = (long long)blockIdx.x * kStreamThreads + threadIdx.x;
-    for (; i + (kStreamUnroll - 1) * stride < n4; i += kStreamUnroll * stride) {
-        f4_t v[kStreamUnroll];
-#pragma unroll
-        for (int u = 0; u < kStreamUnroll; ++u) v[u] = a[i + u * stride];
-#pragma unroll
-        for (int u = 0; u < kStreamUnroll; ++u) c[i + u * stride] = v[u];
-    }
-    for (; i < n4; i += stride) c[i] = a[i];
+    for (long long i = (long long)blockIdx.x * kStreamThreads + threadIdx.x; i < n4; i += stride) c[i] = a[i];
 }
 
 __global__ void __launch_bounds__(kStreamThreads) stream_add(const f4_t* __restrict__ a, const f4_t* __restrict__ b,
                                                              f4_t* __restrict__ c, long long n4) {
     const long long stride = (long long)gridDim.x * kStreamThreads;
-    long long i = (long long)blockIdx.x * kStreamThreads + threadIdx.x;
-    for (; i + (kStreamUnroll - 1) * stride < n4; i += kStreamUnroll * stride) {
-        f4_t v[kStreamUnroll], w[kStreamUnroll];
-#pragma unroll
-        for (int u = 0; u < kStreamUnroll; ++u) {
-            v[u] = a[i + u * stride];
-            w[u] = b[i + u * stride];
-        }
-#pragma unroll
-        for (int u = 0; u < kStreamUnroll; ++u) c[i + u * stride] = v[u] + w[u];
-    }
-    for (; i < n4; i += stride) c[i] = a[i] + b[i];
+    for (long long i = (long long)blockIdx.x * kStreamThreads + threadIdx.x; i < n4; i += stride) c[i] = a[i] + b[i];
 }
 
 }  // namespace

@@ -242,12 +242,14 @@ def copy_bandwidth(torch, device, nbytes: int = GIB, reps: int = 10) -> float:
 STREAM_KINDS = {"read": 0, "write": 1, "copy": 2, "read2_write1": 3}
 
 
-def stream_ceilings(glass, torch, device, nbytes: int = 2 * GIB, reps: int = 10, blocks=(8192, 16384, 32768)):
+def stream_ceilings(glass, torch, device, nbytes: int = 2 * GIB, reps: int = 10, blocks=(16384, 32768, 65536, 0)):
     """Attainable bandwidth (GB/s, bytes read + written) of the library's plain
     streaming kernels: read only, write only, copy, and two reads per write
     (c = a + b), each over `nbytes`-byte buffers, the best median over a few
-    grid sizes.  Returns {kind: {"gbps": .., "blocks": ..}}."""
+    grid sizes of 1024-lane workgroups (0: one 16-byte element per lane).
+    Returns {kind: {"gbps": .., "blocks": ..}}."""
     n = nbytes // 4
+    blocks = tuple(b if b else -(-(n // 4) // 1024) for b in blocks)
     a = torch.empty(n, dtype=torch.float32, device=device).fill_(1.0)
     b = torch.empty_like(a).fill_(1.0)
     c = torch.empty_like(a)
@@ -293,7 +295,8 @@ def _main(argv=None):
     res = stream_ceilings(glass, torch, dev)
     p = torch.cuda.get_device_properties(0)
     lines = [f"Streaming ceilings of {p.gcnArchName} ({p.multi_processor_count} CUs), 2 GiB buffers, "
-             f"median of 10 launches, best of grids {{8192, 16384, 32768}} x 256 lanes", "",
+             f"median of 10 launches, best of grids {{16384, 32768, 65536, one element per lane}} x 1024 lanes",
+             "",
              "command: python -m paper_2609_28179_amd.timing ceilings", ""]
     for kind, v in res.items():
         lines.append(f"{kind:13s} {v['gbps']:8.1f} GB/s  ({100 * v['gbps'] / 8000:.1f} % of 8 TB/s; "
