@@ -49,15 +49,42 @@ TABLE_SOURCES = ("glass_internal.hpp", "device_common.hpp", "chol.hip", "chol_de
 RAGGED_SOURCES = ("glass_internal.hpp", "device_common.hpp", "chol_device.hpp", "chol_blk.hpp", "ragged.hip")
 
 
+def _code_only(text: str) -> str:
+    """C/C++ source without its comments and with runs of whitespace folded,
+    so that a hash over it changes with the code and not with the prose.
+    String and character literals are kept whole (a // inside one is not a
+    comment)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_hash(kind: str = "table") -> str:
-    """First 16 hex digits of a SHA-256 over the sources a table is measured
-    on (TABLE_SOURCES or RAGGED_SOURCES under csrc/, in that order).  A sweep
-    records it when it starts; emit stamps it into the table and refuses a
-    sweep taken on other sources."""
+    """First 16 hex digits of a SHA-256 over the code of the sources a table
+    is measured on (TABLE_SOURCES or RAGGED_SOURCES under csrc/, in that
+    order, comments removed).  A sweep records it when it starts; emit stamps
+    it into the table and refuses a sweep taken on other code."""
     h = hashlib.sha256()
     for f in TABLE_SOURCES if kind == "table" else RAGGED_SOURCES:
         h.update(f.encode() + b"\0")
-        h.update(open(os.path.join(PKG, "csrc", f), "rb").read())
+        h.update(_code_only(open(os.path.join(PKG, "csrc", f)).read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -107,3 +107,16 @@ def test_table_choice_is_stable_across_half_sweeps():
             if halves[b][win] > best * autotune.MARGIN and cell not in HALF_SWEEP_EXCEPTIONS:
                 bad.append((cell, win, round(halves[b][win] / best, 3)))
     assert not bad, bad
+
+
+def test_source_hash_ignores_comments_not_code():
+    """The provenance hash follows the code: comments and whitespace runs do
+    not change it, a changed token does, and // or /* inside a string
+    literal is code."""
+    a = "int f(int x) { return x + 1; } // one\n/* two */ const char* s = \"a//b\";"
+    b = "int f(int x) {\n  return x + 1;  }\n/* other */ const char* s = \"a//b\"; // three"
+    c = "int f(int x) { return x + 2; } const char* s = \"a//b\";"
+    d = "int f(int x) { return x + 1; } const char* s = \"a\";"
+    assert autotune._code_only(a) == autotune._code_only(b)
+    assert autotune._code_only(a) != autotune._code_only(c)
+    assert autotune._code_only(a) != autotune._code_only(d)
