@@ -8,7 +8,8 @@
 namespace glass {
 namespace {
 
-// op: 0 POTRF, 1 POSV, 2 POTRS, 3 TRSV (trans: 0 forward, 1 backward).
+// op: 0 POTRF, 1 POSV, 2 POTRS, 3 TRSV (trans: 0 forward, 1 backward), 4 POSV
+// with one right-hand side.
 template <int NBLK, int OP, bool FULL>
 __global__ void __launch_bounds__(512) chol_blk(int n, int nrhs, int trans, int batch, float* __restrict__ A,
                                                 float* __restrict__ B, int32_t* __restrict__ info) {
@@ -21,11 +22,11 @@ __global__ void __launch_bounds__(512) chol_blk(int n, int nrhs, int trans, int 
     const int w = wave_index(), lane = threadIdx.x & 63;
     const long long p = (long long)blockIdx.x * (blockDim.x >> 6) + w;
     if (p >= batch) return;
-    const int nr = OP == 3 ? 1 : nrhs;
+    const int nr = OP >= 3 ? 1 : nrhs;
     const bool vec = FULL || ((n & 3) == 0 && aligned16(A));
     const int inf = blk_one<NBLK, OP, FULL>(A + p * n * n, OP == 0 ? nullptr : B + p * n * nr, n, nrhs, trans, vec,
                                             lds + (size_t)w * kBlkRegionFloats, lane);
-    if (OP <= 1 && info && lane == 0) info[p] = inf;
+    if ((OP <= 1 || OP == 4) && info && lane == 0) info[p] = inf;
 }
 
 // One right-hand side (TRSV; POTRS with nrhs = 1) on VALU, no inverses:
@@ -40,7 +41,7 @@ __global__ void __launch_bounds__(512) chol_blk_solve1(int n, int batch, const f
     const int q = lane >> 4, r = lane & 15;
     f4_t T[NBLK * (NBLK + 1) / 2];
     blk_load<NBLK, FULL>(T, L + p * n * n, n, q, r);
-    blk_solve1<NBLK, FULL, FWD, BWD>(T, B + p * n, n, lds + (size_t)w * kBlkRegionFloats, q, r);
+    blk_solve1<NBLK, FULL, FWD, BWD>(T, B + p * n, n, lds + (size_t)w * kBlkSolve1Floats, q, r);
 }
 
 }  // namespace
@@ -53,7 +54,10 @@ int launch_chol_blk(const Shape& sh, const Geometry& g, int batch, float* A, flo
     if (n < kBlkMinN || n > kMaxN) return (int)hipErrorInvalidValue;
     const int nblk = n <= 32 ? 2 : n <= 48 ? 3 : 4;
     const bool full = n == 16 * nblk && (reinterpret_cast<uintptr_t>(A) & 15) == 0;
-    const int op = sh.op == GLASS_OP_POTRF ? 0 : sh.op == GLASS_OP_POSV ? 1 : sh.op == GLASS_OP_POTRS ? 2 : 3;
+    const int op = sh.op == GLASS_OP_POTRF ? 0
+                   : sh.op == GLASS_OP_POSV ? (sh.nrhs == 1 ? 4 : 1)
+                   : sh.op == GLASS_OP_POTRS ? 2
+                                             : 3;
     dim3 grid((unsigned)g.grid), block(g.threads);
     if (op == 3 || (op == 2 && sh.nrhs == 1)) {
         const int mode = op == 2 ? 3 : sh.trans == 0 ? 1 : 2;  // 1: L y = b, 2: L^T x = b, 3: both
@@ -76,7 +80,8 @@ int launch_chol_blk(const Shape& sh, const Geometry& g, int batch, float* A, flo
                            A, B, info);                                                                        \
         return (int)hipGetLastError();                                                                         \
     }
-#define BLK_OPS(NBLK, FULL) BLK(NBLK, 0, FULL) BLK(NBLK, 1, FULL) BLK(NBLK, 2, FULL) BLK(NBLK, 3, FULL)
+#define BLK_OPS(NBLK, FULL) \
+    BLK(NBLK, 0, FULL) BLK(NBLK, 1, FULL) BLK(NBLK, 2, FULL) BLK(NBLK, 3, FULL) BLK(NBLK, 4, FULL)
     BLK_OPS(2, false) BLK_OPS(2, true) BLK_OPS(3, false) BLK_OPS(3, true) BLK_OPS(4, false) BLK_OPS(4, true)
 #undef BLK_OPS
 #undef BLK

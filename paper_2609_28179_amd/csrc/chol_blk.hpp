@@ -45,6 +45,7 @@ namespace glass {
 constexpr int kXS = 20;  // LDS row stride of a 16 x 16 exchange block
 constexpr int kRS = 68;  // LDS row stride of a staged block row of L (64 + 4)
 static_assert(16 * kRS <= kBlkRegionFloats && 4 * 16 * kXS <= kBlkRegionFloats, "LDS region");
+static_assert(16 * kXS <= kBlkSolve1Floats, "LDS region of the one-column solves");
 
 constexpr int BI(int i, int j) { return i * (i + 1) / 2 + j; }
 
@@ -473,14 +474,19 @@ GLASS_DEV void blk_solve1(const f4_t (&T)[NBLK * (NBLK + 1) / 2], float* bg, int
 }
 
 // One problem: factor (POTRF, POSV) or take L as given (POTRS, TRSV), then
-// solve.  op: 0 POTRF, 1 POSV, 2 POTRS, 3 TRSV (trans: 0 forward, 1 backward);
-// Ag is A (L for the solves), Bg the problem's [n][nr] right-hand sides (nr =
-// 1 for TRSV); vec: Ag 16-byte aligned with n % 4 == 0.  xs: the wavefront's
-// kBlkRegionFloats of LDS.  Returns info (0 for the solves); a failed
-// factorization leaves B untouched.
+// solve.  op: 0 POTRF, 1 POSV, 2 POTRS, 3 TRSV (trans: 0 forward, 1 backward),
+// 4 POSV with one right-hand side (the factorization of op 1, then the VALU
+// substitution of blk_solve1 on the factor in registers: no inverse of the
+// last diagonal block and no block transposes); Ag is A (L for the solves),
+// Bg the problem's [n][nr] right-hand sides (nr = 1 for TRSV and op 4); vec:
+// Ag 16-byte aligned with n % 4 == 0.  xs: the wavefront's kBlkRegionFloats
+// of LDS.  Returns info (0 for the solves); a failed factorization leaves B
+// untouched.
 template <int NBLK, int OP, bool FULL>
 GLASS_DEV int blk_one(float* Ag, float* Bg, int n, int nrhs, int trans, bool vec, float* xs, int lane) {
     constexpr int NT = NBLK * (NBLK + 1) / 2;
+    constexpr bool FACTOR = OP == 0 || OP == 1 || OP == 4;
+    constexpr bool MFMA_SOLVE = OP >= 1 && OP <= 3;
     const int q = lane >> 4, r = lane & 15;
     f4_t T[NT];
     blk_load<NBLK, FULL>(T, Ag, n, q, r);
@@ -491,18 +497,23 @@ GLASS_DEV int blk_one(float* Ag, float* Bg, int n, int nrhs, int trans, bool vec
         float a[16];
         const float d = diag_rows(T[BI(k, k)], a, xs, q, r);
         float myinv = 1.f;
-        if (OP <= 1) {
+        if (FACTOR) {
             int f = 0;
             SegStep<16, 16, 0>::run(a, f, myinv);
 #pragma unroll
             for (int c = 0; c < 16; ++c) a[c] = c <= r ? a[c] : 0.f;
             if (inf == 0 && f != 0) inf = 16 * k + f;
             store_block_row<NBLK, FULL>(T, k, a, Ag, n, xs, q, r, lane, vec);
+            if (OP == 4)  // L_kk back in T layout: lane (q, r) keeps row r, columns 4 q .. 4 q + 3
+                T[BI(k, k)] = q == 0   ? f4_t{a[0], a[1], a[2], a[3]}
+                              : q == 1 ? f4_t{a[4], a[5], a[6], a[7]}
+                              : q == 2 ? f4_t{a[8], a[9], a[10], a[11]}
+                                       : f4_t{a[12], a[13], a[14], a[15]};
         } else {
             myinv = 1.0f / d;
         }
-        if (OP >= 1 || k + 1 < NBLK) linv[k] = tri_inverse(a, myinv, q, r);
-        if (OP <= 1) {
+        if (MFMA_SOLVE || k + 1 < NBLK) linv[k] = tri_inverse(a, myinv, q, r);
+        if (FACTOR) {
 #pragma unroll
             for (int i = k + 1; i < NBLK; ++i) T[BI(i, k)] = mma(linv[k], T[BI(i, k)], zero4());
 #pragma unroll
@@ -512,6 +523,10 @@ GLASS_DEV int blk_one(float* Ag, float* Bg, int n, int nrhs, int trans, bool vec
                 for (int i = j; i < NBLK; ++i) T[BI(i, j)] = mma(nq, T[BI(i, k)], T[BI(i, j)]);
             }
         }
+    }
+    if (OP == 4) {
+        if (inf == 0) blk_solve1<NBLK, FULL, true, true>(T, Bg, n, xs, q, r);
+        return inf;
     }
     if (OP == 0 || inf != 0) return inf;  // a failed factorization leaves B untouched
     // off-diagonal blocks of L, negated: the forward pass subtracts L_kj Y_j

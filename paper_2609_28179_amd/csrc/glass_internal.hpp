@@ -109,9 +109,27 @@ constexpr int kGemmStageStride = 68;  // LDS row stride of the staged 16-row out
 // 16 x 16 exchange blocks.
 constexpr int kBlkMinN = 25;
 constexpr int kBlkRegionFloats = 1280;
+// With one right-hand side (TRSV; POTRS with nrhs = 1) the blocked kernel
+// passes only a diagonal block through LDS and reserves 16 x 20 floats per
+// wavefront.
+constexpr int kBlkSolve1Floats = 320;
+inline bool blk_solve1_shape(const Shape& s) {
+    return s.n >= kBlkMinN && (s.op == GLASS_OP_TRSV || (s.op == GLASS_OP_POTRS && s.nrhs == 1));
+}
+
+// Square GEMV at wave scope keeps A in registers (no LDS) from order 17 up
+// when rows split into whole 16-byte pieces, and at every order whose staged
+// regions no longer fit eight wavefronts in the LDS budget (from 42 up), so
+// that feasibility stays monotone in the order.
+inline bool gemv_uses_dpp(const Shape& s) {
+    if (s.op != GLASS_OP_GEMV || s.m != s.n || s.n <= 16) return false;
+    return s.n % 4 == 0 || 8 * region_floats(s) * sizeof(float) > kLdsBudgetBytes;
+}
 
 inline size_t wave_region_floats(const Shape& s) {
     switch (s.op) {
+    case GLASS_OP_GEMV:
+        return gemv_uses_dpp(s) ? 0 : region_floats(s);
     case GLASS_OP_GEMM:
         // MFMA path: one 16-row block of C staged for full-row stores
         return gemm_uses_mfma(s) ? (size_t)16 * kGemmStageStride : region_floats(s);
@@ -119,6 +137,7 @@ inline size_t wave_region_floats(const Shape& s) {
     case GLASS_OP_POTRS:
     case GLASS_OP_POSV:
     case GLASS_OP_TRSV:
+        if (blk_solve1_shape(s)) return (size_t)kBlkSolve1Floats;
         return s.n >= kBlkMinN ? (size_t)kBlkRegionFloats : (size_t)8 * bucket8_host(s.n);
     case GLASS_OP_POSV_ADJOINT:
         return (size_t)8 * bucket8_host(s.n);
