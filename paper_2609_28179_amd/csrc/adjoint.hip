@@ -110,17 +110,26 @@ __global__ void __launch_bounds__(512) adjoint_wave(int n, int nrhs, int batch, 
     float* buf = lds + (size_t)w * region;
     const float* Lg = L + p * n * n;
     const long long ob = p * n * nrhs;
+    // the diagonal and the first column of g and x are issued with the rows;
+    // each later column is loaded before the previous one's substitutions
+    const int ro = (lane < n ? lane : 0) * nrhs;
+    const float dg = diag_load(Lg, n, lane);
+    float gn = G[ob + ro], xn = X[ob + ro];
     float a[NB];
     rows_load_lower<NB, true>(a, Lg, n, lane);
-    const float myinv = diag_inv(Lg, n, lane);
+    const float myinv = diag_inv(dg, n, lane);
     float d[NB];
 #pragma unroll
     for (int j = 0; j < NB; ++j) d[j] = 0.f;
     for (int c = 0; c < nrhs; ++c) {
-        float acc = lane < n ? G[ob + lane * nrhs + c] : 0.f;
+        float acc = lane < n ? gn : 0.f;
+        const float xc = lane < n ? xn : 0.f;
+        if (c + 1 < nrhs) {
+            gn = G[ob + ro + c + 1];
+            xn = X[ob + ro + c + 1];
+        }
         acc = wave_fwd<NB>(a, acc, myinv, lane);
         acc = wave_chunks_desc<NB>(a, buf, nullptr, false, n, lane, true, acc, myinv);
-        const float xc = lane < n ? X[ob + lane * nrhs + c] : 0.f;
         if (lane < n) dB[ob + lane * nrhs + c] = acc;
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
@@ -163,20 +172,29 @@ __global__ void __launch_bounds__(512) adjoint_seg(int n, int nrhs, int batch, c
     float* buf = lds + (size_t)w * region;
     float* sb = buf + s * NB * (NB + 4);
     const float* Lb = L + p0 * n * n;
+    // the diagonal and the first column of g and x are issued with the rows
+    // (a lane without a row reads its wave's first problem's entries); each
+    // later column is loaded before the previous one's substitutions
+    const long long ob = (p0 + s) * n * nrhs, ob_safe = row ? ob + i * nrhs : p0 * n * nrhs;
+    const float dg = Lb[row ? s * n * n + i * n + i : 0];
+    float gn = G[ob_safe], xn = X[ob_safe];
     float a[NB];
     seg_load_rows<NB, true>(a, Lb, np, n, s, i);
-    const float myinv = row ? 1.0f / Lb[s * n * n + i * n + i] : 1.f;
+    const float myinv = row ? 1.0f / dg : 1.f;
     seg_rows_to_lds<NB>(a, sb, i);
     wave_sync();
-    const long long ob = (p0 + s) * n * nrhs;
     float d[NB];
 #pragma unroll
     for (int j = 0; j < NB; ++j) d[j] = 0.f;
     for (int c = 0; c < nrhs; ++c) {
-        float acc[1] = {row ? G[ob + i * nrhs + c] : 0.f}, y[1] = {0.f};
+        float acc[1] = {row ? gn : 0.f}, y[1] = {0.f};
+        const float xc = row ? xn : 0.f;
+        if (c + 1 < nrhs) {
+            gn = G[ob_safe + (row ? c + 1 : 0)];
+            xn = X[ob_safe + (row ? c + 1 : 0)];
+        }
         SegFwd<SEG, NB, 0, 1>::run(a, acc, y, myinv);
         SegBwd<SEG, NB, NB - 1, 1>::run(sb, i, y, myinv);
-        const float xc = row ? X[ob + i * nrhs + c] : 0.f;
         if (row) dB[ob + i * nrhs + c] = y[0];
         SegDa<SEG, NB, 0>::run(d, y[0], xc);
     }

@@ -128,6 +128,7 @@ __global__ void __launch_bounds__(512) posv_wave(int n, int nrhs, int batch, flo
     float* buf = lds + (size_t)w * region;
     float* Ag = A + p * n * n;
     float* Bg = B + p * n * nrhs;
+    const float b0 = MULTI ? 0.f : lane_elem(Bg, n, lane);  // issued with the rows
     float a[NB];
     rows_load_lower<NB, false>(a, Ag, n, lane);
     float myinv;
@@ -138,7 +139,7 @@ __global__ void __launch_bounds__(512) posv_wave(int n, int nrhs, int batch, flo
     } else if (MULTI) {
         wave_solve_all<NB>(a, buf, Ag, vec, Bg, n, nrhs, myinv, lane);
     } else {
-        float acc = lane < n ? Bg[lane] : 0.f;
+        float acc = b0;
         acc = wave_fwd<NB>(a, acc, myinv, lane);
         acc = wave_chunks_desc<NB>(a, buf, Ag, vec, n, lane, true, acc, myinv);
         if (lane < n) Bg[lane] = acc;
@@ -156,13 +157,14 @@ __global__ void __launch_bounds__(512) potrs_wave(int n, int nrhs, int batch, co
     float* buf = lds + (size_t)w * region;
     const float* Lg = L + p * n * n;
     float* Bg = B + p * n * nrhs;
+    const float dg = diag_load(Lg, n, lane), b0 = MULTI ? 0.f : lane_elem(Bg, n, lane);  // issued with the rows
     float a[NB];
     rows_load_lower<NB, true>(a, Lg, n, lane);
-    const float myinv = diag_inv(Lg, n, lane);
+    const float myinv = diag_inv(dg, n, lane);
     if (MULTI) {
         wave_solve_all<NB>(a, buf, nullptr, false, Bg, n, nrhs, myinv, lane);
     } else {
-        float acc = lane < n ? Bg[lane] : 0.f;
+        float acc = b0;
         acc = wave_fwd<NB>(a, acc, myinv, lane);
         acc = wave_chunks_desc<NB>(a, buf, nullptr, false, n, lane, true, acc, myinv);
         if (lane < n) Bg[lane] = acc;
@@ -178,10 +180,11 @@ __global__ void __launch_bounds__(512) trsv_wave(int n, int trans, int batch, co
     if (p >= batch) return;
     float* buf = lds + (size_t)w * region;
     const float* Lg = L + p * n * n;
+    const float dg = diag_load(Lg, n, lane);
+    float acc = lane_elem(x + p * n, n, lane);  // issued with the rows
     float a[NB];
     rows_load_lower<NB, true>(a, Lg, n, lane);
-    const float myinv = diag_inv(Lg, n, lane);
-    float acc = lane < n ? x[p * n + lane] : 0.f;
+    const float myinv = diag_inv(dg, n, lane);
     if (trans == 0)
         acc = wave_fwd<NB>(a, acc, myinv, lane);
     else

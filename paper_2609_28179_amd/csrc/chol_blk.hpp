@@ -60,7 +60,14 @@ GLASS_DEV f4_t mma(const f4_t& m, const f4_t& x, f4_t c) {
 }
 
 // The lower blocks of the problem at Ag in T layout.  FULL: n == 16 NBLK.
-// The strict upper part of a diagonal block is not read (zero).
+// The strict upper part of a diagonal block is not read (zero).  Otherwise
+// every lane still issues one 16-byte load per piece into registers of its
+// own, all before any is read (loads under a per-lane branch, or a separate
+// element-wise load of a row's last piece, made the compiler wait for each
+// piece in turn): a piece past the problem reads the first one (in range)
+// and is cleared, the piece of the last row that would run past the problem
+// is loaded as its last 16 bytes and moved down, and the entries past
+// column n of the other rows are cleared; loads are 4-byte aligned.
 template <int NBLK, bool FULL>
 GLASS_DEV void blk_load(f4_t (&T)[NBLK * (NBLK + 1) / 2], const float* Ag, int n, int q, int r) {
     const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(Ag, (uint32_t)(n * n) * 4u);
@@ -73,19 +80,35 @@ GLASS_DEV void blk_load(f4_t (&T)[NBLK * (NBLK + 1) / 2], const float* Ag, int n
             f4_t v = zero4();
             if (FULL) {
                 v = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, (R * n + C) * 4, 0, 0));
-            } else if (R < n) {
-                if (C + 4 <= n) {
-                    v = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, (R * n + C) * 4, 0, 0));
-                } else {
+            } else {  // a piece past the problem loads the first one (in range) and is cleared below
+                const int off = !(R < n && C < n) ? 0 : (R == n - 1 && C + 4 > n) ? n * n - 4 : R * n + C;
+                v = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off * 4, 0, 0));
+            }
+            T[BI(i, j)] = v;
+        }
+    }
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        if (C + e < n)
-                            v[e] = __builtin_bit_cast(float,
-                                                      __builtin_amdgcn_raw_buffer_load_b32(rs, (R * n + C + e) * 4, 0, 0));
+    for (int i = 0; i < NBLK; ++i) {
+        const int R = 16 * i + r;
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            const int C = 16 * j + 4 * q;
+            f4_t v = T[BI(i, j)];
+            if (!FULL) {
+                if (!(R < n && C < n)) v = zero4();
+                if (16 * j < n && 16 * j + 16 > n) {  // the block column that holds column n - 1
+                    const int over = C + 4 - n;          // entries of the piece past column n
+                    const f4_t d = over == 1   ? f4_t{v[1], v[2], v[3], 0.f}
+                                   : over == 2 ? f4_t{v[2], v[3], 0.f, 0.f}
+                                               : f4_t{v[3], 0.f, 0.f, 0.f};
+                    const f4_t k = f4_t{C < n ? v[0] : 0.f, C + 1 < n ? v[1] : 0.f, C + 2 < n ? v[2] : 0.f,
+                                        C + 3 < n ? v[3] : 0.f};
+                    v = (R == n - 1 && over > 0 && over < 4) ? d : k;
                 }
-            } else if (i == j) {
+                if (i == j && R >= n) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) v[e] = (4 * q + e == r) ? 1.f : 0.f;
+                    for (int e = 0; e < 4; ++e) v[e] = (4 * q + e == r) ? 1.f : 0.f;
+                }
             }
             if (i == j) {
 #pragma unroll

@@ -185,24 +185,58 @@ GLASS_DEV void thread_solve_rhs(const float (&a)[N * (N + 1) / 2], const float (
 //     leave every other row unchanged.  The identity is built from the lane's
 //     own 4-wide block and element (no compare per column, which would stay
 //     live across the unrolled factorization).
+// The 16-byte pieces t = 0 .. NB / 4 - 1 of row r of the n x n row-major
+// problem at float offset pb of the descriptor: the pieces at or left of the
+// diagonal (4 t <= r) of a row that exists (ld), zero elsewhere.  Every lane
+// issues one 16-byte load per piece into registers of its own (a lane with
+// nothing to load reads the descriptor's first piece, which is in range),
+// and all loads go out before any is read; the selects come after.  A piece
+// of the problem's last row that would run past the problem is loaded as
+// the problem's last 16 bytes and moved down by 4 t + 4 - n elements (zero
+// above).  (Loads under a per-lane branch, or an element-wise load of that
+// piece into the registers of the vector load, made the compiler wait for
+// each piece before issuing the next.)  Elements past n of the other rows
+// hold the next row's entries; loads are 4-byte aligned.
+template <int NB>
+GLASS_DEV void row_pieces(f4_t (&w)[NB / 4], __amdgpu_buffer_rsrc_t rs, int pb, int n, int r, bool ld) {
+    if (n == 1) {  // the whole problem is one element
+        const float x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, ld ? pb * 4 : 0, 0, 0));
+        w[0] = f4_t{ld && r == 0 ? x : 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 1; t < NB / 4; ++t) w[t] = f4_t{0.f, 0.f, 0.f, 0.f};
+        return;
+    }
+    const bool last = r == n - 1;
+#pragma unroll
+    for (int t = 0; t < NB / 4; ++t) {
+        const bool want = ld && 4 * t <= r;
+        const int off = !want ? 0 : (last && 4 * t + 4 > n) ? pb + n * n - 4 : pb + r * n + 4 * t;
+        w[t] = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off * 4, 0, 0));
+    }
+#pragma unroll
+    for (int t = 0; t < NB / 4; ++t) {
+        const bool want = ld && 4 * t <= r;
+        const int sh = 4 * t + 4 - n;  // wave-uniform; 1..3 for the piece that holds column n - 1
+        f4_t v = w[t];
+        if (sh > 0 && sh < 4) {
+            const f4_t d = sh == 1   ? f4_t{v[1], v[2], v[3], 0.f}
+                           : sh == 2 ? f4_t{v[2], v[3], 0.f, 0.f}
+                                     : f4_t{v[3], 0.f, 0.f, 0.f};
+            v = last ? d : v;
+        }
+        w[t] = want ? v : f4_t{0.f, 0.f, 0.f, 0.f};
+    }
+}
+
 template <int NB, bool MASK>
 GLASS_DEV void rows_load_lower(float (&a)[NB], const float* Ag, int n, int lane) {
     const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(Ag, (uint32_t)(n * n) * 4u);
     const bool row = lane < n;
+    f4_t w[NB / 4];
+    row_pieces<NB>(w, rs, 0, n, lane, row);
 #pragma unroll
     for (int t = 0; t < NB / 4; ++t) {
-        f4_t v = {0.f, 0.f, 0.f, 0.f};
-        if (row && 4 * t <= lane) {
-            if (lane * n + 4 * t + 4 <= n * n) {
-                v = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, lane * n * 4, t * 16, 0));
-            } else {  // last row, block past the end of the problem: element-wise
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (4 * t + e < n)
-                        v[e] = __builtin_bit_cast(
-                            float, __builtin_amdgcn_raw_buffer_load_b32(rs, (lane * n + 4 * t + e) * 4, 0, 0));
-            }
-        }
+        const f4_t v = w[t];
         if (MASK) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) a[4 * t + e] = (4 * t + e <= lane) ? v[e] : 0.f;
@@ -422,7 +456,11 @@ GLASS_DEV void wave_solve_cols(const float (&a)[NB], float* buf, float* Lg, bool
                                int c0, float myinv, int lane) {
     float acc[RG], y[RG];
 #pragma unroll
-    for (int c = 0; c < RG; ++c) acc[c] = (lane < n && c0 + c < nrhs) ? Bg[lane * nrhs + c0 + c] : 0.f;
+    for (int c = 0; c < RG; ++c) {  // unconditional loads (Bg[0] for the rest), so that all issue at once
+        const bool ok = lane < n && c0 + c < nrhs;
+        const float v = Bg[ok ? lane * nrhs + c0 + c : 0];
+        acc[c] = ok ? v : 0.f;
+    }
     wave_fwd_rg<NB, RG>(a, acc, y, myinv, lane);
     for (int r0 = (n - 1) & ~7; r0 >= 0; r0 -= 8) {
         const int r1 = min(r0 + 8, n);
@@ -599,11 +637,14 @@ struct SegBwd<SEG, NB, -1, RG> {
 // segment's L in LDS, row stride NB + 4.
 template <int SEG, int NB, int RG>
 GLASS_DEV void seg_solve_cols(const float (&a)[NB], const float* sb, float* Bs, int n, int r, int c0, int i,
-                              float myinv, bool act, bool fwd, bool bwd) {
+                              float myinv, bool act, bool fwd, bool bwd,
+                              const float* Bsafe) {
     float acc[RG], y[RG];
 #pragma unroll
-    for (int c = 0; c < RG; ++c) {
-        acc[c] = (act && i < n && c0 + c < r) ? Bs[i * r + c0 + c] : 0.f;
+    for (int c = 0; c < RG; ++c) {  // unconditional loads (Bsafe for the rest), so that all issue at once
+        const bool ok = act && i < n && c0 + c < r;
+        const float v = *(ok ? Bs + i * r + c0 + c : Bsafe);
+        acc[c] = ok ? v : 0.f;
         y[c] = acc[c];
     }
     if (fwd) {
@@ -617,25 +658,43 @@ GLASS_DEV void seg_solve_cols(const float (&a)[NB], const float* sb, float* Bs, 
         if (act && i < n && c0 + c < r) Bs[i * r + c0 + c] = y[c];
 }
 
+// One right-hand side, already in b (lane i of the segment: b_i, zero past
+// n), so that its load could issue with the rows: solved and stored to Bs.
+template <int SEG, int NB>
+GLASS_DEV void seg_solve_one(const float (&a)[NB], const float* sb, float* Bs, int n, int i, float myinv, bool act,
+                             bool fwd, bool bwd, float b) {
+    float acc[1] = {b}, y[1] = {b};
+    if (fwd) {
+        y[0] = 0.f;
+        SegFwd<SEG, NB, 0, 1>::run(a, acc, y, myinv);
+    }
+    if (bwd) SegBwd<SEG, NB, NB - 1, 1>::run(sb, i, y, myinv);
+    if (act && i < n) Bs[i] = y[0];
+}
+
 // All columns of every segment in groups of 8 / 4 / 1.  r is this lane's
 // segment's column count (the row stride of its Bs); the groups run to
 // rloop, which must be wave-uniform and at least every segment's r (every
 // DPP step runs in all lanes): the batch's nrhs for a uniform batch (the
-// default), the wavefront's largest count for a ragged one.
+// default), the wavefront's largest count for a ragged one.  Bsafe: an
+// address every lane may read, which lanes with nothing to load read instead
+// so that the loads need no branch (default Bs, when every lane's Bs is
+// valid).
 template <int SEG, int NB>
 GLASS_DEV void seg_solve_all(const float (&a)[NB], const float* sb, float* Bs, int n, int r, int i, float myinv,
-                             bool act, bool fwd, bool bwd, int rloop = -1) {
+                             bool act, bool fwd, bool bwd, int rloop = -1, const float* Bsafe = nullptr) {
     if (rloop < 0) rloop = r;
+    if (!Bsafe) Bsafe = Bs;
     for (int c0 = 0; c0 < rloop;) {
         const int left = rloop - c0;
         if (left >= 5) {
-            seg_solve_cols<SEG, NB, 8>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd);
+            seg_solve_cols<SEG, NB, 8>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd, Bsafe);
             c0 += 8;
         } else if (left >= 2) {
-            seg_solve_cols<SEG, NB, 4>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd);
+            seg_solve_cols<SEG, NB, 4>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd, Bsafe);
             c0 += 4;
         } else {
-            seg_solve_cols<SEG, NB, 1>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd);
+            seg_solve_cols<SEG, NB, 1>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd, Bsafe);
             c0 += 1;
         }
     }
@@ -649,21 +708,11 @@ template <int NB, bool MASK>
 GLASS_DEV void seg_load_rows(float (&a)[NB], const float* base, int np, int n, int s, int i) {
     const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(base, (uint32_t)(np * n * n) * 4u);
     const bool row = s < np && i < n;
-    const int off = s * n * n + i * n;
+    f4_t w[NB / 4];
+    row_pieces<NB>(w, rs, s * n * n, n, i, row);
 #pragma unroll
     for (int t = 0; t < NB / 4; ++t) {
-        f4_t v = {0.f, 0.f, 0.f, 0.f};
-        if (row && 4 * t <= i) {
-            if (i * n + 4 * t + 4 <= n * n) {
-                v = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off * 4, t * 16, 0));
-            } else {  // last row of the problem: element-wise, never past the problem
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (4 * t + e < n)
-                        v[e] = __builtin_bit_cast(
-                            float, __builtin_amdgcn_raw_buffer_load_b32(rs, (off + 4 * t + e) * 4, 0, 0));
-            }
-        }
+        const f4_t v = w[t];
         if (MASK) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) a[4 * t + e] = (4 * t + e <= i) ? v[e] : 0.f;
@@ -714,8 +763,15 @@ GLASS_DEV void seg_store_L(float* __restrict__ dst, const float* buf, int np, in
 }
 
 // 1 / L_ii of lane i's row (1 beyond n), read from global memory.
-GLASS_DEV float diag_inv(const float* Lg, int n, int lane) {
-    return lane < n ? 1.0f / Lg[lane * n + lane] : 1.f;
+// L_ii of the lane's row, loaded unconditionally (a lane past n reads L_00)
+// so that the load can issue with the row loads; diag_inv of it.
+GLASS_DEV float diag_load(const float* Lg, int n, int lane) { return Lg[(lane < n ? lane : 0) * (n + 1)]; }
+GLASS_DEV float diag_inv(float d, int n, int lane) { return lane < n ? 1.0f / d : 1.f; }
+
+// x[lane] for lane < n, else 0, loaded unconditionally (x[0] is read instead).
+GLASS_DEV float lane_elem(const float* x, int n, int lane) {
+    const float v = x[lane < n ? lane : 0];
+    return lane < n ? v : 0.f;
 }
 
 

@@ -162,7 +162,10 @@ GLASS_DEV void ragged_thread_one(float* __restrict__ Ag, float* __restrict__ Bg,
 #pragma unroll
     for (int i = 0; i < N; ++i)
 #pragma unroll
-        for (int j = 0; j <= i; ++j) a[TI(i, j)] = (i < n) ? Ag[i * n + j] : (i == j ? 1.f : 0.f);
+        for (int j = 0; j <= i; ++j) {  // unconditional loads (Ag[0] past n), so that all issue at once
+            const float v = Ag[i < n ? i * n + j : 0];
+            a[TI(i, j)] = (i < n) ? v : (i == j ? 1.f : 0.f);
+        }
     float dinv[N];
     const int inf = tri_potrf<N>(a, dinv);
 #pragma unroll
@@ -177,7 +180,10 @@ GLASS_DEV void ragged_thread_one(float* __restrict__ Ag, float* __restrict__ Bg,
     for (int c = 0; c < nrhs; ++c) {
         float y[N];
 #pragma unroll
-        for (int i = 0; i < N; ++i) y[i] = i < n ? Bg[i * nrhs + c] : 0.f;
+        for (int i = 0; i < N; ++i) {
+            const float v = Bg[i < n ? i * nrhs + c : 0];
+            y[i] = i < n ? v : 0.f;
+        }
         tri_fwd<N>(a, dinv, y);
         tri_bwd<N>(a, dinv, y);
 #pragma unroll
@@ -219,7 +225,11 @@ GLASS_DEV void ragged_seg(float* A, float* B, const int64_t* offA, const int64_t
     float* Bg = act ? B + offB[e] : B;
     float a[NB];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) a[j] = (i < nn && j <= i) ? Ag[i * nn + j] : (j == i ? 1.f : 0.f);
+    for (int j = 0; j < NB; ++j) {  // unconditional loads (Ag[0] for the rest), so that all issue at once
+        const bool ok = i < nn && j <= i;
+        const float v = Ag[ok ? i * nn + j : 0];
+        a[j] = ok ? v : (j == i ? 1.f : 0.f);
+    }
     int inf = 0;
     float myinv = 1.f;
     SegStep<SEG, NB, 0>::run(a, inf, myinv);

@@ -34,6 +34,14 @@ __global__ void __launch_bounds__(512) chol_seg(int n, int nrhs, int trans, int 
     float* buf = lds + (size_t)w * region;
     float* sb = buf + s * NB * (NB + 4);
     float* Ab = A + p0 * n * n;
+    const int r = OP == 3 ? 1 : nrhs;
+    float* Bs = B + (p0 + s) * n * r;
+    // With one right-hand side its entry, and for the solves the diagonal,
+    // are loaded with the rows (a lane without a row reads its wave's first
+    // problem's entries).
+    const bool row = act && i < n, one = OP >= 1 && r == 1;
+    const float b1 = one ? B[row ? (p0 + s) * n + i : p0 * n] : 0.f;
+    const float dg = OP >= 2 ? Ab[row ? s * n * n + i * n + i : 0] : 1.f;
     float a[NB];
     float myinv = 1.f;
     int inf = 0;
@@ -44,7 +52,7 @@ __global__ void __launch_bounds__(512) chol_seg(int n, int nrhs, int trans, int 
         for (int k = 0; k < NB; ++k) a[k] = k <= i ? a[k] : 0.f;
     } else {
         seg_load_rows<NB, true>(a, Ab, np, n, s, i);
-        myinv = (act && i < n) ? 1.0f / Ab[s * n * n + i * n + i] : 1.f;
+        myinv = row ? 1.0f / dg : 1.f;
     }
     const bool fwd = OP != 3 || trans == 0, bwd = OP != 3 || trans == 1;
     if (OP <= 1 || bwd) {
@@ -56,10 +64,11 @@ __global__ void __launch_bounds__(512) chol_seg(int n, int nrhs, int trans, int 
         if (info && act && i == 0) info[p0 + s] = inf;
     }
     if (OP == 0) return;
-    const int r = OP == 3 ? 1 : nrhs;
-    float* Bs = B + (p0 + s) * n * r;
     const bool solve = act && inf == 0;  // a failed factorization leaves B untouched
-    seg_solve_all<SEG, NB>(a, sb, Bs, n, r, i, myinv, solve, fwd, bwd);
+    if (one)
+        seg_solve_one<SEG, NB>(a, sb, Bs, n, i, myinv, solve, fwd, bwd, row ? b1 : 0.f);
+    else
+        seg_solve_all<SEG, NB>(a, sb, Bs, n, r, i, myinv, solve, fwd, bwd, -1, B + p0 * n * r);
 }
 
 }  // namespace
