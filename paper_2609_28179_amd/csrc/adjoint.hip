@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(512) adjoint_thread(int nrhs, int batch, const
     float dinv[N];
     thread_load_tri<N>(a, L + p0 * SZ, lds, cnt, tid, nt);
 #pragma unroll
-    for (int i = 0; i < N; ++i) dinv[i] = 1.0f / a[TI(i, i)];
+    for (int i = 0; i < N; ++i) dinv[i] = recip(a[TI(i, i)]);
     const FastDiv fb = make_fastdiv(SBn);
     stage_in<2>(gs, G + p0 * SBn, cnt * SBn, fb, SB, tid, nt);
     stage_in<2>(xs, X + p0 * SBn, cnt * SBn, fb, SB, tid, nt);
@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(512) adjoint_seg(int n, int nrhs, int batch, c
     float gn = G[ob_safe], xn = X[ob_safe];
     float a[NB];
     seg_load_rows<NB, true>(a, Lb, np, n, s, i);
-    const float myinv = row ? 1.0f / dg : 1.f;
+    const float myinv = row ? recip(dg) : 1.f;
     seg_rows_to_lds<NB>(a, sb, i);
     wave_sync();
     float d[NB];

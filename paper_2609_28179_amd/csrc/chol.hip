@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(512) potrs_thread(int nrhs, int batch, const f
     float dinv[N];
     thread_load_tri<N>(a, L + p0 * (N * N), lds, cnt, tid, nt);
 #pragma unroll
-    for (int i = 0; i < N; ++i) dinv[i] = 1.0f / a[TI(i, i)];
+    for (int i = 0; i < N; ++i) dinv[i] = recip(a[TI(i, i)]);
     thread_solve_rhs<N>(a, dinv, B + p0 * N * nrhs, lds, nrhs, cnt, tid, nt, true, true, tid < cnt);
 }
 
@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(512) trsv_thread(int trans, int batch, const f
     float dinv[N];
     thread_load_tri<N>(a, L + p0 * (N * N), lds, cnt, tid, nt);
 #pragma unroll
-    for (int i = 0; i < N; ++i) dinv[i] = 1.0f / a[TI(i, i)];
+    for (int i = 0; i < N; ++i) dinv[i] = recip(a[TI(i, i)]);
     thread_solve_rhs<N>(a, dinv, x + p0 * N, lds, 1, cnt, tid, nt, trans == 0, trans != 0, tid < cnt);
 }
 

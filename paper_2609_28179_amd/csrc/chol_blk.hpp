@@ -189,15 +189,21 @@ struct InvCoef<16> {
 // substitution against the identity reads u_rc = delta_rc + sum_{k<r}
 // (-L_rk / L_kk) u_kc, so the rows are finished in order k = 0..15 and each
 // step is one v_fmac with lane k's u broadcast.
-GLASS_DEV f4_t tri_inverse(const float (&a)[16], float myinv, int q, int r) {
-    float m[16];
-    InvCoef<0>::run(a, myinv, m);
+// tri_inverse_m takes the coefficients m_K = -L_rK / L_KK (zero in lane K)
+// already formed; they are also the forward substitution's.
+GLASS_DEV f4_t tri_inverse_m(const float (&m)[16], float myinv, int q, int r) {
     float u[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) u[c] = (4 * q + c == r) ? 1.f : 0.f;
     asm volatile("s_nop 1" : "+v"(u[0]), "+v"(u[1]), "+v"(u[2]), "+v"(u[3]));
     InvStep<0>::run(u, m);
     return f4_t{u[0] * myinv, u[1] * myinv, u[2] * myinv, u[3] * myinv};
+}
+
+GLASS_DEV f4_t tri_inverse(const float (&a)[16], float myinv, int q, int r) {
+    float m[16];
+    InvCoef<0>::run(a, myinv, m);
+    return tri_inverse_m(m, myinv, q, r);
 }
 
 // Block row k of L (rows 16 k .. 16 k + 15): the finished blocks left of the
@@ -430,63 +436,19 @@ GLASS_DEV float diag_cols(const f4_t& t, float (&col)[16], float* xs, int q, int
     return d;
 }
 
-// L x = b (FWD) and / or L^T x = b (BWD) for one right-hand side bg[0..n)
-// (unit stride), in place; T: L in T layout (diagonal blocks with a zero
-// strict upper part, identity rows past n).
-template <int NBLK, bool FULL, bool FWD, bool BWD>
-GLASS_DEV void blk_solve1(const f4_t (&T)[NBLK * (NBLK + 1) / 2], float* bg, int n, float* xs, int q, int r) {
-    float x[NBLK];
+// The pieces of the single-column solve; x[k] is block k of the vector in R
+// form (lane (q, r) holds element 16 k + r in every row q).
+template <int NBLK, bool FULL>
+GLASS_DEV void blk_x_load(float (&x)[NBLK], const float* bg, int n, int r) {
 #pragma unroll
     for (int k = 0; k < NBLK; ++k) {
         const int R = 16 * k + r;
         x[k] = (FULL || R < n) ? bg[R] : 0.f;
     }
-    if (FWD) {
-        float p[NBLK];  // pending sum_j L_kj x_j of block row k, split over the rows q
-#pragma unroll
-        for (int k = 0; k < NBLK; ++k) p[k] = 0.f;
-#pragma unroll
-        for (int k = 0; k < NBLK; ++k) {
-            float s = k > 0 ? x[k] - sum_rows4(p[k]) : x[k];
-            float a[16], m[16];
-            const float myinv = 1.0f / diag_rows(T[BI(k, k)], a, xs, q, r);
-            InvCoef<0>::run(a, myinv, m);
-            DiagSub<0, 1>::run(s, m);
-            x[k] = s * myinv;
-            if (k + 1 < NBLK) {
-                float xc[4];
-                r_to_c(x[k], xc, q);
-#pragma unroll
-                for (int i = k + 1; i < NBLK; ++i)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) p[i] = fmaf(T[BI(i, k)][c], xc[c], p[i]);
-            }
-        }
-    }
-    if (BWD) {
-        float z[NBLK][4];  // pending sum_i L_ik^T x_i of block column k, split over the lanes of a row
-#pragma unroll
-        for (int k = 0; k < NBLK; ++k)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) z[k][c] = 0.f;
-#pragma unroll
-        for (int k = NBLK - 1; k >= 0; --k) {
-            float s = x[k];
-            if (k + 1 < NBLK) {
-                sum_row16(z[k]);
-                s -= c_to_r(z[k], r);
-            }
-            float col[16], m[16];
-            const float myinv = 1.0f / diag_cols(T[BI(k, k)], col, xs, q, r);
-            InvCoef<0>::run(col, myinv, m);
-            DiagSub<15, -1>::run(s, m);
-            x[k] = s * myinv;
-#pragma unroll
-            for (int j = 0; j < k; ++j)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) z[j][c] = fmaf(T[BI(k, j)][c], x[k], z[j][c]);
-        }
-    }
+}
+
+template <int NBLK, bool FULL>
+GLASS_DEV void blk_x_store(const float (&x)[NBLK], float* bg, int n, int q, int r) {
     if (q == 0) {
 #pragma unroll
         for (int k = 0; k < NBLK; ++k) {
@@ -496,11 +458,84 @@ GLASS_DEV void blk_solve1(const f4_t (&T)[NBLK * (NBLK + 1) / 2], float* bg, int
     }
 }
 
+// Forward step k: block k of y from its pending sum p[k], the diagonal
+// block's substitution coefficients m and 1 / L_rr, then its contributions
+// L_ik y_k to the pending sums of the later blocks (right-looking, p[i]
+// split over the rows q).
+template <int NBLK>
+GLASS_DEV void blk_fwd_step(const f4_t (&T)[NBLK * (NBLK + 1) / 2], int k, const float (&m)[16], float myinv,
+                            float (&x)[NBLK], float (&p)[NBLK], int q) {
+    float s = k > 0 ? x[k] - sum_rows4(p[k]) : x[k];
+    DiagSub<0, 1>::run(s, m);
+    x[k] = s * myinv;
+    if (k + 1 < NBLK) {
+        float xc[4];
+        r_to_c(x[k], xc, q);
+#pragma unroll
+        for (int i = k + 1; i < NBLK; ++i)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) p[i] = fmaf(T[BI(i, k)][c], xc[c], p[i]);
+    }
+}
+
+// L^T x = y, bottom block first (left-looking over the columns: z[j] collects
+// sum_i L_ij^T x_i split over the lanes of a row).
+template <int NBLK>
+GLASS_DEV void blk_bwd1(const f4_t (&T)[NBLK * (NBLK + 1) / 2], float (&x)[NBLK], float* xs, int q, int r) {
+    float z[NBLK][4];
+#pragma unroll
+    for (int k = 0; k < NBLK; ++k)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) z[k][c] = 0.f;
+#pragma unroll
+    for (int k = NBLK - 1; k >= 0; --k) {
+        float s = x[k];
+        if (k + 1 < NBLK) {
+            sum_row16(z[k]);
+            s -= c_to_r(z[k], r);
+        }
+        float col[16], m[16];
+        const float myinv = recip(diag_cols(T[BI(k, k)], col, xs, q, r));
+        InvCoef<0>::run(col, myinv, m);
+        DiagSub<15, -1>::run(s, m);
+        x[k] = s * myinv;
+#pragma unroll
+        for (int j = 0; j < k; ++j)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) z[j][c] = fmaf(T[BI(k, j)][c], x[k], z[j][c]);
+    }
+}
+
+// L x = b (FWD) and / or L^T x = b (BWD) for one right-hand side bg[0..n)
+// (unit stride), in place; T: L in T layout (diagonal blocks with a zero
+// strict upper part, identity rows past n).
+template <int NBLK, bool FULL, bool FWD, bool BWD>
+GLASS_DEV void blk_solve1(const f4_t (&T)[NBLK * (NBLK + 1) / 2], float* bg, int n, float* xs, int q, int r) {
+    float x[NBLK];
+    blk_x_load<NBLK, FULL>(x, bg, n, r);
+    if (FWD) {
+        float p[NBLK];  // pending sum_j L_kj x_j of block row k, split over the rows q
+#pragma unroll
+        for (int k = 0; k < NBLK; ++k) p[k] = 0.f;
+#pragma unroll
+        for (int k = 0; k < NBLK; ++k) {
+            float a[16], m[16];
+            const float myinv = recip(diag_rows(T[BI(k, k)], a, xs, q, r));
+            InvCoef<0>::run(a, myinv, m);
+            blk_fwd_step<NBLK>(T, k, m, myinv, x, p, q);
+        }
+    }
+    if (BWD) blk_bwd1<NBLK>(T, x, xs, q, r);
+    blk_x_store<NBLK, FULL>(x, bg, n, q, r);
+}
+
 // One problem: factor (POTRF, POSV) or take L as given (POTRS, TRSV), then
 // solve.  op: 0 POTRF, 1 POSV, 2 POTRS, 3 TRSV (trans: 0 forward, 1 backward),
-// 4 POSV with one right-hand side (the factorization of op 1, then the VALU
-// substitution of blk_solve1 on the factor in registers: no inverse of the
-// last diagonal block and no block transposes); Ag is A (L for the solves),
+// 4 POSV with one right-hand side (the factorization of op 1 with the VALU
+// substitution of blk_solve1 on the factor in registers: each forward step
+// runs inside its factorization step with the block inverse's coefficients,
+// the backward pass after it; no inverse of the last diagonal block and no
+// block transposes); Ag is A (L for the solves),
 // Bg the problem's [n][nr] right-hand sides (nr = 1 for TRSV and op 4); vec:
 // Ag 16-byte aligned with n % 4 == 0.  xs: the wavefront's kBlkRegionFloats
 // of LDS.  Returns info (0 for the solves); a failed factorization leaves B
@@ -513,6 +548,14 @@ GLASS_DEV int blk_one(float* Ag, float* Bg, int n, int nrhs, int trans, bool vec
     const int q = lane >> 4, r = lane & 15;
     f4_t T[NT];
     blk_load<NBLK, FULL>(T, Ag, n, q, r);
+    // op 4: the right-hand side, loaded with A, and the forward substitution's
+    // pending sums; step k of the substitution runs inside factorization step k
+    float x1[NBLK], p1[NBLK];
+    if (OP == 4) {
+        blk_x_load<NBLK, FULL>(x1, Bg, n, r);
+#pragma unroll
+        for (int k = 0; k < NBLK; ++k) p1[k] = 0.f;
+    }
     f4_t linv[NBLK];
     int inf = 0;
 #pragma unroll
@@ -526,29 +569,47 @@ GLASS_DEV int blk_one(float* Ag, float* Bg, int n, int nrhs, int trans, bool vec
 #pragma unroll
             for (int c = 0; c < 16; ++c) a[c] = c <= r ? a[c] : 0.f;
             if (inf == 0 && f != 0) inf = 16 * k + f;
-            store_block_row<NBLK, FULL>(T, k, a, Ag, n, xs, q, r, lane, vec);
+            if (NBLK < 3) store_block_row<NBLK, FULL>(T, k, a, Ag, n, xs, q, r, lane, vec);
             if (OP == 4)  // L_kk back in T layout: lane (q, r) keeps row r, columns 4 q .. 4 q + 3
                 T[BI(k, k)] = q == 0   ? f4_t{a[0], a[1], a[2], a[3]}
                               : q == 1 ? f4_t{a[4], a[5], a[6], a[7]}
                               : q == 2 ? f4_t{a[8], a[9], a[10], a[11]}
                                        : f4_t{a[12], a[13], a[14], a[15]};
         } else {
-            myinv = 1.0f / d;
+            myinv = recip(d);
         }
-        if (MFMA_SOLVE || k + 1 < NBLK) linv[k] = tri_inverse(a, myinv, q, r);
+        float m[16];  // op 4: the coefficients of the block's inverse serve its forward step too
+        if (OP == 4) {
+            InvCoef<0>::run(a, myinv, m);
+            if (k + 1 < NBLK) linv[k] = tri_inverse_m(m, myinv, q, r);
+        } else if (MFMA_SOLVE || k + 1 < NBLK) {
+            linv[k] = tri_inverse(a, myinv, q, r);
+        }
         if (FACTOR) {
 #pragma unroll
             for (int i = k + 1; i < NBLK; ++i) T[BI(i, k)] = mma(linv[k], T[BI(i, k)], zero4());
+            // Block row k is final.  On three or four tiles per side it is
+            // staged and stored while the matrix cores run the panel products
+            // just issued (3 % on POTRF / POSV n = 64 x 4096, whose waves are
+            // bound by this chain); on two tiles, memory-bound at large
+            // batches, it goes out first, right after its diagonal block.
+            if (NBLK >= 3) store_block_row<NBLK, FULL>(T, k, a, Ag, n, xs, q, r, lane, vec);
 #pragma unroll
             for (int j = k + 1; j < NBLK; ++j) {
                 const f4_t nq = neg4(T[BI(j, k)]);
 #pragma unroll
                 for (int i = j; i < NBLK; ++i) T[BI(i, j)] = mma(nq, T[BI(i, k)], T[BI(i, j)]);
             }
+            // op 4: forward step k (needs this step's panel L_ik), on VALU
+            // while the matrix cores run the trailing products
+            if (OP == 4) blk_fwd_step<NBLK>(T, k, m, myinv, x1, p1, q);
         }
     }
-    if (OP == 4) {
-        if (inf == 0) blk_solve1<NBLK, FULL, true, true>(T, Bg, n, xs, q, r);
+    if (OP == 4) {  // a failed factorization leaves B untouched
+        if (inf == 0) {
+            blk_bwd1<NBLK>(T, x1, xs, q, r);
+            blk_x_store<NBLK, FULL>(x1, Bg, n, q, r);
+        }
         return inf;
     }
     if (OP == 0 || inf != 0) return inf;  // a failed factorization leaves B untouched

@@ -766,7 +766,7 @@ GLASS_DEV void seg_store_L(float* __restrict__ dst, const float* buf, int np, in
 // L_ii of the lane's row, loaded unconditionally (a lane past n reads L_00)
 // so that the load can issue with the row loads; diag_inv of it.
 GLASS_DEV float diag_load(const float* Lg, int n, int lane) { return Lg[(lane < n ? lane : 0) * (n + 1)]; }
-GLASS_DEV float diag_inv(float d, int n, int lane) { return lane < n ? 1.0f / d : 1.f; }
+GLASS_DEV float diag_inv(float d, int n, int lane) { return lane < n ? recip(d) : 1.f; }
 
 // x[lane] for lane < n, else 0, loaded unconditionally (x[0] is read instead).
 GLASS_DEV float lane_elem(const float* x, int n, int lane) {

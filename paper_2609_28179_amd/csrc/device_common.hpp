@@ -60,6 +60,12 @@ typedef float f2_t __attribute__((ext_vector_type(2)));
 
 GLASS_DEV bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
+// 1 / x by v_rcp_f32 (1 ulp; +-inf at +-0, NaN at NaN), the reciprocal of a
+// given diagonal entry in the solves, as the factorizations take their pivots'
+// reciprocal square roots from v_rsq_f32.  A correctly rounded division is a
+// sequence of about ten instructions.
+GLASS_DEV float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Write 4 consecutive span elements starting at element g into the padded
 // LDS layout (rows of cols.d floats at stride ldst).
 GLASS_DEV void lds_put4(float* dst, int g, const f4_t& v, FastDiv cols, int ldst) {

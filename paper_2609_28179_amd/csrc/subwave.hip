@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(512) chol_seg(int n, int nrhs, int trans, int 
         for (int k = 0; k < NB; ++k) a[k] = k <= i ? a[k] : 0.f;
     } else {
         seg_load_rows<NB, true>(a, Ab, np, n, s, i);
-        myinv = row ? 1.0f / dg : 1.f;
+        myinv = row ? recip(dg) : 1.f;
     }
     const bool fwd = OP != 3 || trans == 0, bwd = OP != 3 || trans == 1;
     if (OP <= 1 || bwd) {
