@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(512) adjoint_seg(int n, int nrhs, int batch, c
             xn = X[ob_safe + (row ? c + 1 : 0)];
         }
         SegFwd<SEG, NB, 0, 1>::run(a, acc, y, myinv);
-        SegBwd<SEG, NB, NB - 1, 1>::run(sb, i, y, myinv);
+        seg_bwd<SEG, NB, 1, true>(sb, i, y, myinv);
         if (row) dB[ob + i * nrhs + c] = y[0];
         SegDa<SEG, NB, 0>::run(d, y[0], xc);
     }

@@ -400,10 +400,20 @@ GLASS_DEV void chunk_to_global(float* __restrict__ dst, const float* buf, int ro
 // r0 .. r1-1, descending, row stride NB); lane i < k reads L_ki from row k.
 template <int NB>
 GLASS_DEV float wave_bwd_chunk(const float* buf, int r0, int r1, float acc, float myinv, int lane) {
-    for (int k = r1 - 1; k >= r0; --k) {
-        const float lki = lane < k ? buf[(k - r0) * NB + lane] : 0.f;
-        const float xk = readlane(acc * myinv, k);
-        acc = lane == k ? xk : fmaf(-lki, xk, acc);
+    // the chunk's eight entries of column `lane` are read before the steps
+    // (a read at each step put an LDS round trip on the dependent chain)
+    float lk[8];
+    const int col = lane < NB ? lane : 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) lk[j] = buf[j * NB + col];
+#pragma unroll
+    for (int j = 7; j >= 0; --j) {
+        if (j < r1 - r0) {  // wave-uniform
+            const int k = r0 + j;
+            const float lki = lane < k ? lk[j] : 0.f;
+            const float xk = readlane(acc * myinv, k);
+            acc = lane == k ? xk : fmaf(-lki, xk, acc);
+        }
     }
     return acc;
 }
@@ -438,13 +448,21 @@ GLASS_DEV void wave_fwd_rg(const float (&a)[NB], float (&acc)[RG], float (&y)[RG
 
 template <int NB, int RG>
 GLASS_DEV void wave_bwd_chunk_rg(const float* buf, int r0, int r1, float (&acc)[RG], float myinv, int lane) {
-    for (int k = r1 - 1; k >= r0; --k) {
-        const float lki = lane < k ? buf[(k - r0) * NB + lane] : 0.f;
-        float xk[RG];
+    float lk[8];  // read before the steps, as in wave_bwd_chunk
+    const int col = lane < NB ? lane : 0;
 #pragma unroll
-        for (int c = 0; c < RG; ++c) xk[c] = readlane(acc[c] * myinv, k);
+    for (int j = 0; j < 8; ++j) lk[j] = buf[j * NB + col];
 #pragma unroll
-        for (int c = 0; c < RG; ++c) acc[c] = lane == k ? xk[c] : fmaf(-lki, xk[c], acc[c]);
+    for (int j = 7; j >= 0; --j) {
+        if (j < r1 - r0) {  // wave-uniform
+            const int k = r0 + j;
+            const float lki = lane < k ? lk[j] : 0.f;
+            float xk[RG];
+#pragma unroll
+            for (int c = 0; c < RG; ++c) xk[c] = readlane(acc[c] * myinv, k);
+#pragma unroll
+            for (int c = 0; c < RG; ++c) acc[c] = lane == k ? xk[c] : fmaf(-lki, xk[c], acc[c]);
+        }
     }
 }
 
@@ -611,25 +629,72 @@ struct SegFwd<SEG, NB, NB, RG> {
 };
 
 // Backward substitution L^T x = y; row K of the segment's L is read from its
-// LDS block (row stride NB + 4; lane i takes L_Ki).
-template <int SEG, int NB, int K, int RG>
+// LDS block (row stride NB + 4; lane i takes L_Ki, zero for K <= i), AHEAD
+// steps before row K is used (the first AHEAD rows by the prologue).  In the
+// one-column solves (EARLY, AHEAD = kSegBwdAhead) a read at its own step,
+// behind the inline-asm DPP steps, put one LDS round trip on every step of
+// the dependent chain.  The column groups of seg_solve_all read at the step
+// (AHEAD = 0): they share each read among their columns, and there the rows
+// of L stay live for the next group, so reads moved up would add NB
+// registers to the kernel.
+constexpr int kSegBwdAhead = 8;
+
+// COND: a read under the lane's condition, which the compiler leaves at its
+// step; otherwise an unconditional read of an in-range entry and a select.
+template <int NB, int K, bool COND>
+GLASS_DEV void seg_col_read(const float* sb, int i, float (&lc)[NB]) {
+    if (K >= 0) {
+        if (COND) {
+            lc[K] = i < K ? sb[K * (NB + 4) + i] : 0.f;
+        } else {
+            const float v = sb[K * (NB + 4) + (i < K ? i : 0)];
+            lc[K] = i < K ? v : 0.f;
+        }
+    }
+}
+
+template <int NB, int K, int STOP>
+struct SegBwdPrologue {
+    static GLASS_DEV void run(const float* sb, int i, float (&lc)[NB]) {
+        seg_col_read<NB, K, false>(sb, i, lc);
+        SegBwdPrologue<NB, K - 1, STOP>::run(sb, i, lc);
+    }
+};
+template <int NB, int STOP>
+struct SegBwdPrologue<NB, STOP, STOP> {
+    static GLASS_DEV void run(const float*, int, float (&)[NB]) {}
+};
+
+template <int SEG, int NB, int K, int RG, int AHEAD>
 struct SegBwd {
-    static GLASS_DEV void run(const float* sb, int i, float (&acc)[RG], float myinv) {
-        const float lki = i < K ? sb[K * (NB + 4) + i] : 0.f;
+    static GLASS_DEV void run(const float* sb, int i, float (&lc)[NB], float (&acc)[RG], float myinv) {
+        seg_col_read<NB, (K - AHEAD >= 0 ? K - AHEAD : -1), AHEAD == 0>(sb, i, lc);
 #pragma unroll
         for (int c = 0; c < RG; ++c) {
             float t = acc[c] * myinv;  // x_K in lane K
             float u = acc[c];
-            seg_fnmac<SEG, K>(u, t, lki);
+            seg_fnmac<SEG, K>(u, t, lc[K]);
             acc[c] = seg_select<SEG, K>(u, t);
         }
-        SegBwd<SEG, NB, K - 1, RG>::run(sb, i, acc, myinv);
+        SegBwd<SEG, NB, K - 1, RG, AHEAD>::run(sb, i, lc, acc, myinv);
     }
 };
-template <int SEG, int NB, int RG>
-struct SegBwd<SEG, NB, -1, RG> {
-    static GLASS_DEV void run(const float*, int, float (&)[RG], float) {}
+template <int SEG, int NB, int RG, int AHEAD>
+struct SegBwd<SEG, NB, -1, RG, AHEAD> {
+    static GLASS_DEV void run(const float*, int, float (&)[NB], float (&)[RG], float) {}
 };
+
+// L^T x = y for the segment (sb: its L in LDS).
+template <int SEG, int NB, int RG, bool EARLY>
+GLASS_DEV void seg_bwd(const float* sb, int i, float (&y)[RG], float myinv) {
+    constexpr int AHEAD = EARLY ? (kSegBwdAhead < NB ? kSegBwdAhead : NB) : 0;
+    float lc[NB];
+    // the early reads start here, not above the forward pass (where the
+    // rows of L are still live)
+    if (AHEAD > 0) asm volatile("" ::: "memory");
+    SegBwdPrologue<NB, NB - 1, NB - 1 - AHEAD>::run(sb, i, lc);
+    SegBwd<SEG, NB, NB - 1, RG, AHEAD>::run(sb, i, lc, y, myinv);
+}
 
 // Columns c0 .. c0+RG-1 of segment-local right-hand sides Bs (row-major
 // [n][r]; columns past r and rows past n are zero padding and are not
@@ -637,8 +702,7 @@ struct SegBwd<SEG, NB, -1, RG> {
 // segment's L in LDS, row stride NB + 4.
 template <int SEG, int NB, int RG>
 GLASS_DEV void seg_solve_cols(const float (&a)[NB], const float* sb, float* Bs, int n, int r, int c0, int i,
-                              float myinv, bool act, bool fwd, bool bwd,
-                              const float* Bsafe) {
+                              float myinv, bool act, bool fwd, bool bwd, const float* Bsafe) {
     float acc[RG], y[RG];
 #pragma unroll
     for (int c = 0; c < RG; ++c) {  // unconditional loads (Bsafe for the rest), so that all issue at once
@@ -652,7 +716,7 @@ GLASS_DEV void seg_solve_cols(const float (&a)[NB], const float* sb, float* Bs, 
         for (int c = 0; c < RG; ++c) y[c] = 0.f;
         SegFwd<SEG, NB, 0, RG>::run(a, acc, y, myinv);
     }
-    if (bwd) SegBwd<SEG, NB, NB - 1, RG>::run(sb, i, y, myinv);
+    if (bwd) seg_bwd<SEG, NB, RG, false>(sb, i, y, myinv);
 #pragma unroll
     for (int c = 0; c < RG; ++c)
         if (act && i < n && c0 + c < r) Bs[i * r + c0 + c] = y[c];
@@ -668,7 +732,7 @@ GLASS_DEV void seg_solve_one(const float (&a)[NB], const float* sb, float* Bs, i
         y[0] = 0.f;
         SegFwd<SEG, NB, 0, 1>::run(a, acc, y, myinv);
     }
-    if (bwd) SegBwd<SEG, NB, NB - 1, 1>::run(sb, i, y, myinv);
+    if (bwd) seg_bwd<SEG, NB, 1, true>(sb, i, y, myinv);
     if (act && i < n) Bs[i] = y[0];
 }
 
