@@ -16,7 +16,7 @@ glass_mlp_adam.  Features (d = 15): one-hot op over the eight table ops, ln n
 sub-wave), log2 pack; each column standardised with the training set's mean and standard
 deviation (columns with zero spread are left centred).  Target: ln of the
 median microseconds per launch.  Loss: mean squared error over the whole
-training set every step (full batch); Adam with lr 1e-3 for 2000 steps
+training set every step (full batch); Adam with lr 3e-3 for 5000 steps
 (picked by leave-one-order-out cross-validation on the training sweep
 before the held-out cells were measured), beta (0.9, 0.999), eps 1e-8;
 He-normal initial weights from a fixed seed.
@@ -48,8 +48,8 @@ FEATURE_OPS = ("gemm", "gemv", "potrf", "potrs", "posv", "trsv", "se3_compose", 
 D = 15
 HIDDEN = 64
 TOP_K = 3
-STEPS = 2000
-LR = 1e-3   # chosen by leave-one-order-out cross-validation on the training sweep
+STEPS = 5000
+LR = 3e-3   # chosen by leave-one-order-out cross-validation on the training sweep
 SEED = 0
 
 
