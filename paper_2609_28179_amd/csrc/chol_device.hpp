@@ -171,20 +171,6 @@ GLASS_DEV void thread_solve_rhs(const float (&a)[N * (N + 1) / 2], const float (
 }
 
 
-// -------------------------------------------------------------- wave scope --
-// Lane i owns row i.  Rows come straight from global memory with 16-byte
-// buffer loads of only the column blocks at or left of the diagonal; blocks
-// right of the diagonal block are zero.
-//   MASK (L used as stored: POTRS, TRSV, the adjoint): the diagonal block is
-//     cut at the diagonal and rows past n are zero.
-//   !MASK (a factorization): the diagonal block keeps whatever the row holds
-//     past the diagonal -- it stays in the upper part (an update of row i
-//     writes only columns past the current step, and those of row i's lower
-//     part use only lower entries) and wave_potrf clears it at the end -- and
-//     rows past n are identity rows, so their steps take a unit pivot and
-//     leave every other row unchanged.  The identity is built from the lane's
-//     own 4-wide block and element (no compare per column, which would stay
-//     live across the unrolled factorization).
 // The 16-byte pieces t = 0 .. NB / 4 - 1 of row r of the n x n row-major
 // problem at float offset pb of the descriptor: the pieces at or left of the
 // diagonal (4 t <= r) of a row that exists (ld), zero elsewhere.  Every lane
@@ -228,6 +214,20 @@ GLASS_DEV void row_pieces(f4_t (&w)[NB / 4], __amdgpu_buffer_rsrc_t rs, int pb, 
     }
 }
 
+// -------------------------------------------------------------- wave scope --
+// Lane i owns row i.  Rows come straight from global memory with 16-byte
+// buffer loads of only the column blocks at or left of the diagonal; blocks
+// right of the diagonal block are zero.
+//   MASK (L used as stored: POTRS, TRSV, the adjoint): the diagonal block is
+//     cut at the diagonal and rows past n are zero.
+//   !MASK (a factorization): the diagonal block keeps whatever the row holds
+//     past the diagonal -- it stays in the upper part (an update of row i
+//     writes only columns past the current step, and those of row i's lower
+//     part use only lower entries) and wave_potrf clears it at the end -- and
+//     rows past n are identity rows, so their steps take a unit pivot and
+//     leave every other row unchanged.  The identity is built from the lane's
+//     own 4-wide block and element (no compare per column, which would stay
+//     live across the unrolled factorization).
 template <int NB, bool MASK>
 GLASS_DEV void rows_load_lower(float (&a)[NB], const float* Ag, int n, int lane) {
     const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(Ag, (uint32_t)(n * n) * 4u);
