@@ -183,17 +183,18 @@ __global__ void __launch_bounds__(512) adjoint_seg(int n, int nrhs, int batch, c
     const float myinv = row ? recip(dg) : 1.f;
     seg_rows_to_lds<NB>(a, sb, i);
     wave_sync();
+    seg_scale_row<NB>(a, myinv);
     float d[NB];
 #pragma unroll
     for (int j = 0; j < NB; ++j) d[j] = 0.f;
     for (int c = 0; c < nrhs; ++c) {
-        float acc[1] = {row ? gn : 0.f}, y[1] = {0.f};
+        float y[1] = {(row ? gn : 0.f) * myinv};
         const float xc = row ? xn : 0.f;
         if (c + 1 < nrhs) {
             gn = G[ob_safe + (row ? c + 1 : 0)];
             xn = X[ob_safe + (row ? c + 1 : 0)];
         }
-        SegFwd<SEG, NB, 0, 1>::run(a, acc, y, myinv);
+        SegFwdL<SEG, NB, 0, 1>::run(a, y);
         seg_bwd<SEG, NB, 1, true>(sb, i, y, myinv);
         if (row) dB[ob + i * nrhs + c] = y[0];
         SegDa<SEG, NB, 0>::run(d, y[0], xc);
@@ -238,12 +239,12 @@ int launch_posv_adjoint(const Shape& sh, const Geometry& g, int batch, const flo
         }
     } else if (g.scope == GLASS_SCOPE_SUBWAVE) {
         const int region = (int)subwave_region_floats(n);
-        switch (bucket8(n)) {
+        switch (subwave_nb(n)) {
 #define CASE(SEG, NB)                                                                                               \
     case NB:                                                                                                        \
         hipLaunchKernelGGL((adjoint_seg<SEG, NB>), grid, block, g.lds_bytes, st, n, r, batch, L, X, G, dB, dA, region); \
         break;
-            CASE(16, 8) CASE(16, 16) CASE(32, 24) CASE(32, 32)
+            CASE(16, 4) CASE(16, 8) CASE(16, 12) CASE(16, 16) CASE(32, 24) CASE(32, 32)
 #undef CASE
         default: return (int)hipErrorInvalidValue;
         }

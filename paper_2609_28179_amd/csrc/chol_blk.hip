@@ -24,8 +24,9 @@ __global__ void __launch_bounds__(512) chol_blk(int n, int nrhs, int trans, int 
     if (p >= batch) return;
     const int nr = OP >= 3 ? 1 : nrhs;
     const bool vec = FULL || ((n & 3) == 0 && aligned16(A));
+    constexpr int region = OP == 4 ? blk_posv1_floats(NBLK) : kBlkRegionFloats;
     const int inf = blk_one<NBLK, OP, FULL>(A + p * n * n, OP == 0 ? nullptr : B + p * n * nr, n, nrhs, trans, vec,
-                                            lds + (size_t)w * kBlkRegionFloats, lane);
+                                            lds + (size_t)w * region, lane);
     if ((OP <= 1 || OP == 4) && info && lane == 0) info[p] = inf;
 }
 

@@ -42,10 +42,10 @@
 
 namespace glass {
 
-constexpr int kXS = 20;  // LDS row stride of a 16 x 16 exchange block
-constexpr int kRS = 68;  // LDS row stride of a staged block row of L (64 + 4)
-static_assert(16 * kRS <= kBlkRegionFloats && 4 * 16 * kXS <= kBlkRegionFloats, "LDS region");
+constexpr int kXS = kBlkXS;
+static_assert(16 * blk_row_stride(4) <= kBlkRegionFloats && 4 * 16 * kXS <= kBlkRegionFloats, "LDS region");
 static_assert(16 * kXS <= kBlkSolve1Floats, "LDS region of the one-column solves");
+static_assert(16 * kXS <= 16 * blk_row_stride(2), "exchange block inside the staging area");
 
 constexpr int BI(int i, int j) { return i * (i + 1) / 2 + j; }
 
@@ -121,17 +121,23 @@ GLASS_DEV void blk_load(f4_t (&T)[NBLK * (NBLK + 1) / 2], const float* Ag, int n
 
 // Diagonal block (T layout) to row-per-lane form: lane (q, r) receives row r
 // (every 16-lane row of the wavefront a full copy).  Returns the lane's
-// diagonal entry.
+// diagonal entry; ZD: the rows come with that entry cleared.
+template <bool ZD = false>
 GLASS_DEV float diag_rows(const f4_t& t, float (&a)[16], float* xs, int q, int r) {
     *reinterpret_cast<f4_t*>(xs + r * kXS + 4 * q) = t;
     wave_sync();
+    float d = 0.f;
+    if (ZD) {
+        d = xs[r * kXS + r];
+        xs[r * kXS + r] = 0.f;
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const f4_t v = *reinterpret_cast<const f4_t*>(xs + r * kXS + 4 * u);
 #pragma unroll
         for (int e = 0; e < 4; ++e) a[4 * u + e] = v[e];
     }
-    const float d = xs[r * kXS + r];
+    if (!ZD) d = xs[r * kXS + r];
     wave_sync();
     return d;
 }
@@ -160,50 +166,45 @@ struct InvStep<16> {
     static GLASS_DEV void run(float (&)[4], const float (&)[16]) {}
 };
 
-// -(bcast_K(s) * a): the broadcast folded into the multiply, the negation
-// its source modifier; s_nop 1 gives the DPP read of s its wait states.
-template <int K>
-GLASS_DEV float neg_mul_bcast(float s, float a) {
-    float r;
-    asm volatile("s_nop 1\n\tv_mul_f32_dpp %0, %1, -%2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
-                 : "=v"(r)
-                 : "v"(s), "v"(a), "n"(K));
-    return r;
-}
-
-template <int K>
-struct InvCoef {
-    static GLASS_DEV void run(const float (&a)[16], float myinv, float (&m)[16]) {
-        m[K] = seg_select<16, K>(neg_mul_bcast<K>(myinv, a[K]), 0.f);
-        InvCoef<K + 1>::run(a, myinv, m);
-    }
-};
-template <>
-struct InvCoef<16> {
-    static GLASS_DEV void run(const float (&)[16], float, float (&)[16]) {}
-};
-
-// L^{-1} of the 16 x 16 lower factor held row-per-lane (a: row r with a zero
-// strict upper part, myinv = 1 / L_rr), in T layout: lane (q, r) returns
-// row r, columns 4 q .. 4 q + 3.  With u_r = L_rr X_r (X = L^{-1}), forward
-// substitution against the identity reads u_rc = delta_rc + sum_{k<r}
-// (-L_rk / L_kk) u_kc, so the rows are finished in order k = 0..15 and each
-// step is one v_fmac with lane k's u broadcast.
-// tri_inverse_m takes the coefficients m_K = -L_rK / L_KK (zero in lane K)
-// already formed; they are also the forward substitution's.
-GLASS_DEV f4_t tri_inverse_m(const float (&m)[16], float myinv, int q, int r) {
+// X = L^{-1} of a 16 x 16 lower diagonal block, in T layout: lane (q, r)
+// returns row r, columns 4 q .. 4 q + 3.  Forward substitution against the
+// identity with the lane's own coefficients m_K = -L_rK / L_rr (zero in lane
+// K and above the diagonal) and myinv = 1 / L_rr reads
+// X_r = e_r / L_rr + sum_{K<r} m_K X_K, so the rows are finished in order
+// K = 0..15 and each step is one v_fmac per column with lane K's row
+// broadcast.
+GLASS_DEV f4_t tri_inverse_l(const float (&m)[16], float myinv, int q, int r) {
     float u[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) u[c] = (4 * q + c == r) ? 1.f : 0.f;
+    for (int c = 0; c < 4; ++c) u[c] = (4 * q + c == r) ? myinv : 0.f;
     asm volatile("s_nop 1" : "+v"(u[0]), "+v"(u[1]), "+v"(u[2]), "+v"(u[3]));
     InvStep<0>::run(u, m);
-    return f4_t{u[0] * myinv, u[1] * myinv, u[2] * myinv, u[3] * myinv};
+    return f4_t{u[0], u[1], u[2], u[3]};
 }
 
-GLASS_DEV f4_t tri_inverse(const float (&a)[16], float myinv, int q, int r) {
-    float m[16];
-    InvCoef<0>::run(a, myinv, m);
-    return tri_inverse_m(m, myinv, q, r);
+// Row r of a factored diagonal block with its diagonal entry cleared, read
+// back through LDS at xs (row stride S).  STAGED: the rows are already there
+// (the staged block row); otherwise the lanes of row 0 write them first.
+// Leaves the cleared rows in LDS.
+template <int S, bool STAGED>
+GLASS_DEV void rows_zero_diag(const float (&a)[16], float (&az)[16], float* xs, int q, int r) {
+    if (!STAGED) {
+        if (q == 0) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                *reinterpret_cast<f4_t*>(xs + r * S + 4 * u) = f4_t{a[4 * u], a[4 * u + 1], a[4 * u + 2], a[4 * u + 3]};
+        }
+        wave_sync();
+    }
+    xs[r * S + r] = 0.f;
+    wave_sync();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const f4_t v = *reinterpret_cast<const f4_t*>(xs + r * S + 4 * u);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) az[4 * u + e] = v[e];
+    }
+    wave_sync();
 }
 
 // Block row k of L (rows 16 k .. 16 k + 15): the finished blocks left of the
@@ -212,6 +213,7 @@ GLASS_DEV f4_t tri_inverse(const float (&a)[16], float myinv, int q, int r) {
 template <int NBLK, bool FULL>
 GLASS_DEV void store_block_row(const f4_t (&T)[NBLK * (NBLK + 1) / 2], int k, const float (&a)[16], float* Ag,
                                int n, float* xs, int q, int r, int lane, bool vec) {
+    constexpr int kRS = blk_row_stride(NBLK);
 #pragma unroll
     for (int j = 0; j < NBLK; ++j) {
         if (j < k) *reinterpret_cast<f4_t*>(xs + r * kRS + 16 * j + 4 * q) = T[BI(k, j)];
@@ -325,9 +327,11 @@ struct BwdBlk<NBLK, -1> {
 //   R form: a 16-vector of block row k with lane (q, r) holding v[r] in
 //           every one of the four 16-lane rows q;
 //   diagonal block: plain substitution on its rows (forward) or columns
-//           (backward) in row-per-lane form, one DPP step per unknown:
-//           s += bcast_K(s) * m_K with m_K = -L_rK / L_KK (forward) or
-//           -L_Kr / L_KK (backward), zero in lane K, then x = s / L_rr;
+//           (backward) in row-per-lane form, one DPP step per unknown on
+//           s = b_r / L_rr: s += bcast_K(s) * m_K with m_K = -L_rK / L_rr
+//           (forward) or -L_Kr / L_rr (backward), the lane's own entries
+//           times its own -1 / L_rr (the diagonal entry is cleared on the
+//           way through LDS, so m_K is zero in lane K with no select);
 //   off-diagonal blocks: a lane's four T-layout entries times the matching
 //           four unknowns, summed across the four rows q (two permlane
 //           swaps) for L_kj x_j, or across the 16 lanes of a row (four DPP
@@ -420,18 +424,20 @@ GLASS_DEV float c_to_r(const float (&z)[4], int r) {
 }
 
 // Diagonal block k of L (T layout) transposed through LDS: lane (q, r)
-// receives column r (col[j] = L_kk[j][r]); returns L_kk[r][r].
+// receives column r (col[j] = L_kk[j][r]) with its diagonal entry cleared;
+// returns L_kk[r][r].
 GLASS_DEV float diag_cols(const f4_t& t, float (&col)[16], float* xs, int q, int r) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) xs[(4 * q + c) * kXS + r] = t[c];
     wave_sync();
+    const float d = xs[r * kXS + r];
+    xs[r * kXS + r] = 0.f;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const f4_t v = *reinterpret_cast<const f4_t*>(xs + r * kXS + 4 * u);
 #pragma unroll
         for (int e = 0; e < 4; ++e) col[4 * u + e] = v[e];
     }
-    const float d = xs[r * kXS + r];
     wave_sync();
     return d;
 }
@@ -461,13 +467,15 @@ GLASS_DEV void blk_x_store(const float (&x)[NBLK], float* bg, int n, int q, int 
 // Forward step k: block k of y from its pending sum p[k], the diagonal
 // block's substitution coefficients m and 1 / L_rr, then its contributions
 // L_ik y_k to the pending sums of the later blocks (right-looking, p[i]
-// split over the rows q).
-template <int NBLK>
+// split over the rows q).  m_K = -L_rK / L_KK, or with LOCAL -L_rK / L_rr
+// (then the right-hand side is scaled by 1 / L_rr first).
+template <int NBLK, bool LOCAL = false>
 GLASS_DEV void blk_fwd_step(const f4_t (&T)[NBLK * (NBLK + 1) / 2], int k, const float (&m)[16], float myinv,
                             float (&x)[NBLK], float (&p)[NBLK], int q) {
     float s = k > 0 ? x[k] - sum_rows4(p[k]) : x[k];
+    if (LOCAL) s *= myinv;
     DiagSub<0, 1>::run(s, m);
-    x[k] = s * myinv;
+    x[k] = LOCAL ? s : s * myinv;
     if (k + 1 < NBLK) {
         float xc[4];
         r_to_c(x[k], xc, q);
@@ -494,11 +502,65 @@ GLASS_DEV void blk_bwd1(const f4_t (&T)[NBLK * (NBLK + 1) / 2], float (&x)[NBLK]
             sum_row16(z[k]);
             s -= c_to_r(z[k], r);
         }
-        float col[16], m[16];
-        const float myinv = recip(diag_cols(T[BI(k, k)], col, xs, q, r));
-        InvCoef<0>::run(col, myinv, m);
-        DiagSub<15, -1>::run(s, m);
-        x[k] = s * myinv;
+        float col[16];
+        const float myinv = recip(diag_cols(T[BI(k, k)], col, xs, q, r)), nmy = -myinv;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) col[j] *= nmy;  // -L_jr / L_rr
+        s *= myinv;
+        DiagSub<15, -1>::run(s, col);
+        x[k] = s;
+#pragma unroll
+        for (int j = 0; j < k; ++j)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) z[j][c] = fmaf(T[BI(k, j)][c], x[k], z[j][c]);
+    }
+}
+
+// The backward pass of op 4 (POSV, one right-hand side), L^T x = y with y in
+// R form in x, on what the factorization leaves behind:
+//   last block K: the rows of L_KK are still staged in LDS (xs, row stride
+//       blk_row_stride(NBLK)) with the diagonal entry cleared, so lane r
+//       reads column r and scales it by its own -1 / L_rr, the coefficients
+//       of blk_bwd1: x_r = s_r / L_rr + sum_{j>r} (-L_jr / L_rr) x_j, one
+//       DPP step per unknown;
+//   blocks k < K: L_kk^{-1} is in LDS at lt (T layout, 16 x kXS floats per
+//       block), so lane (q, r) reads its column r, rows 4 q .. 4 q + 3, and
+//       x_k = L_kk^{-T} s is four FMAs on s in C form (the form the sum of
+//       the pending products L_ik^T x_i already has) and one sum over the
+//       four rows q -- no substitution chain.
+template <int NBLK>
+GLASS_DEV void blk_bwd1_posv(const f4_t (&T)[NBLK * (NBLK + 1) / 2], float (&x)[NBLK], float myinv_last,
+                             const float* lt, float* xs, int q, int r) {
+    constexpr int K = NBLK - 1;
+    constexpr int RS = blk_row_stride(NBLK);
+    float z[NBLK][4];
+#pragma unroll
+    for (int k = 0; k < NBLK; ++k)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) z[k][c] = 0.f;
+    {
+        const float* colr = xs + 16 * K + r;  // column r of the staged L_KK
+        const float nmy = -myinv_last;
+        float mt[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) mt[j] = colr[j * RS] * nmy;
+        float s = x[K] * myinv_last;
+        DiagSub<15, -1>::run(s, mt);
+        x[K] = s;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) z[j][c] = fmaf(T[BI(K, j)][c], x[K], z[j][c]);
+    }
+#pragma unroll
+    for (int k = K - 1; k >= 0; --k) {
+        float yc[4];
+        r_to_c(x[k], yc, q);
+        sum_row16(z[k]);
+        float part = 0.f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) part = fmaf(lt[k * 16 * kXS + (4 * q + c) * kXS + r], yc[c] - z[k][c], part);
+        x[k] = sum_rows4(part);
 #pragma unroll
         for (int j = 0; j < k; ++j)
 #pragma unroll
@@ -519,10 +581,11 @@ GLASS_DEV void blk_solve1(const f4_t (&T)[NBLK * (NBLK + 1) / 2], float* bg, int
         for (int k = 0; k < NBLK; ++k) p[k] = 0.f;
 #pragma unroll
         for (int k = 0; k < NBLK; ++k) {
-            float a[16], m[16];
-            const float myinv = recip(diag_rows(T[BI(k, k)], a, xs, q, r));
-            InvCoef<0>::run(a, myinv, m);
-            blk_fwd_step<NBLK>(T, k, m, myinv, x, p, q);
+            float a[16];
+            const float myinv = recip(diag_rows<true>(T[BI(k, k)], a, xs, q, r)), nmy = -myinv;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) a[j] *= nmy;  // -L_rj / L_rr
+            blk_fwd_step<NBLK, true>(T, k, a, myinv, x, p, q);
         }
     }
     if (BWD) blk_bwd1<NBLK>(T, x, xs, q, r);
@@ -531,15 +594,19 @@ GLASS_DEV void blk_solve1(const f4_t (&T)[NBLK * (NBLK + 1) / 2], float* bg, int
 
 // One problem: factor (POTRF, POSV) or take L as given (POTRS, TRSV), then
 // solve.  op: 0 POTRF, 1 POSV, 2 POTRS, 3 TRSV (trans: 0 forward, 1 backward),
-// 4 POSV with one right-hand side (the factorization of op 1 with the VALU
-// substitution of blk_solve1 on the factor in registers: each forward step
-// runs inside its factorization step with the block inverse's coefficients,
-// the backward pass after it; no inverse of the last diagonal block and no
-// block transposes); Ag is A (L for the solves),
-// Bg the problem's [n][nr] right-hand sides (nr = 1 for TRSV and op 4); vec:
-// Ag 16-byte aligned with n % 4 == 0.  xs: the wavefront's kBlkRegionFloats
-// of LDS.  Returns info (0 for the solves); a failed factorization leaves B
-// untouched.
+// 4 POSV with one right-hand side (the factorization of op 1 with VALU
+// substitutions on the factor in registers: each forward step runs inside its
+// factorization step with the block inverse's coefficients, the backward pass
+// of blk_bwd1_posv after it on the inverses the panels used; no inverse of
+// the last diagonal block and no block transposes).  POTRF and op 4 form
+// the diagonal blocks' inverses from the lane-local coefficients of
+// tri_inverse_l, on the factored rows read back through LDS with their
+// diagonal cleared (the staged block row itself when it is already out:
+// two tiles per side, and the last block).  Ag is A (L for the
+// solves), Bg the problem's [n][nr] right-hand sides (nr = 1 for TRSV and op
+// 4); vec: Ag 16-byte aligned with n % 4 == 0.  xs: the wavefront's LDS,
+// kBlkRegionFloats (op 4: blk_posv1_floats(NBLK)).  Returns info (0 for the
+// solves); a failed factorization leaves B untouched.
 template <int NBLK, int OP, bool FULL>
 GLASS_DEV int blk_one(float* Ag, float* Bg, int n, int nrhs, int trans, bool vec, float* xs, int lane) {
     constexpr int NT = NBLK * (NBLK + 1) / 2;
@@ -550,7 +617,8 @@ GLASS_DEV int blk_one(float* Ag, float* Bg, int n, int nrhs, int trans, bool vec
     blk_load<NBLK, FULL>(T, Ag, n, q, r);
     // op 4: the right-hand side, loaded with A, and the forward substitution's
     // pending sums; step k of the substitution runs inside factorization step k
-    float x1[NBLK], p1[NBLK];
+    float x1[NBLK], p1[NBLK], myinv_last = 1.f;
+    float* lt = xs + 16 * blk_row_stride(NBLK);  // op 4: L_kk^{-1} of the blocks k < NBLK - 1
     if (OP == 4) {
         blk_x_load<NBLK, FULL>(x1, Bg, n, r);
 #pragma unroll
@@ -560,8 +628,14 @@ GLASS_DEV int blk_one(float* Ag, float* Bg, int n, int nrhs, int trans, bool vec
     int inf = 0;
 #pragma unroll
     for (int k = 0; k < NBLK; ++k) {
+        // Block row k is final once its diagonal block is factored.  On three
+        // or four tiles per side it is staged and stored while the matrix
+        // cores run the panel products (3 % on POTRF / POSV n = 64 x 4096,
+        // whose waves are bound by this chain); on two tiles, memory-bound
+        // at large batches, and for the last block it goes out first.
+        const bool early = NBLK < 3 || k + 1 == NBLK;
         float a[16];
-        const float d = diag_rows(T[BI(k, k)], a, xs, q, r);
+        const float d = diag_rows<!FACTOR>(T[BI(k, k)], a, xs, q, r);
         float myinv = 1.f;
         if (FACTOR) {
             int f = 0;
@@ -569,31 +643,40 @@ GLASS_DEV int blk_one(float* Ag, float* Bg, int n, int nrhs, int trans, bool vec
 #pragma unroll
             for (int c = 0; c < 16; ++c) a[c] = c <= r ? a[c] : 0.f;
             if (inf == 0 && f != 0) inf = 16 * k + f;
-            if (NBLK < 3) store_block_row<NBLK, FULL>(T, k, a, Ag, n, xs, q, r, lane, vec);
-            if (OP == 4)  // L_kk back in T layout: lane (q, r) keeps row r, columns 4 q .. 4 q + 3
-                T[BI(k, k)] = q == 0   ? f4_t{a[0], a[1], a[2], a[3]}
-                              : q == 1 ? f4_t{a[4], a[5], a[6], a[7]}
-                              : q == 2 ? f4_t{a[8], a[9], a[10], a[11]}
-                                       : f4_t{a[12], a[13], a[14], a[15]};
+            if (early) store_block_row<NBLK, FULL>(T, k, a, Ag, n, xs, q, r, lane, vec);
         } else {
             myinv = recip(d);
         }
-        float m[16];  // op 4: the coefficients of the block's inverse serve its forward step too
-        if (OP == 4) {
-            InvCoef<0>::run(a, myinv, m);
-            if (k + 1 < NBLK) linv[k] = tri_inverse_m(m, myinv, q, r);
-        } else if (MFMA_SOLVE || k + 1 < NBLK) {
-            linv[k] = tri_inverse(a, myinv, q, r);
+        // The coefficients -L_rj / L_rr of the block's substitutions (its
+        // inverse; op 4's forward step): the rows with their diagonal entry
+        // cleared, read back through LDS after a factorization (from the
+        // staged block row when it is already out), as they come for the
+        // solves.
+        const bool need_inv = MFMA_SOLVE || k + 1 < NBLK;
+        float m[16];
+        if (need_inv || OP == 4) {
+            if (FACTOR) {
+                if (early)
+                    rows_zero_diag<blk_row_stride(NBLK), true>(a, m, xs + 16 * k, q, r);
+                else
+                    rows_zero_diag<kXS, false>(a, m, xs, q, r);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 16; ++j) m[j] = a[j];
+            }
+            const float nmy = -myinv;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) m[j] *= nmy;
         }
+        if (need_inv) {
+            linv[k] = tri_inverse_l(m, myinv, q, r);
+            if (OP == 4) *reinterpret_cast<f4_t*>(lt + k * 16 * kXS + r * kXS + 4 * q) = linv[k];
+        }
+        if (OP == 4 && k + 1 == NBLK) myinv_last = myinv;
         if (FACTOR) {
 #pragma unroll
             for (int i = k + 1; i < NBLK; ++i) T[BI(i, k)] = mma(linv[k], T[BI(i, k)], zero4());
-            // Block row k is final.  On three or four tiles per side it is
-            // staged and stored while the matrix cores run the panel products
-            // just issued (3 % on POTRF / POSV n = 64 x 4096, whose waves are
-            // bound by this chain); on two tiles, memory-bound at large
-            // batches, it goes out first, right after its diagonal block.
-            if (NBLK >= 3) store_block_row<NBLK, FULL>(T, k, a, Ag, n, xs, q, r, lane, vec);
+            if (!early) store_block_row<NBLK, FULL>(T, k, a, Ag, n, xs, q, r, lane, vec);
 #pragma unroll
             for (int j = k + 1; j < NBLK; ++j) {
                 const f4_t nq = neg4(T[BI(j, k)]);
@@ -602,12 +685,12 @@ GLASS_DEV int blk_one(float* Ag, float* Bg, int n, int nrhs, int trans, bool vec
             }
             // op 4: forward step k (needs this step's panel L_ik), on VALU
             // while the matrix cores run the trailing products
-            if (OP == 4) blk_fwd_step<NBLK>(T, k, m, myinv, x1, p1, q);
+            if (OP == 4) blk_fwd_step<NBLK, true>(T, k, m, myinv, x1, p1, q);
         }
     }
     if (OP == 4) {  // a failed factorization leaves B untouched
         if (inf == 0) {
-            blk_bwd1<NBLK>(T, x1, xs, q, r);
+            blk_bwd1_posv<NBLK>(T, x1, myinv_last, lt, xs, q, r);
             blk_x_store<NBLK, FULL>(x1, Bg, n, q, r);
         }
         return inf;

@@ -608,8 +608,51 @@ GLASS_DEV void seg_fnmac(float& acc, float& t, float lik) {
     }
 }
 
-// Forward substitution L y = b, one unknown per step: lane K of the segment
-// holds t = acc * (1 / L_KK) = y_K, which every lane subtracts through the
+// acc -= bcast_K(acc) * m within the segment: lane K's own value, broadcast
+// from the accumulating register itself (SEG = 32: replicated across the two
+// 16-lane rows first); s_nop 1 gives the DPP read of acc its wait states.
+template <int SEG, int K>
+GLASS_DEV void seg_fnmac_self(float& acc, float m) {
+    if (SEG == 16) {
+        asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %0, -%1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
+                     : "+v"(acc)
+                     : "v"(m), "n"(K));
+    } else {
+        float R[4];
+        replicate_rows<2>(acc, R);  // ends with the wait states a DPP read needs
+        fnmac_bcast<K % 16>(acc, R[K / 16], m);
+    }
+}
+
+// Forward substitution L y = b on the lane's own coefficients: w holds
+// b_i / L_ii on entry and y_i on exit; step K subtracts m_K y_K with
+// m_K = L_iK / L_ii (row i scaled by its own 1 / L_ii, diagonal entry and
+// upper part zero, so lane K and the lanes above it are left alone), y_K
+// being lane K's w, final by then.  One DPP FMA per unknown on the
+// dependent chain.
+template <int SEG, int NB, int K, int RG>
+struct SegFwdL {
+    static GLASS_DEV void run(const float (&m)[NB], float (&w)[RG]) {
+#pragma unroll
+        for (int c = 0; c < RG; ++c) seg_fnmac_self<SEG, K>(w[c], m[K]);
+        SegFwdL<SEG, NB, K + 1, RG>::run(m, w);
+    }
+};
+template <int SEG, int NB, int RG>
+struct SegFwdL<SEG, NB, NB, RG> {
+    static GLASS_DEV void run(const float (&)[NB], float (&)[RG]) {}
+};
+
+// Row i of L scaled by 1 / L_ii, in place: the coefficients of SegFwdL.
+template <int NB>
+GLASS_DEV void seg_scale_row(float (&a)[NB], float myinv) {
+#pragma unroll
+    for (int k = 0; k < NB; ++k) a[k] *= myinv;
+}
+
+// Forward substitution L y = b on rows that keep their diagonal (a
+// factorization's), one unknown per step: lane K of the segment holds
+// t = acc * (1 / L_KK) = y_K, which every lane subtracts through the
 // broadcast and lane K keeps (its own t, no broadcast needed).
 template <int SEG, int NB, int K, int RG>
 struct SegFwd {
@@ -665,18 +708,17 @@ struct SegBwdPrologue<NB, STOP, STOP> {
     static GLASS_DEV void run(const float*, int, float (&)[NB]) {}
 };
 
+// Step K on the lane's own coefficients: w_i -= (L_Ki / L_ii) x_K with x_K
+// lane K's w (L_Ki is read as zero for K <= i, so lane K and the lanes below
+// it are left alone).
 template <int SEG, int NB, int K, int RG, int AHEAD>
 struct SegBwd {
-    static GLASS_DEV void run(const float* sb, int i, float (&lc)[NB], float (&acc)[RG], float myinv) {
+    static GLASS_DEV void run(const float* sb, int i, float (&lc)[NB], float (&w)[RG], float myinv) {
         seg_col_read<NB, (K - AHEAD >= 0 ? K - AHEAD : -1), AHEAD == 0>(sb, i, lc);
+        const float m = lc[K] * myinv;
 #pragma unroll
-        for (int c = 0; c < RG; ++c) {
-            float t = acc[c] * myinv;  // x_K in lane K
-            float u = acc[c];
-            seg_fnmac<SEG, K>(u, t, lc[K]);
-            acc[c] = seg_select<SEG, K>(u, t);
-        }
-        SegBwd<SEG, NB, K - 1, RG, AHEAD>::run(sb, i, lc, acc, myinv);
+        for (int c = 0; c < RG; ++c) seg_fnmac_self<SEG, K>(w[c], m);
+        SegBwd<SEG, NB, K - 1, RG, AHEAD>::run(sb, i, lc, w, myinv);
     }
 };
 template <int SEG, int NB, int RG, int AHEAD>
@@ -693,14 +735,18 @@ GLASS_DEV void seg_bwd(const float* sb, int i, float (&y)[RG], float myinv) {
     // rows of L are still live)
     if (AHEAD > 0) asm volatile("" ::: "memory");
     SegBwdPrologue<NB, NB - 1, NB - 1 - AHEAD>::run(sb, i, lc);
+#pragma unroll
+    for (int c = 0; c < RG; ++c) y[c] *= myinv;  // x_i = y_i / L_ii - sum_{K>i} (L_Ki / L_ii) x_K
     SegBwd<SEG, NB, NB - 1, RG, AHEAD>::run(sb, i, lc, y, myinv);
 }
 
 // Columns c0 .. c0+RG-1 of segment-local right-hand sides Bs (row-major
 // [n][r]; columns past r and rows past n are zero padding and are not
 // stored); act: this lane's segment has a problem to solve.  sb: the
-// segment's L in LDS, row stride NB + 4.
-template <int SEG, int NB, int RG>
+// segment's L in LDS, row stride NB + 4.  a: row i of L for the forward
+// pass, as factored (SegFwd) or (ZD) with its diagonal entry zero and scaled
+// by 1 / L_ii, the coefficients of SegFwdL.
+template <int SEG, int NB, int RG, bool ZD>
 GLASS_DEV void seg_solve_cols(const float (&a)[NB], const float* sb, float* Bs, int n, int r, int c0, int i,
                               float myinv, bool act, bool fwd, bool bwd, const float* Bsafe) {
     float acc[RG], y[RG];
@@ -711,7 +757,11 @@ GLASS_DEV void seg_solve_cols(const float (&a)[NB], const float* sb, float* Bs, 
         acc[c] = ok ? v : 0.f;
         y[c] = acc[c];
     }
-    if (fwd) {
+    if (fwd && ZD) {
+#pragma unroll
+        for (int c = 0; c < RG; ++c) y[c] *= myinv;
+        SegFwdL<SEG, NB, 0, RG>::run(a, y);
+    } else if (fwd) {
 #pragma unroll
         for (int c = 0; c < RG; ++c) y[c] = 0.f;
         SegFwd<SEG, NB, 0, RG>::run(a, acc, y, myinv);
@@ -724,11 +774,15 @@ GLASS_DEV void seg_solve_cols(const float (&a)[NB], const float* sb, float* Bs, 
 
 // One right-hand side, already in b (lane i of the segment: b_i, zero past
 // n), so that its load could issue with the rows: solved and stored to Bs.
-template <int SEG, int NB>
+// a as for seg_solve_cols.
+template <int SEG, int NB, bool ZD>
 GLASS_DEV void seg_solve_one(const float (&a)[NB], const float* sb, float* Bs, int n, int i, float myinv, bool act,
                              bool fwd, bool bwd, float b) {
     float acc[1] = {b}, y[1] = {b};
-    if (fwd) {
+    if (fwd && ZD) {
+        y[0] *= myinv;
+        SegFwdL<SEG, NB, 0, 1>::run(a, y);
+    } else if (fwd) {
         y[0] = 0.f;
         SegFwd<SEG, NB, 0, 1>::run(a, acc, y, myinv);
     }
@@ -743,8 +797,8 @@ GLASS_DEV void seg_solve_one(const float (&a)[NB], const float* sb, float* Bs, i
 // default), the wavefront's largest count for a ragged one.  Bsafe: an
 // address every lane may read, which lanes with nothing to load read instead
 // so that the loads need no branch (default Bs, when every lane's Bs is
-// valid).
-template <int SEG, int NB>
+// valid).  a as for seg_solve_cols.
+template <int SEG, int NB, bool ZD>
 GLASS_DEV void seg_solve_all(const float (&a)[NB], const float* sb, float* Bs, int n, int r, int i, float myinv,
                              bool act, bool fwd, bool bwd, int rloop = -1, const float* Bsafe = nullptr) {
     if (rloop < 0) rloop = r;
@@ -752,22 +806,25 @@ GLASS_DEV void seg_solve_all(const float (&a)[NB], const float* sb, float* Bs, i
     for (int c0 = 0; c0 < rloop;) {
         const int left = rloop - c0;
         if (left >= 5) {
-            seg_solve_cols<SEG, NB, 8>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd, Bsafe);
+            seg_solve_cols<SEG, NB, 8, ZD>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd, Bsafe);
             c0 += 8;
         } else if (left >= 2) {
-            seg_solve_cols<SEG, NB, 4>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd, Bsafe);
+            seg_solve_cols<SEG, NB, 4, ZD>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd, Bsafe);
             c0 += 4;
         } else {
-            seg_solve_cols<SEG, NB, 1>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd, Bsafe);
+            seg_solve_cols<SEG, NB, 1, ZD>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd, Bsafe);
             c0 += 1;
         }
     }
 }
 
 // Row i of segment s's problem (lane 16s + i or 32s + i) from the wavefront's
-// np adjacent problems starting at base.  MASK and the padding follow
+// np adjacent problems starting at base.  The padding follows
 // rows_load_lower (identity rows for a factorization, zero rows otherwise;
-// a segment past np holds only padding rows).
+// a segment past np holds only padding rows).  MASK (L as stored: the
+// solves, the adjoint): the strict lower part only -- the callers load the
+// diagonal apart, and the lane-local substitutions want it zero in the row.
+// !MASK (a factorization): as rows_load_lower.
 template <int NB, bool MASK>
 GLASS_DEV void seg_load_rows(float (&a)[NB], const float* base, int np, int n, int s, int i) {
     const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(base, (uint32_t)(np * n * n) * 4u);
@@ -779,7 +836,7 @@ GLASS_DEV void seg_load_rows(float (&a)[NB], const float* base, int np, int n, i
         const f4_t v = w[t];
         if (MASK) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) a[4 * t + e] = (4 * t + e <= i) ? v[e] : 0.f;
+            for (int e = 0; e < 4; ++e) a[4 * t + e] = (4 * t + e < i) ? v[e] : 0.f;
         } else {
             const bool dblk = !row && t == (i >> 2);
 #pragma unroll

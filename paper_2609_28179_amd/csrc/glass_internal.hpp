@@ -109,6 +109,15 @@ constexpr int kGemmStageStride = 68;  // LDS row stride of the staged 16-row out
 // 16 x 16 exchange blocks.
 constexpr int kBlkMinN = 25;
 constexpr int kBlkRegionFloats = 1280;
+constexpr int kBlkXS = 20;  // LDS row stride of a 16 x 16 exchange block
+// LDS row stride of a staged block row of L: 16 nblk floats and four of padding.
+constexpr int blk_row_stride(int nblk) { return 16 * nblk + 4; }
+inline int blk_nblk(int n) { return n <= 32 ? 2 : n <= 48 ? 3 : 4; }
+// POSV with one right-hand side keeps L_kk^{-1} of every diagonal block but
+// the last (16 x 20 floats each) for its backward pass, after the staged
+// block row: 896, 1472 and 2048 floats per wavefront for 2, 3 and 4 tiles.
+constexpr int blk_posv1_floats(int nblk) { return 16 * blk_row_stride(nblk) + (nblk - 1) * 16 * kBlkXS; }
+inline bool blk_posv1_shape(const Shape& s) { return s.op == GLASS_OP_POSV && s.nrhs == 1 && s.n >= kBlkMinN; }
 // With one right-hand side (TRSV; POTRS with nrhs = 1) the blocked kernel
 // passes only a diagonal block through LDS and reserves 16 x 20 floats per
 // wavefront.
@@ -138,6 +147,7 @@ inline size_t wave_region_floats(const Shape& s) {
     case GLASS_OP_POSV:
     case GLASS_OP_TRSV:
         if (blk_solve1_shape(s)) return (size_t)kBlkSolve1Floats;
+        if (blk_posv1_shape(s)) return (size_t)blk_posv1_floats(blk_nblk(s.n));
         return s.n >= kBlkMinN ? (size_t)kBlkRegionFloats : (size_t)8 * bucket8_host(s.n);
     case GLASS_OP_POSV_ADJOINT:
         return (size_t)8 * bucket8_host(s.n);
@@ -148,13 +158,16 @@ inline size_t wave_region_floats(const Shape& s) {
 
 // Sub-wave scope of the batched Cholesky family (orders <= 32): 64 / SEG
 // problems per wavefront, one per SEG-lane segment, SEG = 16 up to order 16
-// and 32 above.  LDS per wavefront: one block of L per segment, rows padded
-// to NB + 4 floats (NB = order rounded up to 8).
+// and 32 above.  Every step of the factorization and the substitutions runs
+// once per padded row NB: NB is the order rounded up to a multiple of 4 up
+// to 16 and to 24 or 32 above.  LDS per wavefront: one block of L per
+// segment, rows padded to NB + 4 floats.
 constexpr int kSubwaveMaxN = 32;
 constexpr int kSubwaveBlasMaxN = 16;  // GEMM / GEMV at sub-wave scope: m, n, k <= 16, no transposes
 inline int subwave_seg(int n) { return n <= 16 ? 16 : 32; }
+inline int subwave_nb(int n) { return n <= 16 ? ((n + 3) / 4) * 4 : n <= 24 ? 24 : 32; }
 inline size_t subwave_region_floats(int n) {
-    const int nb = bucket8_host(n);
+    const int nb = subwave_nb(n);
     return (size_t)(kWave / subwave_seg(n)) * nb * (nb + 4);
 }
 inline bool subwave_op(glass_op_t op) {

@@ -123,7 +123,11 @@ __global__ void __launch_bounds__(512) riccati_mfma(int nx, int nu, int batch, c
     for (int c = 0; c < 16; ++c) a[c] = c <= r ? a[c] : 0.f;
     if (info && lane == 0) info[p] = f;
     if (f != 0) return;  // K is not written for an indefinite S
-    const f4_t linv = tri_inverse(a, myinv, q, r);  // L^{-1} in T layout
+    float m[16];  // the rows again, diagonal entry cleared, scaled by -1 / L_rr
+    rows_zero_diag<kXS, false>(a, m, xs, q, r);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) m[j] *= -myinv;
+    const f4_t linv = tri_inverse_l(m, myinv, q, r);  // L^{-1} in T layout
     f4_t lt[4];
     lt[0] = linv;
     transpose_blocks<1>(lt, xs, q, r);  // lt[0]: L^{-T} in T layout

@@ -7,9 +7,13 @@
 // row i.  Broadcasts stay inside a segment: DPP row_newbcast reaches the 16
 // lanes of a row, and for SEG = 32 v_permlane16_swap first replicates each
 // 16-lane row across its 32-lane half (replicate_rows<2>), so the two halves
-// of the wavefront never mix.  The per-segment pivot, 1 / L_ii and the solved
-// unknowns use the same broadcast and a literal lane mask that repeats every
-// SEG lanes.  The backward substitution reads L from a per-segment LDS block;
+// of the wavefront never mix.  The per-segment pivot and 1 / L_ii use the
+// same broadcast and a literal lane mask that repeats every SEG lanes; the
+// substitutions scale each row by its own 1 / L_ii, so that a solved unknown
+// is its lane's running value, broadcast in the FMA that consumes it (rows
+// with the diagonal entry cleared: read so for the solves, read back from
+// LDS after the factorization).  The backward substitution reads L from a
+// per-segment LDS block;
 // L leaves through that block as one contiguous copy of the wavefront's
 // problems (they are adjacent in the batch).
 #include "device_common.hpp"
@@ -64,11 +68,25 @@ __global__ void __launch_bounds__(512) chol_seg(int n, int nrhs, int trans, int 
         if (info && act && i == 0) info[p0 + s] = inf;
     }
     if (OP == 0) return;
+    if (OP == 1) {  // the factored rows again, diagonal entry cleared, for the lane-local forward pass
+        if (i < NB) sb[i * (NB + 4) + i] = 0.f;
+        wave_sync();
+        if (i < NB) {
+#pragma unroll
+            for (int t = 0; t < NB / 4; ++t) {
+                const f4_t v = *reinterpret_cast<const f4_t*>(sb + i * (NB + 4) + 4 * t);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) a[4 * t + e] = v[e];
+            }
+        }
+        wave_sync();
+    }
+    seg_scale_row<NB>(a, myinv);
     const bool solve = act && inf == 0;  // a failed factorization leaves B untouched
     if (one)
-        seg_solve_one<SEG, NB>(a, sb, Bs, n, i, myinv, solve, fwd, bwd, row ? b1 : 0.f);
+        seg_solve_one<SEG, NB, true>(a, sb, Bs, n, i, myinv, solve, fwd, bwd, row ? b1 : 0.f);
     else
-        seg_solve_all<SEG, NB>(a, sb, Bs, n, r, i, myinv, solve, fwd, bwd, -1, B + p0 * n * r);
+        seg_solve_all<SEG, NB, true>(a, sb, Bs, n, r, i, myinv, solve, fwd, bwd, -1, B + p0 * n * r);
 }
 
 }  // namespace
@@ -77,7 +95,7 @@ int launch_chol_subwave(const Shape& sh, const Geometry& g, int batch, float* A,
                         void* stream) {
     (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
     hipStream_t st = (hipStream_t)stream;
-    const int n = sh.n, nb = bucket8_host(n);
+    const int n = sh.n, nb = subwave_nb(n);
     if (n > kSubwaveMaxN) return (int)hipErrorInvalidValue;
     const int region = (int)subwave_region_floats(n);
     dim3 grid((unsigned)g.grid), block(g.threads);
@@ -89,7 +107,7 @@ int launch_chol_subwave(const Shape& sh, const Geometry& g, int batch, float* A,
         return (int)hipGetLastError();                                                                          \
     }
 #define SW_OPS(SEG, NB) SW(SEG, NB, 0) SW(SEG, NB, 1) SW(SEG, NB, 2) SW(SEG, NB, 3)
-    SW_OPS(16, 8) SW_OPS(16, 16) SW_OPS(32, 24) SW_OPS(32, 32)
+    SW_OPS(16, 4) SW_OPS(16, 8) SW_OPS(16, 12) SW_OPS(16, 16) SW_OPS(32, 24) SW_OPS(32, 32)
 #undef SW_OPS
 #undef SW
     return (int)hipErrorInvalidValue;
