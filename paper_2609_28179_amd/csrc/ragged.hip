@@ -252,12 +252,26 @@ GLASS_DEV void ragged_seg(float* A, float* B, const int64_t* offA, const int64_t
             if (j < nn) Ag[i * nn + j] = a[j];
     }
     if (act && i == 0) info[e] = inf;
+    // the rows again from the segment's block, diagonal entry cleared and
+    // scaled by 1 / L_ii: the coefficients of the lane-local forward pass
+    if (i < NB) sb[i * (NB + 4) + i] = 0.f;
+    wave_sync();
+    if (i < NB) {
+#pragma unroll
+        for (int t = 0; t < NB / 4; ++t) {
+            const f4_t v = *reinterpret_cast<const f4_t*>(sb + i * (NB + 4) + 4 * t);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[4 * t + q] = v[q];
+        }
+    }
+    wave_sync();
+    seg_scale_row<NB>(a, myinv);
     // a failed or empty segment solves zero columns and stores nothing
     const int reff = (act && inf == 0) ? r : 0;
     int rmax = 0;
 #pragma unroll
     for (int t = 0; t < 64 / SEG; ++t) rmax = max(rmax, __builtin_amdgcn_readlane(reff, t * SEG));
-    seg_solve_all<SEG, NB, false>(a, sb, Bg, nn, reff, i, myinv, reff > 0, true, true, rmax);
+    seg_solve_all<SEG, NB, true>(a, sb, Bg, nn, reff, i, myinv, reff > 0, true, true, rmax);
 }
 
 // One work item per wavefront: wavefront g of the launch takes item g of the
