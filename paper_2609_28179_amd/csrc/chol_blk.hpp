@@ -465,17 +465,17 @@ GLASS_DEV void blk_x_store(const float (&x)[NBLK], float* bg, int n, int q, int 
 }
 
 // Forward step k: block k of y from its pending sum p[k], the diagonal
-// block's substitution coefficients m and 1 / L_rr, then its contributions
-// L_ik y_k to the pending sums of the later blocks (right-looking, p[i]
-// split over the rows q).  m_K = -L_rK / L_KK, or with LOCAL -L_rK / L_rr
-// (then the right-hand side is scaled by 1 / L_rr first).
-template <int NBLK, bool LOCAL = false>
+// block's lane-local coefficients m_K = -L_rK / L_rr and 1 / L_rr (the
+// right-hand side is scaled by it first), then its contributions L_ik y_k to
+// the pending sums of the later blocks (right-looking, p[i] split over the
+// rows q).
+template <int NBLK>
 GLASS_DEV void blk_fwd_step(const f4_t (&T)[NBLK * (NBLK + 1) / 2], int k, const float (&m)[16], float myinv,
                             float (&x)[NBLK], float (&p)[NBLK], int q) {
     float s = k > 0 ? x[k] - sum_rows4(p[k]) : x[k];
-    if (LOCAL) s *= myinv;
+    s *= myinv;
     DiagSub<0, 1>::run(s, m);
-    x[k] = LOCAL ? s : s * myinv;
+    x[k] = s;
     if (k + 1 < NBLK) {
         float xc[4];
         r_to_c(x[k], xc, q);
@@ -585,7 +585,7 @@ GLASS_DEV void blk_solve1(const f4_t (&T)[NBLK * (NBLK + 1) / 2], float* bg, int
             const float myinv = recip(diag_rows<true>(T[BI(k, k)], a, xs, q, r)), nmy = -myinv;
 #pragma unroll
             for (int j = 0; j < 16; ++j) a[j] *= nmy;  // -L_rj / L_rr
-            blk_fwd_step<NBLK, true>(T, k, a, myinv, x, p, q);
+            blk_fwd_step<NBLK>(T, k, a, myinv, x, p, q);
         }
     }
     if (BWD) blk_bwd1<NBLK>(T, x, xs, q, r);
@@ -598,11 +598,12 @@ GLASS_DEV void blk_solve1(const f4_t (&T)[NBLK * (NBLK + 1) / 2], float* bg, int
 // substitutions on the factor in registers: each forward step runs inside its
 // factorization step with the block inverse's coefficients, the backward pass
 // of blk_bwd1_posv after it on the inverses the panels used; no inverse of
-// the last diagonal block and no block transposes).  POTRF and op 4 form
-// the diagonal blocks' inverses from the lane-local coefficients of
-// tri_inverse_l, on the factored rows read back through LDS with their
-// diagonal cleared (the staged block row itself when it is already out:
-// two tiles per side, and the last block).  Ag is A (L for the
+// the last diagonal block and no block transposes).  Every op forms the
+// diagonal blocks' inverses with tri_inverse_l on lane-local coefficients:
+// after a factorization from the factored rows read back through LDS with
+// their diagonal cleared (the staged block row itself when it is already
+// out: two tiles per side, and the last block), for the solves from rows
+// read without it.  Ag is A (L for the
 // solves), Bg the problem's [n][nr] right-hand sides (nr = 1 for TRSV and op
 // 4); vec: Ag 16-byte aligned with n % 4 == 0.  xs: the wavefront's LDS,
 // kBlkRegionFloats (op 4: blk_posv1_floats(NBLK)).  Returns info (0 for the
@@ -685,7 +686,7 @@ GLASS_DEV int blk_one(float* Ag, float* Bg, int n, int nrhs, int trans, bool vec
             }
             // op 4: forward step k (needs this step's panel L_ik), on VALU
             // while the matrix cores run the trailing products
-            if (OP == 4) blk_fwd_step<NBLK, true>(T, k, m, myinv, x1, p1, q);
+            if (OP == 4) blk_fwd_step<NBLK>(T, k, m, myinv, x1, p1, q);
         }
     }
     if (OP == 4) {  // a failed factorization leaves B untouched

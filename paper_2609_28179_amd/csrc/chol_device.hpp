@@ -592,22 +592,6 @@ struct SegStep<SEG, NB, NB> {
     static GLASS_DEV void run(float (&)[NB], int& info, float& myinv) { info = first_nonfinite<SEG>(myinv); }
 };
 
-// acc -= L_iK * x_K with x_K = bcast_K(t): the broadcast is the FMA's DPP
-// operand (its source t is given the wait states a DPP read needs first; t
-// is passed by reference so the caller's later reads use the same register
-// and no copy is made).
-template <int SEG, int K>
-GLASS_DEV void seg_fnmac(float& acc, float& t, float lik) {
-    if (SEG == 16) {
-        asm volatile("s_nop 1" : "+v"(t));
-        fnmac_bcast<K>(acc, t, lik);
-    } else {
-        float R[4];
-        replicate_rows<2>(t, R);  // ends with the wait states a DPP read needs
-        fnmac_bcast<K % 16>(acc, R[K / 16], lik);
-    }
-}
-
 // acc -= bcast_K(acc) * m within the segment: lane K's own value, broadcast
 // from the accumulating register itself (SEG = 32: replicated across the two
 // 16-lane rows first); s_nop 1 gives the DPP read of acc its wait states.
@@ -649,27 +633,6 @@ GLASS_DEV void seg_scale_row(float (&a)[NB], float myinv) {
 #pragma unroll
     for (int k = 0; k < NB; ++k) a[k] *= myinv;
 }
-
-// Forward substitution L y = b on rows that keep their diagonal (a
-// factorization's), one unknown per step: lane K of the segment holds
-// t = acc * (1 / L_KK) = y_K, which every lane subtracts through the
-// broadcast and lane K keeps (its own t, no broadcast needed).
-template <int SEG, int NB, int K, int RG>
-struct SegFwd {
-    static GLASS_DEV void run(const float (&a)[NB], float (&acc)[RG], float (&y)[RG], float myinv) {
-#pragma unroll
-        for (int c = 0; c < RG; ++c) {
-            float t = acc[c] * myinv;
-            seg_fnmac<SEG, K>(acc[c], t, a[K]);
-            y[c] = seg_select<SEG, K>(y[c], t);
-        }
-        SegFwd<SEG, NB, K + 1, RG>::run(a, acc, y, myinv);
-    }
-};
-template <int SEG, int NB, int RG>
-struct SegFwd<SEG, NB, NB, RG> {
-    static GLASS_DEV void run(const float (&)[NB], float (&)[RG], float (&)[RG], float) {}
-};
 
 // Backward substitution L^T x = y; row K of the segment's L is read from its
 // LDS block (row stride NB + 4; lane i takes L_Ki, zero for K <= i), AHEAD
@@ -744,27 +707,22 @@ GLASS_DEV void seg_bwd(const float* sb, int i, float (&y)[RG], float myinv) {
 // [n][r]; columns past r and rows past n are zero padding and are not
 // stored); act: this lane's segment has a problem to solve.  sb: the
 // segment's L in LDS, row stride NB + 4.  a: row i of L for the forward
-// pass, as factored (SegFwd) or (ZD) with its diagonal entry zero and scaled
-// by 1 / L_ii, the coefficients of SegFwdL.
-template <int SEG, int NB, int RG, bool ZD>
+// pass with its diagonal entry zero, scaled by 1 / L_ii (the coefficients of
+// SegFwdL).
+template <int SEG, int NB, int RG>
 GLASS_DEV void seg_solve_cols(const float (&a)[NB], const float* sb, float* Bs, int n, int r, int c0, int i,
                               float myinv, bool act, bool fwd, bool bwd, const float* Bsafe) {
-    float acc[RG], y[RG];
+    float y[RG];
 #pragma unroll
     for (int c = 0; c < RG; ++c) {  // unconditional loads (Bsafe for the rest), so that all issue at once
         const bool ok = act && i < n && c0 + c < r;
         const float v = *(ok ? Bs + i * r + c0 + c : Bsafe);
-        acc[c] = ok ? v : 0.f;
-        y[c] = acc[c];
+        y[c] = ok ? v : 0.f;
     }
-    if (fwd && ZD) {
+    if (fwd) {
 #pragma unroll
         for (int c = 0; c < RG; ++c) y[c] *= myinv;
         SegFwdL<SEG, NB, 0, RG>::run(a, y);
-    } else if (fwd) {
-#pragma unroll
-        for (int c = 0; c < RG; ++c) y[c] = 0.f;
-        SegFwd<SEG, NB, 0, RG>::run(a, acc, y, myinv);
     }
     if (bwd) seg_bwd<SEG, NB, RG, false>(sb, i, y, myinv);
 #pragma unroll
@@ -775,16 +733,13 @@ GLASS_DEV void seg_solve_cols(const float (&a)[NB], const float* sb, float* Bs, 
 // One right-hand side, already in b (lane i of the segment: b_i, zero past
 // n), so that its load could issue with the rows: solved and stored to Bs.
 // a as for seg_solve_cols.
-template <int SEG, int NB, bool ZD>
+template <int SEG, int NB>
 GLASS_DEV void seg_solve_one(const float (&a)[NB], const float* sb, float* Bs, int n, int i, float myinv, bool act,
                              bool fwd, bool bwd, float b) {
-    float acc[1] = {b}, y[1] = {b};
-    if (fwd && ZD) {
+    float y[1] = {b};
+    if (fwd) {
         y[0] *= myinv;
         SegFwdL<SEG, NB, 0, 1>::run(a, y);
-    } else if (fwd) {
-        y[0] = 0.f;
-        SegFwd<SEG, NB, 0, 1>::run(a, acc, y, myinv);
     }
     if (bwd) seg_bwd<SEG, NB, 1, true>(sb, i, y, myinv);
     if (act && i < n) Bs[i] = y[0];
@@ -798,7 +753,7 @@ GLASS_DEV void seg_solve_one(const float (&a)[NB], const float* sb, float* Bs, i
 // address every lane may read, which lanes with nothing to load read instead
 // so that the loads need no branch (default Bs, when every lane's Bs is
 // valid).  a as for seg_solve_cols.
-template <int SEG, int NB, bool ZD>
+template <int SEG, int NB>
 GLASS_DEV void seg_solve_all(const float (&a)[NB], const float* sb, float* Bs, int n, int r, int i, float myinv,
                              bool act, bool fwd, bool bwd, int rloop = -1, const float* Bsafe = nullptr) {
     if (rloop < 0) rloop = r;
@@ -806,13 +761,13 @@ GLASS_DEV void seg_solve_all(const float (&a)[NB], const float* sb, float* Bs, i
     for (int c0 = 0; c0 < rloop;) {
         const int left = rloop - c0;
         if (left >= 5) {
-            seg_solve_cols<SEG, NB, 8, ZD>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd, Bsafe);
+            seg_solve_cols<SEG, NB, 8>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd, Bsafe);
             c0 += 8;
         } else if (left >= 2) {
-            seg_solve_cols<SEG, NB, 4, ZD>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd, Bsafe);
+            seg_solve_cols<SEG, NB, 4>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd, Bsafe);
             c0 += 4;
         } else {
-            seg_solve_cols<SEG, NB, 1, ZD>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd, Bsafe);
+            seg_solve_cols<SEG, NB, 1>(a, sb, Bs, n, r, c0, i, myinv, act, fwd, bwd, Bsafe);
             c0 += 1;
         }
     }

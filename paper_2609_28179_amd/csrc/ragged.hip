@@ -271,7 +271,7 @@ GLASS_DEV void ragged_seg(float* A, float* B, const int64_t* offA, const int64_t
     int rmax = 0;
 #pragma unroll
     for (int t = 0; t < 64 / SEG; ++t) rmax = max(rmax, __builtin_amdgcn_readlane(reff, t * SEG));
-    seg_solve_all<SEG, NB, true>(a, sb, Bg, nn, reff, i, myinv, reff > 0, true, true, rmax);
+    seg_solve_all<SEG, NB>(a, sb, Bg, nn, reff, i, myinv, reff > 0, true, true, rmax);
 }
 
 // One work item per wavefront: wavefront g of the launch takes item g of the

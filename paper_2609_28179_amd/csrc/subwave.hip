@@ -84,9 +84,9 @@ __global__ void __launch_bounds__(512) chol_seg(int n, int nrhs, int trans, int 
     seg_scale_row<NB>(a, myinv);
     const bool solve = act && inf == 0;  // a failed factorization leaves B untouched
     if (one)
-        seg_solve_one<SEG, NB, true>(a, sb, Bs, n, i, myinv, solve, fwd, bwd, row ? b1 : 0.f);
+        seg_solve_one<SEG, NB>(a, sb, Bs, n, i, myinv, solve, fwd, bwd, row ? b1 : 0.f);
     else
-        seg_solve_all<SEG, NB, true>(a, sb, Bs, n, r, i, myinv, solve, fwd, bwd, -1, B + p0 * n * r);
+        seg_solve_all<SEG, NB>(a, sb, Bs, n, r, i, myinv, solve, fwd, bwd, -1, B + p0 * n * r);
 }
 
 }  // namespace
