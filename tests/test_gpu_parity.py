@@ -59,7 +59,10 @@ def test_parity_square_ops(env, op, scope):
             if pack != 1 and n not in N_PACKS and n not in (4, 12):
                 continue
             feas = glass.glass_placement_feasible(glass.OPS[op], n, 1, glass.SCOPES[scope], pack)
-            for batch in BATCHES if pack == 1 else (67,):
+            # the last workgroup ends part-way (at sub-wave P = 8, 32
+            # problems per workgroup: one partial wavefront at 67, a full and
+            # a partial one at 70)
+            for batch in BATCHES if pack == 1 else (67, 70):
                 label = f"{op} n={n} batch={batch} {scope}/P={pack}"
                 if feas != 1:
                     res = run_case(glass, torch, op, n, 1, scope, pack, check_guards=False)
