@@ -121,8 +121,8 @@ __global__ void __launch_bounds__(256) gemv_wg(int m, int n, int batch, int pack
     }
 }
 
-// Square orders 17 .. 64 at wave scope, with no LDS: one problem per
-// wavefront, padded to N = 32 or 64.  Every byte of A is loaded once into
+// Square orders 12, 16 and 17 .. 64 at wave scope, with no LDS: one problem
+// per wavefront, padded to N = 16, 32 or 64.  Every byte of A is loaded once into
 // registers by instructions that cover whole consecutive rows: lane
 // (g, c) = (lane / LPR, lane % LPR) takes row RPI k + g, columns
 // 4 c .. 4 c + 3 in instruction k (LPR = N / 4 lanes per row, RPI = 64 / LPR
@@ -135,8 +135,9 @@ __global__ void __launch_bounds__(256) gemv_wg(int m, int n, int batch, int pack
 // clear keeps the lower half of its values and the other the upper half,
 // each adding its partner's copy.  Afterwards lane c of a group holds the
 // whole dot product of row RPI k + g for k = c (N = 64) or k = c / 2 (N = 32;
-// lanes c and c ^ 1 agree).  VEC: n % 4 == 0 with A and x 16-byte aligned;
-// FULL: besides, n == N (no padding, no masks).
+// lanes c and c ^ 1 agree).  At N = 16 a row is one instruction's four lanes
+// (K = 1) and two quad exchanges sum them.  VEC: n % 4 == 0 with A and x
+// 16-byte aligned; FULL: besides, n == N (no padding, no masks).
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
@@ -153,13 +154,13 @@ __device__ __forceinline__ void bfly_step(float (&v)[16], bool hi) {
     for (int j = 0; j < M / 2; ++j) v[j] = (hi ? v[j + M / 2] : v[j]) + dpp_mov<CTRL>(send[j]);
 }
 
-constexpr int kDppRowMirror = 0x140, kDppHalfMirror = 0x141, kDppXor3 = 0x1B, kDppXor1 = 0xB1;
+constexpr int kDppRowMirror = 0x140, kDppHalfMirror = 0x141, kDppXor3 = 0x1B, kDppXor2 = 0x4E, kDppXor1 = 0xB1;
 
 template <int N, bool VEC, bool FULL>
 __global__ void __launch_bounds__(512) gemv_wave_dpp(int n, int batch, float alpha, const float* __restrict__ A,
                                                      const float* __restrict__ x, float beta,
                                                      float* __restrict__ y) {
-    static_assert(N == 32 || N == 64, "padded orders 32 and 64");
+    static_assert(N == 16 || N == 32 || N == 64, "padded orders 16, 32 and 64");
     static_assert(VEC || !FULL, "the unpadded form loads 16-byte pieces");
     if (FULL) n = N;
     constexpr int LPR = N / 4, RPI = 64 / LPR, K = N / RPI;
@@ -214,12 +215,17 @@ __global__ void __launch_bounds__(512) gemv_wave_dpp(int n, int batch, float alp
         bfly_step<4, kDppXor3>(v, (c & 2) != 0);
         bfly_step<2, kDppXor1>(v, (c & 1) != 0);
         row = RPI * c + g;
-    } else {
+    } else if (N == 32) {
         bfly_step<4, kDppHalfMirror>(v, (c & 4) != 0);
         bfly_step<2, kDppXor3>(v, (c & 2) != 0);
         v[0] += dpp_mov<kDppXor1>(v[0]);
         row = RPI * (c >> 1) + g;
         owner = (c & 1) == 0;
+    } else {
+        v[0] += dpp_mov<kDppXor1>(v[0]);
+        v[0] += dpp_mov<kDppXor2>(v[0]);
+        row = g;
+        owner = c == 0;
     }
     if (owner && (FULL || row < n)) {
         float out = alpha * v[0];
@@ -246,13 +252,13 @@ int launch_gemv(const Shape& sh, const Geometry& g, int batch, float alpha, cons
         }
     } else if (g.scope == GLASS_SCOPE_WAVE && gemv_uses_dpp(sh)) {
         const bool vec = sh.n % 4 == 0 && (uintptr_t)A % 16 == 0 && (uintptr_t)x % 16 == 0;
-        const int pad = sh.n <= 32 ? 32 : 64;
+        const int pad = sh.n <= 16 ? 16 : sh.n <= 32 ? 32 : 64;
         const bool full = vec && sh.n == pad;
 #define X(N, V, F)                                                                                            \
     if (pad == N && vec == V && full == F)                                                                    \
         hipLaunchKernelGGL((gemv_wave_dpp<N, V, F>), grid, block, 0, st, sh.n, batch, alpha, A, x, beta, y);
-        X(32, true, true) X(32, true, false) X(32, false, false) X(64, true, true) X(64, true, false)
-        X(64, false, false)
+        X(16, true, true) X(16, true, false) X(16, false, false) X(32, true, true) X(32, true, false)
+        X(32, false, false) X(64, true, true) X(64, true, false) X(64, false, false)
 #undef X
     } else if (g.scope == GLASS_SCOPE_WAVE) {
         const int mn = sh.m * sh.n;

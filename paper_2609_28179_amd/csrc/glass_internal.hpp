@@ -126,12 +126,13 @@ inline bool blk_solve1_shape(const Shape& s) {
     return s.n >= kBlkMinN && (s.op == GLASS_OP_TRSV || (s.op == GLASS_OP_POTRS && s.nrhs == 1));
 }
 
-// Square GEMV at wave scope keeps A in registers (no LDS) from order 17 up
-// when rows split into whole 16-byte pieces, and at every order whose staged
-// regions no longer fit eight wavefronts in the LDS budget (from 42 up), so
-// that feasibility stays monotone in the order.
+// Square GEMV at wave scope keeps A in registers (no LDS) at orders 12 and
+// 16 and from 17 up when rows split into whole 16-byte pieces, and at every
+// order whose staged regions no longer fit eight wavefronts in the LDS
+// budget (from 42 up), so that feasibility stays monotone in the order.
 inline bool gemv_uses_dpp(const Shape& s) {
-    if (s.op != GLASS_OP_GEMV || s.m != s.n || s.n <= 16) return false;
+    if (s.op != GLASS_OP_GEMV || s.m != s.n || s.n < 12) return false;
+    if (s.n <= 16) return s.n % 4 == 0;
     return s.n % 4 == 0 || 8 * region_floats(s) * sizeof(float) > kLdsBudgetBytes;
 }
 
