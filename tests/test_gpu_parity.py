@@ -144,7 +144,7 @@ def test_bit_identical_across_packs(env, op, scope):
 
 # operands 4, 8 and 12 bytes past a 16-byte boundary: every staging and
 # store path that widens to 16 bytes must fall back (contract: 4-byte aligned)
-N_SHIFT = {"thread": (3, 4, 6, 7, 8, 10, 16), "wave": (3, 8, 20, 25, 32, 64), "workgroup": (3, 16, 33),
+N_SHIFT = {"thread": (3, 4, 6, 7, 8, 10, 16), "wave": (3, 8, 12, 16, 20, 25, 32, 64), "workgroup": (3, 16, 33),
            "subwave": (4, 7, 12, 16, 24, 32)}
 
 
