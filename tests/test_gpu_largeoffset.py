@@ -102,3 +102,51 @@ def test_past_2g_elements(op, n):
         del L
     torch.cuda.empty_cache()
     assert err.max() <= TOL, f"max normwise error {err.max():.3e} at problems {idx[err > TOL]}"
+
+
+def test_ragged_past_2g_elements():
+    """The ragged solve with int64 problem offsets on both sides of 2^31
+    elements: the second half of a mixed batch (thread / sub-wave / row and
+    blocked wave classes) is moved up by 2^31 + 7 floats in A and 2^31 + 3 in
+    B (odd shifts, so its problems also lose their 16-byte alignment)."""
+    import torch
+    from paper_2609_28179_amd import glass
+    dev = torch.device("cuda:0")
+    case = inputs.make_ragged(48, seed=9, sizes=(5, 12, 18, 24, 36, 64))
+    half = len(case["n"]) // 2
+    shA, shB = ELEMS + 7, ELEMS + 3
+    offA = case["offA"].copy()
+    offB = case["offB"].copy()
+    offA[half:] += shA
+    offB[half:] += shB
+    print(f"ragged count={len(case['n'])} last offsets A {offA[-1]} B {offB[-1]}", flush=True)
+    A = torch.zeros(int(case["A"].size) + shA, dtype=torch.float32, device=dev)
+    B = torch.zeros(int(case["B"].size) + shB, dtype=torch.float32, device=dev)
+    a0, b0 = int(case["offA"][half]), int(case["offB"][half])
+    A[:a0] = torch.from_numpy(case["A"][:a0]).to(dev)
+    A[a0 + shA:] = torch.from_numpy(case["A"][a0:]).to(dev)
+    B[:b0] = torch.from_numpy(case["B"][:b0]).to(dev)
+    B[b0 + shB:] = torch.from_numpy(case["B"][b0:]).to(dev)
+    t = lambda a: torch.from_numpy(a).to(dev)
+    info = torch.full((len(case["n"]),), -7, dtype=torch.int32, device=dev)
+    ws_bytes = glass.glass_posv_ragged_workspace_size(len(case["n"]))
+    ws = torch.empty((ws_bytes + 3) // 4, dtype=torch.int32, device=dev)
+    assert glass.glass_posv_ragged(len(case["n"]), t(case["n"]), t(case["nrhs"]), t(offA), t(offB), A, B, info, ws,
+                                   ws_bytes) == 0
+    torch.cuda.synchronize()
+    A_ref, B_ref, info_ref = oracle.posv_ragged(case["n"], case["nrhs"], case["offA"], case["offB"], case["A"],
+                                                case["B"])
+    assert np.array_equal(info.cpu().numpy(), info_ref)
+    assert (info_ref == 0).all()
+    for i in range(len(case["n"])):
+        n, r = int(case["n"][i]), int(case["nrhs"][i])
+        L = A[offA[i]:offA[i] + n * n].cpu().numpy().reshape(n, n)
+        Lr = A_ref[case["offA"][i]:case["offA"][i] + n * n].reshape(n, n)
+        X = B[offB[i]:offB[i] + n * r].cpu().numpy()
+        Xr = B_ref[case["offB"][i]:case["offB"][i] + n * r]
+        assert np.max(np.abs(L - Lr)) / np.max(np.abs(Lr)) <= TOL, (i, n, r)
+        assert np.max(np.abs(X - Xr)) / max(np.max(np.abs(Xr)), 2.0 ** -126) <= TOL, (i, n, r)
+        iu = np.triu_indices(n, 1)
+        assert (L[iu] == 0).all() and not np.signbit(L[iu]).any(), (i, n)
+    del A, B
+    torch.cuda.empty_cache()
