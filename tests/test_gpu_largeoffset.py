@@ -21,10 +21,11 @@ def big_batch(n):
     return ELEMS // (n * n) + 3
 
 
-# (op, n): the table's placements at these batches are thread scope for n = 4,
-# sub-wave for n = 16 and the blocked / MFMA / register wave kernels for n = 64
-CASES = [("gemm", 4), ("posv", 4), ("potrf", 16), ("trsv", 16), ("gemm", 64), ("gemv", 64), ("posv", 64),
-         ("potrs", 64)]
+# (op, n): the table's placements at these batches are thread scope for n = 4
+# (SE(3): 4 x 4 transforms), sub-wave for n = 16 and the blocked / MFMA /
+# register wave kernels for n = 64
+CASES = [("gemm", 4), ("posv", 4), ("se3_compose", 4), ("potrf", 16), ("trsv", 16), ("gemm", 64), ("gemv", 64),
+         ("posv", 64), ("potrs", 64)]
 
 
 def sample_index(batch, n):
@@ -61,6 +62,16 @@ def test_past_2g_elements(op, n):
         torch.cuda.synchronize()
         err = normwise(h(y), oracle.gemv(h(A), h(x)))
         del A, x, y
+    elif op == "se3_compose":
+        Ta = inputs.se3_torch(g, batch, dev)
+        Tb = inputs.se3_torch(g, batch, dev)
+        T = torch.full((batch, 4, 4), float("nan"), dtype=torch.float32, device=dev)
+        assert glass.glass_se3_batched(glass.OP_SE3_COMPOSE, batch, Ta, Tb, T, None) == 0
+        torch.cuda.synchronize()
+        err = normwise(h(T), oracle.se3_compose(h(Ta), h(Tb)))
+        row3 = T.index_select(0, ti)[:, 3, :]
+        assert torch.equal(row3, torch.tensor([0.0, 0.0, 0.0, 1.0], device=dev).expand_as(row3))
+        del Ta, Tb, T
     elif op in ("potrf", "posv"):
         A = inputs.spd_torch(g, batch, n, dev, chunk=chunk)
         A0 = h(A)
@@ -100,6 +111,34 @@ def test_past_2g_elements(op, n):
             err = normwise(h(x), oracle.trsv(h(L), x0, 0))
             del x
         del L
+    torch.cuda.empty_cache()
+    assert err.max() <= TOL, f"max normwise error {err.max():.3e} at problems {idx[err > TOL]}"
+
+
+def test_adjoint_past_2g_elements():
+    """The POSV adjoint at n = 12 with L and dA holding 2^31 + 3 problems'
+    worth of floats (14.9 M problems), at the table's placement."""
+    import torch
+    from paper_2609_28179_amd import glass
+    dev = torch.device("cuda:0")
+    n = 12
+    batch = big_batch(n)
+    pl = glass.glass_query_placement(glass.OP_POSV_ADJOINT, n, batch)
+    print(f"adjoint n={n} batch={batch} table {glass.SCOPE_NAMES[pl.scope]}/P={pl.pack}", flush=True)
+    g = inputs.torch_generator(dev, 70_100)
+    L = inputs.lower_factor_torch(g, batch, n, dev, chunk=(1 << 24) // (n * n))
+    X = inputs.uniform_torch(g, (batch, n, 1), dev)
+    G = inputs.uniform_torch(g, (batch, n, 1), dev)
+    dB = torch.full((batch, n, 1), float("nan"), dtype=torch.float32, device=dev)
+    dA = torch.full((batch, n, n), float("nan"), dtype=torch.float32, device=dev)
+    assert glass.glass_posv_adjoint_batched(n, 1, batch, L, X, G, dB, dA, None) == 0
+    torch.cuda.synchronize()
+    idx = sample_index(batch, n)
+    ti = torch.from_numpy(idx).to(dev)
+    h = lambda t: t.index_select(0, ti).cpu().numpy()
+    dB_ref, dA_ref = oracle.posv_adjoint(h(L), h(X), h(G))
+    err = np.maximum(normwise(h(dB), dB_ref), normwise(h(dA), dA_ref))
+    del L, X, G, dB, dA
     torch.cuda.empty_cache()
     assert err.max() <= TOL, f"max normwise error {err.max():.3e} at problems {idx[err > TOL]}"
 
