@@ -20,6 +20,12 @@
 //      stores column c of K (K row-major nu x nx, so a row's stores are
 //      consecutive lanes).
 //
+// riccati_thread (thread scope, nx <= 8, nu <= 4): one problem per lane.  A
+// lane loads its own P, B, R and A (every load issued before any is used),
+// forms PB = P B, the lower triangle of S = R + B^T PB and the columns of
+// T = PB^T A in VGPRs, factors S with the thread-scope Cholesky and solves
+// S k = t for each column of T; its problem's K goes out in one run of stores.
+//
 // riccati_mfma (nx >= kRiccatiMfmaMinNx): every product on the matrix cores,
 // in the blocked layouts of chol_blk.hpp (nx padded to 16-row blocks; nu <= 16
 // is one block).  With B_k in accumulator layout (lane (q, r) holds B[16k+4q+c][r])
@@ -35,6 +41,7 @@
 #include "glass_internal.hpp"
 #include "chol_device.hpp"
 #include "chol_blk.hpp"
+#include "riccati.hpp"
 
 namespace glass {
 namespace {
@@ -144,6 +151,102 @@ __global__ void __launch_bounds__(512) riccati_mfma(int nx, int nu, int batch, c
             if (row < nu && col < nx) Kp[row * nx + col] = kj[e];
         }
     }
+}
+
+// L consecutive floats of one lane's problem at p, in accesses as wide as the
+// problem's size allows when `wide` (the batch's base pointer is 16-byte
+// aligned, so problem p starts at a multiple of L floats from it).
+template <int L>
+GLASS_DEV void lane_load(float (&v)[L], const float* __restrict__ p, bool wide) {
+    constexpr int AL = L % 4 == 0 ? 4 : L % 2 == 0 ? 2 : 1;
+    if (AL == 4 && wide) {
+#pragma unroll
+        for (int t = 0; t < L / 4; ++t) {
+            const f4_t x = *reinterpret_cast<const f4_t*>(p + 4 * t);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[4 * t + e] = x[e];
+        }
+    } else if (AL == 2 && wide) {
+#pragma unroll
+        for (int t = 0; t < L / 2; ++t) {
+            const float2 x = *reinterpret_cast<const float2*>(p + 2 * t);
+            v[2 * t] = x.x;
+            v[2 * t + 1] = x.y;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < L; ++t) v[t] = p[t];
+    }
+}
+
+template <int L>
+GLASS_DEV void lane_store(float* __restrict__ p, const float (&v)[L], bool wide) {
+    constexpr int AL = L % 4 == 0 ? 4 : L % 2 == 0 ? 2 : 1;
+    if (AL == 4 && wide) {
+#pragma unroll
+        for (int t = 0; t < L / 4; ++t) *reinterpret_cast<f4_t*>(p + 4 * t) = f4_t{v[4 * t], v[4 * t + 1], v[4 * t + 2], v[4 * t + 3]};
+    } else if (AL == 2 && wide) {
+#pragma unroll
+        for (int t = 0; t < L / 2; ++t) *reinterpret_cast<float2*>(p + 2 * t) = make_float2(v[2 * t], v[2 * t + 1]);
+    } else {
+#pragma unroll
+        for (int t = 0; t < L; ++t) p[t] = v[t];
+    }
+}
+
+template <int NX, int NU>
+__global__ void __launch_bounds__(512) riccati_thread(int batch, const float* __restrict__ A,
+                                                      const float* __restrict__ B, const float* __restrict__ P,
+                                                      const float* __restrict__ R, float* __restrict__ K,
+                                                      int32_t* __restrict__ info, bool wide) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= batch) return;
+    float pm[NX * NX], b[NX * NU], r[NU * NU], a[NX * NX];
+    lane_load<NX * NX>(pm, P + p * (NX * NX), wide);
+    lane_load<NX * NU>(b, B + p * (NX * NU), wide);
+    lane_load<NU * NU>(r, R + p * (NU * NU), wide);
+    lane_load<NX * NX>(a, A + p * (NX * NX), wide);
+    float pb[NX * NU];  // P B
+#pragma unroll
+    for (int i = 0; i < NX; ++i)
+#pragma unroll
+        for (int j = 0; j < NU; ++j) {
+            float s = 0.f;
+#pragma unroll
+            for (int k = 0; k < NX; ++k) s = fmaf(pm[i * NX + k], b[k * NU + j], s);
+            pb[i * NU + j] = s;
+        }
+    float sl[NU * (NU + 1) / 2];  // lower triangle of S = R + B^T (P B)
+#pragma unroll
+    for (int i = 0; i < NU; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            float s = r[i * NU + j];
+#pragma unroll
+            for (int k = 0; k < NX; ++k) s = fmaf(b[k * NU + i], pb[k * NU + j], s);
+            sl[TI(i, j)] = s;
+        }
+    float dinv[NU];
+    const int inf = tri_potrf<NU>(sl, dinv);
+    if (info) info[p] = inf;
+    if (inf != 0) return;
+    float kk[NU * NX];
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+        float y[NU];  // column c of T = (P B)^T A = B^T P A (P symmetric)
+#pragma unroll
+        for (int i = 0; i < NU; ++i) {
+            float s = 0.f;
+#pragma unroll
+            for (int k = 0; k < NX; ++k) s = fmaf(pb[k * NU + i], a[k * NX + c], s);
+            y[i] = s;
+        }
+        tri_fwd<NU>(sl, dinv, y);
+        tri_bwd<NU>(sl, dinv, y);
+#pragma unroll
+        for (int i = 0; i < NU; ++i) kk[i * NX + c] = y[i];
+    }
+    lane_store<NU * NX>(K + p * (NU * NX), kk, wide);
 }
 
 template <int NX8, int NU8>
@@ -288,6 +391,26 @@ int launch_riccati(int nx, int nu, int batch, int pack, const float* A, const fl
     RK(8, 8) RK(16, 8) RK(24, 8) RK(32, 8) RK(40, 8) RK(48, 8) RK(56, 8)
     RK(8, 16) RK(16, 16) RK(24, 16) RK(32, 16) RK(40, 16) RK(48, 16)
 #undef RK
+    return (int)hipErrorInvalidValue;
+}
+
+int launch_riccati_thread(int nx, int nu, int batch, int pack, const float* A, const float* B, const float* P,
+                          const float* R, float* K, int32_t* info, void* stream) {
+    (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
+    hipStream_t st = (hipStream_t)stream;
+    const int threads = 64 * pack;
+    dim3 grid((unsigned)((batch + threads - 1) / threads)), block(threads);
+    auto al16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
+    const bool wide = al16(A) && al16(B) && al16(P) && al16(R) && al16(K);
+#define RT(NX, NU)                                                                                          \
+    if (nx == NX && nu == NU) {                                                                             \
+        hipLaunchKernelGGL((riccati_thread<NX, NU>), grid, block, 0, st, batch, A, B, P, R, K, info, wide); \
+        return (int)hipGetLastError();                                                                      \
+    }
+#define RT_NX(NX) RT(NX, 1) RT(NX, 2) RT(NX, 3) RT(NX, 4)
+    RT_NX(1) RT_NX(2) RT_NX(3) RT_NX(4) RT_NX(5) RT_NX(6) RT_NX(7) RT_NX(8)
+#undef RT_NX
+#undef RT
     return (int)hipErrorInvalidValue;
 }
 

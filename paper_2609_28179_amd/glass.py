@@ -76,6 +76,7 @@ _SIGS = {
     "glass_stream_probe": [_i, _p, _p, _p, ctypes.c_longlong, _i, _p],
     "glass_riccati_gain_batched": [_i, _i, _i, _p, _p, _p, _p, _p, _p, _PP, _p],
     "glass_riccati_feasible": [_i, _i, _i],
+    "glass_riccati_placement_feasible": [_i, _i, _i, _i],
     "glass_ragged_table_provenance": [],
     "glass_last_launch_error": [],
     "glass_hip_error_name": [_i],
@@ -214,6 +215,10 @@ def glass_stream_probe(kind, a, b, c, n4, blocks, stream=None) -> int:
 
 def glass_riccati_feasible(nx, nu, pack) -> int:
     return _lib.glass_riccati_feasible(nx, nu, pack)
+
+
+def glass_riccati_placement_feasible(nx, nu, scope, pack) -> int:
+    return _lib.glass_riccati_placement_feasible(nx, nu, scope, pack)
 
 
 def glass_ragged_table_provenance() -> str:

@@ -11,6 +11,9 @@ granularity one more measured placement.  Here:
            cores in 16 x 16 tiles and S = R + B^T P B is factored as one
            diagonal tile; below, P and B are staged in LDS and the
            products read them as broadcasts;
+  fused_thread  the same launch at thread scope (nx <= 8, nu <= 4): one
+           problem per lane, every operand and intermediate in VGPRs,
+           64 P lanes per workgroup;
   unfused  the chain of library calls, each its own launch at the table's
            placement:  PB = P B (GEMM);  S = R (device copy);
            S += B^T PB (GEMM, transposed A);  PA = P A (GEMM);
@@ -59,9 +62,9 @@ def _ok(glass, st, what):
         glass._raise(st, what)
 
 
-def fused(glass, A, B, P, R, K, info=None, pack=None):
+def fused(glass, A, B, P, R, K, info=None, pack=None, scope="wave"):
     b, nx, nu = B.shape
-    force = None if pack is None else (glass.SCOPE_WAVE, pack)
+    force = None if pack is None else (glass.SCOPES[scope], pack)
     _ok(glass, glass.glass_riccati_gain_batched(nx, nu, b, A, B, P, R, K, info, force), "riccati_gain")
 
 
@@ -84,8 +87,11 @@ def flops(nx, nu):
     return 2 * nx * nx * (nx + nu) + 2 * nu * nx * (nx + nu) + nu ** 3 / 3 + 2 * nu * nu * nx
 
 
-def feasible_packs(glass, nx, nu):
-    return [p for p in PACKS if glass.glass_riccati_feasible(nx, nu, p) == 1]
+def feasible_packs(glass, nx, nu, scope="wave"):
+    return [p for p in PACKS if glass.glass_riccati_placement_feasible(nx, nu, glass.SCOPES[scope], p) == 1]
+
+
+FUSED_SCOPE = {"fused": "wave", "fused_thread": "thread"}
 
 
 def time_forms(glass, torch, nx, nu, batch, rounds=20, warmup=3, rng=None, device="cuda:0"):
@@ -100,11 +106,11 @@ def time_forms(glass, torch, nx, nu, batch, rounds=20, warmup=3, rng=None, devic
     for s in sets:
         s["K"] = torch.empty((batch, nu, nx), dtype=torch.float32, device=dev)
         s["ws"] = Workspace(torch, nx, nu, batch, dev)
-    forms = [("fused", p) for p in feasible_packs(glass, nx, nu)] + [("unfused", 0)]
+    forms = [(f, p) for f, sc in FUSED_SCOPE.items() for p in feasible_packs(glass, nx, nu, sc)] + [("unfused", 0)]
 
     def run(form, s):
-        if form[0] == "fused":
-            fused(glass, s["A"], s["B"], s["P"], s["R"], s["K"], None, form[1])
+        if form[0] in FUSED_SCOPE:
+            fused(glass, s["A"], s["B"], s["P"], s["R"], s["K"], None, form[1], FUSED_SCOPE[form[0]])
         else:
             unfused(glass, s["A"], s["B"], s["P"], s["R"], s["K"], s["ws"])
 
@@ -148,7 +154,7 @@ def sweep(args):
                            "nsets": nsets, "gbps": alg_bytes(nx, nu) * b / (us * 1e-6) / 1e9}
                     f.write(json.dumps(rec) + "\n")
                 f.flush()
-                fu = min(us for (fm, _), us in meds.items() if fm == "fused")
+                fu = min(us for (fm, _), us in meds.items() if fm in FUSED_SCOPE)
                 un = meds[("unfused", 0)]
                 print(f"nx={nx} nu={nu} batch={b}: fused {fu:.2f} us, unfused {un:.2f} us "
                       f"({'fused' if fu <= un else 'unfused'} {max(fu, un) / min(fu, un):.2f}x)", flush=True)
@@ -160,7 +166,7 @@ def load(path=DEFAULT_SWEEP):
 
 
 def choose(nx, nu, batch, recs=None):
-    """Composition advisor: ("fused", pack) or ("unfused", 0) from the
+    """Composition advisor: ("fused", pack), ("fused_thread", pack) or ("unfused", 0) from the
     measured records, at the nearest measured (nx, nu) (by order, then input
     count) and the nearest measured batch in log2 distance."""
     recs = recs if recs is not None else load()
@@ -180,11 +186,12 @@ def summary(args):
     for (nx, nu) in sorted({(r["nx"], r["nu"]) for r in recs}):
         for b in sorted({r["batch"] for r in recs if (r["nx"], r["nu"]) == (nx, nu)}):
             cell = [r for r in recs if (r["nx"], r["nu"], r["batch"]) == (nx, nu, b)]
-            fu = min((r for r in cell if r["form"] == "fused"), key=lambda r: r["median_us"])
+            fu = min((r for r in cell if r["form"] in FUSED_SCOPE), key=lambda r: r["median_us"])
             un = [r for r in cell if r["form"] == "unfused"][0]
             win = "fused" if fu["median_us"] <= un["median_us"] else "unfused"
             ratio = max(fu["median_us"], un["median_us"]) / min(fu["median_us"], un["median_us"])
-            lines.append(f"| {nx} | {nu} | {b} | P={fu['pack']} | {fu['median_us']:.2f} | {un['median_us']:.2f} | "
+            lines.append(f"| {nx} | {nu} | {b} | {FUSED_SCOPE[fu['form']]} P={fu['pack']} | {fu['median_us']:.2f} | "
+                         f"{un['median_us']:.2f} | "
                          f"{win} | {ratio:.2f}x | {fu['gbps']:.0f} |")
     text = "\n".join(lines) + "\n"
     if args.out:

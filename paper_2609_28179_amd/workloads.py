@@ -185,15 +185,16 @@ def adjoint(glass, torch, n=12, batch=16384, nrhs=1, rounds=20):
 
 
 def riccati_gain(glass, torch, cells=((12, 4, 64), (32, 8, 65536)), rounds=20):
-    """LQR gain fused (best feasible pack) against the unfused chain."""
+    """LQR gain fused (best feasible scope and pack) against the unfused chain."""
     from . import riccati
     out = []
     for nx, nu, batch in cells:
         meds, nsets = riccati.time_forms(glass, torch, nx, nu, batch, rounds=rounds)
-        fu = min(((us, pk) for (f, pk), us in meds.items() if f == "fused"))
+        fu = min(((us, pk, f) for (f, pk), us in meds.items() if f in riccati.FUSED_SCOPE))
         un = meds[("unfused", 0)]
         out.append({"workload": f"riccati_gain nx={nx} nu={nu} batch={batch}", "fused_us": round(fu[0], 2),
-                    "fused_pack": fu[1], "unfused_us": round(un, 2), "fused_speedup": round(un / fu[0], 3),
+                    "fused_scope": riccati.FUSED_SCOPE[fu[2]], "fused_pack": fu[1], "unfused_us": round(un, 2),
+                    "fused_speedup": round(un / fu[0], 3),
                     "fused_gbps": round(riccati.alg_bytes(nx, nu) * batch / (fu[0] * 1e-6) / 1e9, 1)})
     return out
 

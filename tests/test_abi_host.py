@@ -92,6 +92,23 @@ def test_riccati_and_gemm_ex_validation_paths(glass):
     # the LDS-staged form (nx <= 8) at most 464 floats: every pack fits
     for nx, nu in ((48, 16), (56, 8), (8, 16), (1, 1)):
         assert all(g.glass_riccati_feasible(nx, nu, p) == 1 for p in (1, 2, 4, 8)), (nx, nu)
+    # scope-aware feasibility: thread scope up to nx = 8, nu = 4; wavefront as
+    # above; the other scopes never; bad scope / pack and sizes as documented
+    T, W = g.SCOPES["thread"], g.SCOPES["wave"]
+    for nx, nu in ((1, 1), (4, 2), (8, 4), (5, 3)):
+        assert all(g.glass_riccati_placement_feasible(nx, nu, T, p) == 1 for p in (1, 2, 4, 8)), (nx, nu)
+    for nx, nu in ((9, 1), (4, 5), (12, 4), (48, 16)):
+        assert g.glass_riccati_placement_feasible(nx, nu, T, 1) == 0, (nx, nu)
+        assert g.glass_riccati_gain_batched(nx, nu, 3, FAKE, FAKE, FAKE, FAKE, FAKE, force=("thread", 1),
+                                            stream=S) == g.ERR_INFEASIBLE_PLACEMENT
+    for nx, nu in ((12, 4), (4, 2), (56, 8)):
+        for p in (1, 2, 4, 8):
+            assert g.glass_riccati_placement_feasible(nx, nu, W, p) == g.glass_riccati_feasible(nx, nu, p)
+        assert g.glass_riccati_placement_feasible(nx, nu, g.SCOPES["workgroup"], 1) == 0
+        assert g.glass_riccati_placement_feasible(nx, nu, g.SCOPES["subwave"], 1) == 0
+    assert g.glass_riccati_placement_feasible(4, 2, 17, 1) == g.ERR_INVALID_VALUE
+    assert g.glass_riccati_placement_feasible(4, 2, T, 3) == g.ERR_INVALID_VALUE
+    assert g.glass_riccati_placement_feasible(57, 1, T, 1) == g.ERR_UNSUPPORTED
 
 
 def test_mlp_validation_paths(glass):

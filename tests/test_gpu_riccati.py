@@ -87,6 +87,79 @@ def test_fused_gain_parity(env, nx, nu):
             assert normwise(K.cpu().numpy(), K_ref).max() <= TOL
 
 
+THREAD_SIZES = [(1, 1), (1, 4), (2, 3), (3, 1), (4, 2), (5, 3), (6, 4), (7, 2), (8, 1), (8, 4)]
+
+
+@pytest.mark.parametrize("nx,nu", THREAD_SIZES)
+def test_fused_gain_thread_parity(env, nx, nu):
+    """The thread-scope form (one problem per lane), at every pack, on
+    16-byte aligned operands and on operands one float off alignment (the
+    4-byte access path), with batches that leave ragged workgroups."""
+    glass, torch = env
+    assert glass.glass_riccati_placement_feasible(nx, nu, glass.SCOPES["thread"], 1) == 1
+    for batch in (1, 67, 1000):
+        c = inputs.make_riccati(batch, nx, nu, seed=15)
+        K_ref, info_ref = oracle.riccati_gain(c["A"], c["B"], c["P"], c["R"])
+        assert (info_ref == 0).all()
+        for shift in (0, 1):
+            ops = {}
+            for key in ("A", "B", "P", "R"):
+                flat = np.ascontiguousarray(c[key]).reshape(-1)
+                buf = torch.full((flat.size + 4,), float("nan"), device="cuda:0")
+                buf[shift:shift + flat.size] = torch.from_numpy(flat).to("cuda:0")
+                ops[key] = buf[shift:shift + flat.size]
+            Kbuf = torch.full((batch * nu * nx + 8,), float("nan"), device="cuda:0")
+            K = Kbuf[shift + 4:shift + 4 + batch * nu * nx]  # 16-byte aligned at shift 0
+            for pack in (1, 2, 4, 8):
+                print(f"riccati fused thread nx={nx} nu={nu} batch={batch} P={pack} shift={shift}", flush=True)
+                K.fill_(float("nan"))
+                info = torch.full((batch,), -7, dtype=torch.int32, device="cuda:0")
+                st = glass.glass_riccati_gain_batched(nx, nu, batch, ops["A"], ops["B"], ops["P"], ops["R"], K, info,
+                                                      ("thread", pack))
+                assert st == 0, st
+                torch.cuda.synchronize()
+                assert np.array_equal(info.cpu().numpy(), info_ref)
+                assert normwise(K.cpu().numpy().reshape(batch, nu, nx), K_ref).max() <= TOL
+                kb = Kbuf.cpu().numpy()  # nothing written outside K
+                assert np.isnan(kb[:shift + 4]).all() and np.isnan(kb[shift + 4 + batch * nu * nx:]).all()
+
+
+def test_fused_default_placement_small_sizes(env):
+    """force = NULL at sizes within the thread scope's range (its default there)."""
+    glass, torch = env
+    for nx, nu in ((1, 1), (4, 2), (8, 4)):
+        batch = 333
+        c = inputs.make_riccati(batch, nx, nu, seed=17)
+        K_ref, info_ref = oracle.riccati_gain(c["A"], c["B"], c["P"], c["R"])
+        print(f"riccati fused default nx={nx} nu={nu} batch={batch}", flush=True)
+        K = torch.full((batch, nu, nx), float("nan"), device="cuda:0")
+        info = torch.full((batch,), -7, dtype=torch.int32, device="cuda:0")
+        assert glass.glass_riccati_gain_batched(nx, nu, batch, dev(torch, c["A"]), dev(torch, c["B"]),
+                                                dev(torch, c["P"]), dev(torch, c["R"]), K, info) == 0
+        torch.cuda.synchronize()
+        assert np.array_equal(info.cpu().numpy(), info_ref)
+        assert normwise(K.cpu().numpy(), K_ref).max() <= TOL
+
+
+def test_fused_thread_info_on_indefinite_problems(env):
+    glass, torch = env
+    nx, nu, batch = 4, 2, 70
+    c = inputs.make_riccati(batch, nx, nu, seed=16)
+    bad = np.arange(3, batch, 5)
+    c["R"][bad] = -50.0 * np.eye(nu, dtype=np.float32)   # S = R + B^T P B is then negative definite
+    K_ref, info_ref = oracle.riccati_gain(c["A"], c["B"], c["P"], c["R"])
+    assert (info_ref[bad] == 1).all() and (np.delete(info_ref, bad) == 0).all()
+    K = torch.zeros((batch, nu, nx), device="cuda:0")
+    info = torch.full((batch,), -7, dtype=torch.int32, device="cuda:0")
+    assert glass.glass_riccati_gain_batched(nx, nu, batch, dev(torch, c["A"]), dev(torch, c["B"]),
+                                            dev(torch, c["P"]), dev(torch, c["R"]), K, info, ("thread", 1)) == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(info.cpu().numpy(), info_ref)
+    good = np.setdiff1d(np.arange(batch), bad)
+    assert normwise(K.cpu().numpy()[good], K_ref[good]).max() <= TOL
+    assert (K.cpu().numpy()[bad] == 0).all()  # K is not written where info is nonzero
+
+
 @pytest.mark.parametrize("nx,nu", SIZES)
 def test_unfused_chain_parity(env, nx, nu):
     glass, torch = env
