@@ -77,7 +77,35 @@ GLASS_DEV f4_t load_acc_block(const float* M, int ld, int rows, int cols, int r0
     return v;
 }
 
-template <int NXB>
+// L^{-1} of a 16 x 16 lower diagonal block whose rows and columns from NK on
+// are the identity, in T layout: the substitution steps K >= NK add nothing
+// (their coefficients are zero), so only the first NK run.
+template <int K, int NK>
+struct InvStepN {
+    static GLASS_DEV void run(float (&u)[4], const float (&m)[16]) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) fmac_self_bcast<K>(u[c], m[K]);
+        InvStepN<K + 1, NK>::run(u, m);
+    }
+};
+template <int NK>
+struct InvStepN<NK, NK> {
+    static GLASS_DEV void run(float (&)[4], const float (&)[16]) {}
+};
+
+template <int NK>
+GLASS_DEV f4_t tri_inverse_l_first(const float (&m)[16], float myinv, int q, int r) {
+    float u[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) u[c] = (4 * q + c == r) ? myinv : 0.f;
+    asm volatile("s_nop 1" : "+v"(u[0]), "+v"(u[1]), "+v"(u[2]), "+v"(u[3]));
+    InvStepN<0, NK>::run(u, m);
+    return f4_t{u[0], u[1], u[2], u[3]};
+}
+
+// NUB: nu rounded up to 4, 8 or 16.  S is the identity past nu, so its
+// factorization and inverse run NUB pivot steps instead of 16.
+template <int NXB, int NUB>
 __global__ void __launch_bounds__(512) riccati_mfma(int nx, int nu, int batch, const float* __restrict__ A,
                                                     const float* __restrict__ B, const float* __restrict__ P,
                                                     const float* __restrict__ R, float* __restrict__ K,
@@ -125,16 +153,21 @@ __global__ void __launch_bounds__(512) riccati_mfma(int nx, int nu, int batch, c
     wave_sync();
     int f = 0;
     float myinv = 1.f;
-    SegStep<16, 16, 0>::run(a, f, myinv);
+    {
+        float as[NUB];  // the first NUB columns; rows from NUB on are identity rows
 #pragma unroll
-    for (int c = 0; c < 16; ++c) a[c] = c <= r ? a[c] : 0.f;
+        for (int c = 0; c < NUB; ++c) as[c] = a[c];
+        SegStep<16, NUB, 0>::run(as, f, myinv);
+#pragma unroll
+        for (int c = 0; c < 16; ++c) a[c] = c < NUB ? (c <= r ? as[c] : 0.f) : (c == r ? 1.f : 0.f);
+    }
     if (info && lane == 0) info[p] = f;
     if (f != 0) return;  // K is not written for an indefinite S
     float m[16];  // the rows again, diagonal entry cleared, scaled by -1 / L_rr
     rows_zero_diag<kXS, false>(a, m, xs, q, r);
 #pragma unroll
     for (int j = 0; j < 16; ++j) m[j] *= -myinv;
-    const f4_t linv = tri_inverse_l(m, myinv, q, r);  // L^{-1} in T layout
+    const f4_t linv = tri_inverse_l_first<NUB>(m, myinv, q, r);  // L^{-1} in T layout
     f4_t lt[4];
     lt[0] = linv;
     transpose_blocks<1>(lt, xs, q, r);  // lt[0]: L^{-T} in T layout
@@ -372,10 +405,15 @@ int launch_riccati(int nx, int nu, int batch, int pack, const float* A, const fl
     dim3 grid((unsigned)((batch + pack - 1) / pack)), block(64 * pack);
     const size_t lds = sizeof(float) * (size_t)region * pack;
     if (riccati_uses_mfma(nx)) {
-        switch ((nx + 15) / 16) {
-#define RM(NXB) \
-    case NXB: hipLaunchKernelGGL((riccati_mfma<NXB>), grid, block, lds, st, nx, nu, batch, A, B, P, R, K, info); break;
-            RM(1) RM(2) RM(3) RM(4)
+        const int nub = nu <= 4 ? 4 : nu <= 8 ? 8 : 16;
+        switch ((nx + 15) / 16 * 100 + nub) {
+#define RM(NXB, NUB)                                                                                            \
+    case NXB * 100 + NUB:                                                                                       \
+        hipLaunchKernelGGL((riccati_mfma<NXB, NUB>), grid, block, lds, st, nx, nu, batch, A, B, P, R, K, info); \
+        break;
+#define RM_NX(NXB) RM(NXB, 4) RM(NXB, 8) RM(NXB, 16)
+            RM_NX(1) RM_NX(2) RM_NX(3) RM_NX(4)
+#undef RM_NX
 #undef RM
         default: return (int)hipErrorInvalidValue;
         }
