@@ -38,6 +38,62 @@ GLASS_DEV float sym_pair(float acc, float p, float q, float r, float s) {
     return acc + t;
 }
 
+// One right-hand side, N % 4 == 0, every operand 16-byte aligned: the same
+// arithmetic as adjoint_thread with no LDS.  Each lane loads the 16-byte
+// pieces of its own problem's rows at or left of the diagonal, x and g, all
+// issued before any is used, and stores dB and the rows of dA straight to
+// memory.  (dB may be G: a lane reads its g before it writes its dB.)  Entry
+// (i, j) of dA is formed here as b_i x_j + x_i b_j for every j, which is the
+// staged kernel's value of the (j, i) pair with the sum's terms swapped, so
+// the result is the same bit for bit.
+template <int N>
+__global__ void __launch_bounds__(512) adjoint_thread1(int batch, const float* __restrict__ L,
+                                                       const float* __restrict__ X, const float* G, float* dB,
+                                                       float* __restrict__ dA) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= batch) return;
+    const float* Lp = L + p * (N * N);
+    float a[N * (N + 1) / 2];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int t = 0; t <= i / 4; ++t) {
+            const f4_t v = *reinterpret_cast<const f4_t*>(Lp + i * N + 4 * t);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (4 * t + e <= i) a[TI(i, 4 * t + e)] = v[e];
+        }
+    float x[N], y[N];
+#pragma unroll
+    for (int t = 0; t < N / 4; ++t) {
+        const f4_t xv = *reinterpret_cast<const f4_t*>(X + p * N + 4 * t);
+        const f4_t gv = *reinterpret_cast<const f4_t*>(G + p * N + 4 * t);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            x[4 * t + e] = xv[e];
+            y[4 * t + e] = gv[e];
+        }
+    }
+    float dinv[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) dinv[i] = recip(a[TI(i, i)]);
+    tri_fwd<N>(a, dinv, y);
+    tri_bwd<N>(a, dinv, y);
+#pragma unroll
+    for (int t = 0; t < N / 4; ++t)
+        *reinterpret_cast<f4_t*>(dB + p * N + 4 * t) = f4_t{y[4 * t], y[4 * t + 1], y[4 * t + 2], y[4 * t + 3]};
+    float* Ap = dA + p * (N * N);
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int t = 0; t < N / 4; ++t) {
+            f4_t o;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] = -0.5f * sym_pair(0.f, y[i], x[4 * t + e], x[i], y[4 * t + e]);
+            *reinterpret_cast<f4_t*>(Ap + i * N + 4 * t) = o;
+        }
+}
+
 template <int N>
 __global__ void __launch_bounds__(512) adjoint_thread(int nrhs, int batch, const float* __restrict__ L,
                                                       const float* __restrict__ X, const float* G,
@@ -218,6 +274,15 @@ int launch_posv_adjoint(const Shape& sh, const Geometry& g, int batch, const flo
     const int n = sh.n, r = sh.nrhs;
     dim3 grid((unsigned)g.grid), block(g.threads);
     if (g.scope == GLASS_SCOPE_THREAD) {
+        auto al16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
+        if (r == 1 && (n & 3) == 0 && al16(L) && al16(X) && al16(G) && al16(dB) && al16(dA)) {
+            switch (n) {
+#define CASE1(N) \
+    case N: hipLaunchKernelGGL(adjoint_thread1<N>, grid, block, 0, st, batch, L, X, G, dB, dA); return (int)hipGetLastError();
+                CASE1(4) CASE1(8) CASE1(12) CASE1(16)
+#undef CASE1
+            }
+        }
         switch (n) {
 #define CASE(N) \
     case N: hipLaunchKernelGGL(adjoint_thread<N>, grid, block, g.lds_bytes, st, r, batch, L, X, G, dB, dA); break;

@@ -85,3 +85,45 @@ def test_adjoint_config3_and_finite_differences(env):
             fd = ((loss(At + eps * S, Bt) - loss(At - eps * S, Bt))[q] / (2 * eps)).item()
             an = (gA[q] * S[q]).sum().item()
             assert abs(fd - an) <= 1e-2 * max(1.0, abs(an)), (q, i, j, fd, an)
+
+
+@pytest.mark.parametrize("n", [4, 8, 12, 16])
+def test_adjoint_thread_direct_form_bit_identical(env, n):
+    """One right-hand side at thread scope: aligned operands take the direct
+    form (no LDS), operands one float off alignment the staged form; both
+    must give the same dB and dA bit for bit, within the oracle's tolerance,
+    and leave the guard floats around the outputs untouched."""
+    glass, torch = env
+    batch = 333
+    rng = inputs.rng_for(5, "adjoint", n, batch, 1)
+    A = inputs.spd(rng, batch, n)
+    B = inputs.uniform(rng, (batch, n, 1))
+    W = rng.standard_normal(size=(batch, n, 1)).astype(np.float32)
+    L_ref, X_ref, _ = oracle.posv(A, B)
+    dB_ref, dA_ref = oracle.posv_adjoint(L_ref, X_ref, W)
+    Lt = torch.from_numpy(A).to("cuda:0")
+    Xt = torch.from_numpy(B).to("cuda:0")
+    glass.posv_(Lt, Xt, force=("wave", 1))
+    torch.cuda.synchronize()
+    out = {}
+    for shift in (0, 1):
+        print(f"adjoint thread direct n={n} shift={shift}", flush=True)
+        ops = {}
+        for key, t in (("L", Lt), ("X", Xt), ("G", torch.from_numpy(W).to("cuda:0"))):
+            buf = torch.full((t.numel() + 8,), float("nan"), device="cuda:0")
+            buf[4 + shift:4 + shift + t.numel()] = t.reshape(-1)
+            ops[key] = buf[4 + shift:4 + shift + t.numel()]
+        dBb = torch.full((batch * n + 8,), float("nan"), device="cuda:0")
+        dAb = torch.full((batch * n * n + 8,), float("nan"), device="cuda:0")
+        dB = dBb[4 + shift:4 + shift + batch * n]
+        dA = dAb[4 + shift:4 + shift + batch * n * n]
+        assert glass.glass_posv_adjoint_batched(n, 1, batch, ops["L"], ops["X"], ops["G"], dB, dA, ("thread", 1)) == 0
+        torch.cuda.synchronize()
+        for buf in (dBb, dAb):
+            h = buf.cpu().numpy()
+            assert np.isnan(h[:4 + shift]).all() and np.isnan(h[len(h) - 4 + shift:]).all()
+        out[shift] = (dB.cpu().numpy().reshape(batch, n, 1), dA.cpu().numpy().reshape(batch, n, n))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    assert normwise(out[0][0], dB_ref).max() <= TOL
+    assert normwise(out[0][1], dA_ref).max() <= TOL
+    assert np.array_equal(out[0][1], np.swapaxes(out[0][1], 1, 2))
