@@ -268,13 +268,15 @@ size_t glass_posv_ragged_perm_offset(int count);
  * unspecified and not written where it is nonzero).  Device pointers owned
  * by the caller; inputs are not modified.  Sizes: 1 <= nu <= 16,
  * 1 <= nx <= 56, nx + nu <= 64 and nx <= 48 when nu > 8, else
- * GLASS_ERR_UNSUPPORTED.  Two scopes: wavefront (one problem per 64-lane
+ * GLASS_ERR_UNSUPPORTED.  Three scopes: wavefront (one problem per 64-lane
  * wavefront, every intermediate in VGPRs / LDS; force->pack sets the problems
- * per workgroup) and, for nx <= 8 and nu <= 4, thread (one problem per lane,
- * every operand and intermediate in VGPRs; force->pack sets 64 * pack lanes
- * per workgroup).  With force NULL: thread scope with one wavefront per
- * workgroup where it runs, else wavefront scope.  Any other forced scope, or
- * thread scope at larger sizes, is GLASS_ERR_INFEASIBLE_PLACEMENT. */
+ * per workgroup); for nx <= 16 and nu <= 8, sub-wave (four problems per
+ * wavefront, one per 16-lane row; force->pack wavefronts per workgroup); and,
+ * for nx <= 8 and nu <= 4, thread (one problem per lane, every operand and
+ * intermediate in VGPRs; force->pack sets 64 * pack lanes per workgroup).
+ * With force NULL: thread scope with one wavefront per workgroup where it
+ * runs, else wavefront scope.  The workgroup scope, or a scope outside its
+ * sizes, is GLASS_ERR_INFEASIBLE_PLACEMENT. */
 glass_status_t glass_riccati_gain_batched(int nx, int nu, int batch, const float* A,
                                           const float* B, const float* P, const float* R,
                                           float* K, int32_t* info,
@@ -289,7 +291,8 @@ int glass_riccati_feasible(int nx, int nu, int pack);
  * 0 if that placement is infeasible, or a negative status for an invalid
  * scope or pack (GLASS_ERR_INVALID_VALUE) or unsupported sizes
  * (GLASS_ERR_UNSUPPORTED).  Thread scope: nx <= 8 and nu <= 4, any pack;
- * wavefront scope: as glass_riccati_feasible; other scopes: 0. */
+ * sub-wave scope: nx <= 16 and nu <= 8, any pack; wavefront scope: as
+ * glass_riccati_feasible; workgroup scope: 0. */
 int glass_riccati_placement_feasible(int nx, int nu, int scope, int pack);
 
 /* Streaming bandwidth probe: the attainable HBM bandwidth of a plain kernel

@@ -298,6 +298,10 @@ glass_status_t glass_riccati_gain_batched(int nx, int nu, int batch, const float
             if (!riccati_thread_ok(nx, nu)) return GLASS_ERR_INFEASIBLE_PLACEMENT;
             return launched(launch_riccati_thread(nx, nu, batch, force->pack, A, B, P, R, K, info, stream));
         }
+        if (force->scope == GLASS_SCOPE_SUBWAVE) {
+            if (!riccati_seg_ok(nx, nu)) return GLASS_ERR_INFEASIBLE_PLACEMENT;
+            return launched(launch_riccati_seg(nx, nu, batch, force->pack, A, B, P, R, K, info, stream));
+        }
         if (force->scope != GLASS_SCOPE_WAVE) return GLASS_ERR_INFEASIBLE_PLACEMENT;
         pack = force->pack;
     }
@@ -319,6 +323,7 @@ int glass_riccati_placement_feasible(int nx, int nu, int scope, int pack) {
     if (!valid_force(&f)) return GLASS_ERR_INVALID_VALUE;
     if (!riccati_size_ok(nx, nu)) return GLASS_ERR_UNSUPPORTED;
     if (scope == GLASS_SCOPE_THREAD) return riccati_thread_ok(nx, nu) ? 1 : 0;
+    if (scope == GLASS_SCOPE_SUBWAVE) return riccati_seg_ok(nx, nu) ? 1 : 0;
     if (scope == GLASS_SCOPE_WAVE) return glass_riccati_feasible(nx, nu, pack);
     return 0;
 }

@@ -26,6 +26,15 @@
 // T = PB^T A in VGPRs, factors S with the thread-scope Cholesky and solves
 // S k = t for each column of T; its problem's K goes out in one run of stores.
 //
+// riccati_seg (sub-wave scope, nx <= 16, nu <= 8): four problems per
+// wavefront, one per 16-lane row; lane i of a row holds row i of P, B and R
+// and column i of A.  PB's row i takes B's rows as DPP row broadcasts;
+// S = R + B^T PB sums each lane's outer product B_i PB_i^T over the row with
+// four DPP exchanges; S is factored with the segment Cholesky (lane a holds
+// row a of L); column i of T = PB^T A takes PB's rows as broadcasts, and
+// lane i solves L L^T k = t for its own column of K with L's entries as
+// broadcasts.  Every cross-lane move stays inside a 16-lane row.
+//
 // riccati_mfma (nx >= kRiccatiMfmaMinNx): every product on the matrix cores,
 // in the blocked layouts of chol_blk.hpp (nx padded to 16-row blocks; nu <= 16
 // is one block).  With B_k in accumulator layout (lane (q, r) holds B[16k+4q+c][r])
@@ -37,6 +46,8 @@
 //   K_j  = L^{-T} L^{-1} T_j              S = L L^T factored as a diagonal block
 // S's padded diagonal (orders nu..15) is the identity, so the factorization
 // and the solve run on a full 16 x 16 block.
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "glass_internal.hpp"
 #include "chol_device.hpp"
@@ -282,6 +293,133 @@ __global__ void __launch_bounds__(512) riccati_thread(int batch, const float* __
     lane_store<NU * NX>(K + p * (NU * NX), kk, wide);
 }
 
+template <int CTRL>
+GLASS_DEV float row_dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+// lane K of the 16-lane row (row_newbcast)
+template <int K>
+GLASS_DEV float row_bcast(float v) {
+    return row_dpp<0x150 + K>(v);
+}
+// the sum over the 16 lanes of a row, the same value in each: pairs, quads
+// (quad_perm [1,0,3,2] and [2,3,0,1]), then half rows and rows (row_half_mirror,
+// row_mirror); each step adds two equal-order operands, so every lane agrees
+GLASS_DEV float row_sum16(float v) {
+    v += row_dpp<0xB1>(v);
+    v += row_dpp<0x4E>(v);
+    v += row_dpp<0x141>(v);
+    v += row_dpp<0x140>(v);
+    return v;
+}
+
+template <int I, int N, class F>
+GLASS_DEV void static_for(F&& f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+template <int NUB>
+__global__ void __launch_bounds__(512) riccati_seg(int nx, int nu, int batch, const float* __restrict__ A,
+                                                   const float* __restrict__ B, const float* __restrict__ P,
+                                                   const float* __restrict__ R, float* __restrict__ K,
+                                                   int32_t* __restrict__ info) {
+    const int lane = threadIdx.x & 63, s = lane >> 4, i = lane & 15;
+    const long long p0 = ((long long)blockIdx.x * (blockDim.x >> 6) + wave_index()) * 4;
+    if (p0 >= batch) return;
+    const long long ps = p0 + s;
+    const bool act = ps < batch;
+    const long long pp = act ? ps : p0;  // a row past the batch reads its wave's first problem
+    const float* Pp = P + pp * nx * nx;
+    const float* Ap = A + pp * nx * nx;
+    const float* Bp = B + pp * nx * nu;
+    const float* Rp = R + pp * nu * nu;
+    const bool row = i < nx;
+    float prow[16], acol[16], brow[NUB], rrow[NUB];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {  // unconditional loads (entry 0 for the rest), so that all issue at once
+        const bool ok = act && row && k < nx;
+        const float pv = Pp[ok ? i * nx + k : 0];
+        const float av = Ap[ok ? k * nx + i : 0];
+        prow[k] = ok ? pv : 0.f;
+        acol[k] = ok ? av : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < NUB; ++j) {
+        const bool okb = act && row && j < nu, okr = act && i < nu && j < nu;
+        const float bv = Bp[okb ? i * nu + j : 0];
+        const float rv = Rp[okr ? i * nu + j : 0];
+        brow[j] = okb ? bv : 0.f;
+        rrow[j] = okr ? rv : 0.f;
+    }
+    // row i of P B
+    float pb[NUB];
+#pragma unroll
+    for (int j = 0; j < NUB; ++j) pb[j] = 0.f;
+    static_for<0, 16>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+#pragma unroll
+        for (int j = 0; j < NUB; ++j) pb[j] = fmaf(prow[k], row_bcast<k>(brow[j]), pb[j]);
+    });
+    // S = R + B^T P B: lane i contributes B_i PB_i^T; row i of S to lane i
+    // (identity rows from nu to NUB, zero rows past NUB)
+    float srow[NUB];
+#pragma unroll
+    for (int c = 0; c < NUB; ++c) srow[c] = 0.f;
+#pragma unroll
+    for (int a = 0; a < NUB; ++a)
+#pragma unroll
+        for (int c = 0; c <= a; ++c) {
+            const float v = row_sum16(brow[a] * pb[c]);
+            if (i == a) srow[c] = a < nu ? rrow[c] + v : (c == a ? 1.f : 0.f);
+            if (i == c && c != a) srow[a] = c < nu ? rrow[a] + v : 0.f;
+        }
+    int f = 0;
+    float myinv = 1.f;
+    SegStep<16, NUB, 0>::run(srow, f, myinv);
+    if (act && i == 0 && info) info[ps] = f;
+    if (f != 0) return;  // the row's problem is indefinite (or past the batch): K is not written
+    // column i of T = (P B)^T A
+    float t[NUB];
+#pragma unroll
+    for (int a = 0; a < NUB; ++a) t[a] = 0.f;
+    static_for<0, 16>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+#pragma unroll
+        for (int a = 0; a < NUB; ++a) t[a] = fmaf(row_bcast<k>(pb[a]), acol[k], t[a]);
+    });
+    // L's strictly lower entries and 1 / L_aa as broadcasts, then L L^T k = t
+    float lo[NUB][NUB], inv[NUB];
+    static_for<0, NUB>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        inv[a] = row_bcast<a>(myinv);
+#pragma unroll
+        for (int b = 0; b < a; ++b) lo[a][b] = row_bcast<a>(srow[b]);
+    });
+#pragma unroll
+    for (int a = 0; a < NUB; ++a) {
+        float v = t[a];
+#pragma unroll
+        for (int b = 0; b < a; ++b) v = fmaf(-lo[a][b], t[b], v);
+        t[a] = v * inv[a];
+    }
+#pragma unroll
+    for (int a = NUB - 1; a >= 0; --a) {
+        float v = t[a];
+#pragma unroll
+        for (int b = a + 1; b < NUB; ++b) v = fmaf(-lo[b][a], t[b], v);
+        t[a] = v * inv[a];
+    }
+    if (act && row) {
+        float* Kp = K + ps * nu * nx + i;
+#pragma unroll
+        for (int a = 0; a < NUB; ++a)
+            if (a < nu) Kp[a * nx] = t[a];
+    }
+}
+
 template <int NX8, int NU8>
 __global__ void __launch_bounds__(512) riccati_wave(int nx, int nu, int batch, const float* __restrict__ A,
                                                     const float* __restrict__ B, const float* __restrict__ P,
@@ -430,6 +568,19 @@ int launch_riccati(int nx, int nu, int batch, int pack, const float* A, const fl
     RK(8, 16) RK(16, 16) RK(24, 16) RK(32, 16) RK(40, 16) RK(48, 16)
 #undef RK
     return (int)hipErrorInvalidValue;
+}
+
+int launch_riccati_seg(int nx, int nu, int batch, int pack, const float* A, const float* B, const float* P,
+                       const float* R, float* K, int32_t* info, void* stream) {
+    (void)hipGetLastError();  // a stale error of an earlier runtime call is not ours
+    hipStream_t st = (hipStream_t)stream;
+    const int per_wg = 4 * pack;
+    dim3 grid((unsigned)((batch + per_wg - 1) / per_wg)), block(64 * pack);
+    if (nu <= 4)
+        hipLaunchKernelGGL((riccati_seg<4>), grid, block, 0, st, nx, nu, batch, A, B, P, R, K, info);
+    else
+        hipLaunchKernelGGL((riccati_seg<8>), grid, block, 0, st, nx, nu, batch, A, B, P, R, K, info);
+    return (int)hipGetLastError();
 }
 
 int launch_riccati_thread(int nx, int nu, int batch, int pack, const float* A, const float* B, const float* P,

@@ -15,6 +15,19 @@ inline bool riccati_thread_ok(int nx, int nu) {
     return nx >= 1 && nu >= 1 && nx <= kRiccatiThreadMaxNx && nu <= kRiccatiThreadMaxNu;
 }
 
+// Sub-wave scope: four problems per wavefront, one per 16-lane row.
+constexpr int kRiccatiSegMaxNx = 16;
+constexpr int kRiccatiSegMaxNu = 8;
+
+inline bool riccati_seg_ok(int nx, int nu) {
+    return nx >= 1 && nu >= 1 && nx <= kRiccatiSegMaxNx && nu <= kRiccatiSegMaxNu;
+}
+
+// pack wavefronts (4 * pack problems) per workgroup; the caller has checked
+// riccati_seg_ok.
+int launch_riccati_seg(int nx, int nu, int batch, int pack, const float* A, const float* B, const float* P,
+                       const float* R, float* K, int32_t* info, void* stream);
+
 // 64 * pack lanes per workgroup; the caller has checked riccati_thread_ok.
 int launch_riccati_thread(int nx, int nu, int batch, int pack, const float* A, const float* B, const float* P,
                           const float* R, float* K, int32_t* info, void* stream);

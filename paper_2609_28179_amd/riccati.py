@@ -11,6 +11,9 @@ granularity one more measured placement.  Here:
            cores in 16 x 16 tiles and S = R + B^T P B is factored as one
            diagonal tile; below, P and B are staged in LDS and the
            products read them as broadcasts;
+  fused_subwave  the same launch at sub-wave scope (nx <= 16, nu <= 8):
+           four problems per wavefront, one per 16-lane row, every
+           cross-lane move a DPP exchange inside the row;
   fused_thread  the same launch at thread scope (nx <= 8, nu <= 4): one
            problem per lane, every operand and intermediate in VGPRs,
            64 P lanes per workgroup;
@@ -91,7 +94,7 @@ def feasible_packs(glass, nx, nu, scope="wave"):
     return [p for p in PACKS if glass.glass_riccati_placement_feasible(nx, nu, glass.SCOPES[scope], p) == 1]
 
 
-FUSED_SCOPE = {"fused": "wave", "fused_thread": "thread"}
+FUSED_SCOPE = {"fused": "wave", "fused_subwave": "subwave", "fused_thread": "thread"}
 
 
 def time_forms(glass, torch, nx, nu, batch, rounds=20, warmup=3, rng=None, device="cuda:0"):
@@ -166,7 +169,7 @@ def load(path=DEFAULT_SWEEP):
 
 
 def choose(nx, nu, batch, recs=None):
-    """Composition advisor: ("fused", pack), ("fused_thread", pack) or ("unfused", 0) from the
+    """Composition advisor: ("fused", pack), ("fused_subwave", pack), ("fused_thread", pack) or ("unfused", 0) from the
     measured records, at the nearest measured (nx, nu) (by order, then input
     count) and the nearest measured batch in log2 distance."""
     recs = recs if recs is not None else load()

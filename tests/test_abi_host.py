@@ -105,7 +105,14 @@ def test_riccati_and_gemm_ex_validation_paths(glass):
         for p in (1, 2, 4, 8):
             assert g.glass_riccati_placement_feasible(nx, nu, W, p) == g.glass_riccati_feasible(nx, nu, p)
         assert g.glass_riccati_placement_feasible(nx, nu, g.SCOPES["workgroup"], 1) == 0
-        assert g.glass_riccati_placement_feasible(nx, nu, g.SCOPES["subwave"], 1) == 0
+    # sub-wave scope up to nx = 16, nu = 8
+    SW = g.SCOPES["subwave"]
+    for nx, nu in ((1, 1), (4, 2), (12, 4), (14, 7), (16, 8)):
+        assert all(g.glass_riccati_placement_feasible(nx, nu, SW, p) == 1 for p in (1, 2, 4, 8)), (nx, nu)
+    for nx, nu in ((17, 1), (8, 9), (32, 8), (56, 8)):
+        assert g.glass_riccati_placement_feasible(nx, nu, SW, 1) == 0, (nx, nu)
+        assert g.glass_riccati_gain_batched(nx, nu, 3, FAKE, FAKE, FAKE, FAKE, FAKE, force=("subwave", 1),
+                                            stream=S) == g.ERR_INFEASIBLE_PLACEMENT
     assert g.glass_riccati_placement_feasible(4, 2, 17, 1) == g.ERR_INVALID_VALUE
     assert g.glass_riccati_placement_feasible(4, 2, T, 3) == g.ERR_INVALID_VALUE
     assert g.glass_riccati_placement_feasible(57, 1, T, 1) == g.ERR_UNSUPPORTED

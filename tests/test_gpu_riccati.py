@@ -90,6 +90,42 @@ def test_fused_gain_parity(env, nx, nu):
 THREAD_SIZES = [(1, 1), (1, 4), (2, 3), (3, 1), (4, 2), (5, 3), (6, 4), (7, 2), (8, 1), (8, 4)]
 
 
+SUBWAVE_SIZES = [(1, 1), (3, 2), (4, 2), (9, 1), (12, 4), (13, 5), (14, 7), (16, 1), (16, 8)]
+
+
+@pytest.mark.parametrize("nx,nu", SUBWAVE_SIZES)
+def test_fused_gain_subwave_parity(env, nx, nu):
+    """The sub-wave form (four problems per wavefront) at every pack, with
+    batches that leave partly filled wavefronts, NaN guard bands around K,
+    and indefinite problems among healthy ones in the same wavefronts."""
+    glass, torch = env
+    assert glass.glass_riccati_placement_feasible(nx, nu, glass.SCOPES["subwave"], 1) == 1
+    for batch in (1, 6, 67, 1000):
+        c = inputs.make_riccati(batch, nx, nu, seed=18)
+        bad = np.arange(1, batch, 5)
+        c["R"][bad] = -50.0 * np.eye(nu, dtype=np.float32)
+        K_ref, info_ref = oracle.riccati_gain(c["A"], c["B"], c["P"], c["R"])
+        assert (info_ref[bad] != 0).all() and (np.delete(info_ref, bad) == 0).all()
+        good = np.setdiff1d(np.arange(batch), bad)
+        ops = {k: dev(torch, c[k]) for k in ("A", "B", "P", "R")}
+        Kbuf = torch.full((batch * nu * nx + 8,), float("nan"), device="cuda:0")
+        K = Kbuf[4:4 + batch * nu * nx]
+        for pack in (1, 2, 4, 8):
+            print(f"riccati fused subwave nx={nx} nu={nu} batch={batch} P={pack}", flush=True)
+            K.fill_(float("nan"))
+            info = torch.full((batch,), -7, dtype=torch.int32, device="cuda:0")
+            st = glass.glass_riccati_gain_batched(nx, nu, batch, ops["A"], ops["B"], ops["P"], ops["R"], K, info,
+                                                  ("subwave", pack))
+            assert st == 0, st
+            torch.cuda.synchronize()
+            assert np.array_equal(info.cpu().numpy(), info_ref)
+            Kh = K.cpu().numpy().reshape(batch, nu, nx)
+            assert normwise(Kh[good], K_ref[good]).max() <= TOL
+            assert np.isnan(Kh[bad]).all()  # K is not written where info is nonzero
+            kb = Kbuf.cpu().numpy()
+            assert np.isnan(kb[:4]).all() and np.isnan(kb[4 + batch * nu * nx:]).all()
+
+
 @pytest.mark.parametrize("nx,nu", THREAD_SIZES)
 def test_fused_gain_thread_parity(env, nx, nu):
     """The thread-scope form (one problem per lane), at every pack, on
