@@ -22,9 +22,9 @@
 //                      is deterministic: equal classes keep index order);
 //   4. ragged_solve    one wavefront per work item of the class-sorted list
 //                      (64 problems of a thread-scope class, four at sub-wave
-//                      scope, or one problem), in two launches: the classes
-//                      above order 24 (the blocked routines need more
-//                      registers), then the rest at the smaller allocation.
+//                      scope, or one problem), every class in one launch, so
+//                      the small classes fill the slots that the blocked
+//                      classes' last round leaves idle.
 #include <atomic>
 #include <mutex>
 
@@ -280,19 +280,17 @@ GLASS_DEV void ragged_seg(float* A, float* B, const int64_t* offA, const int64_t
 // from an atomic counter in lane 0 compiled to a per-lane exit in which lanes
 // 1..63 never saw a new item and could not leave, so the launch covers the
 // list instead and hardware dispatch order provides the largest-first order.
-// BIG selects the classes of orders above 24 (blocked MFMA routines, which
-// need more registers) or the rest; the two instances are launched over the
-// same item range, the BIG one first, and each leaves the other's items.
-template <bool BIG>
 __global__ void __launch_bounds__(256, 3) ragged_solve(const int32_t* __restrict__ nvec,
                                                     const int32_t* __restrict__ rvec,
                                                     const int64_t* __restrict__ offA,
                                                     const int64_t* __restrict__ offB, float* A, float* B,
                                                     int32_t* info, const int32_t* __restrict__ perm,
                                                     const int32_t* __restrict__ meta, RaggedScopes scopes) {
-    // per wavefront: 8 rows of 64 (wave, orders <= 32), four 16 x 16 blocks
-    // (sub-wave) or the blocked routines' staging (orders above 24)
-    __shared__ float chunk[4][BIG ? kBlkRegionFloats : kRaggedSegFloats];
+    // per wavefront, the largest of: 8 rows of up to 24 (the row-per-lane wave
+    // path), the segments' L blocks (sub-wave) and the blocked routines'
+    // staging (orders above 24)
+    constexpr int kFloats = kBlkRegionFloats > kRaggedSegFloats ? kBlkRegionFloats : kRaggedSegFloats;
+    __shared__ float chunk[4][kFloats];
     const int lane = threadIdx.x & 63, w = wave_index();
     const int item = blockIdx.x * 4 + w;
     if (item >= meta[3 * kClasses]) return;
@@ -303,10 +301,10 @@ __global__ void __launch_bounds__(256, 3) ragged_solve(const int32_t* __restrict
         const int nit = items_of(scopes.s[c], c, cnt);
         if (cnt > 0 && item >= ib && item < ib + nit) k = c;
     }
-    if (BIG != (k >= kBigClass)) return;
+    const bool big = k >= kBigClass;
     const int rel = item - meta[2 * kClasses + k];
     const int cbase = meta[kClasses + k];
-    if (!BIG && scopes.s[k] == kScopeSubwave) {  // classes 0 to 2 only (checked by the caller)
+    if (!big && scopes.s[k] == kScopeSubwave) {  // classes 0 to 2 only (checked by the caller)
         const int seg = k <= 1 ? 16 : 32;
         const int q = rel * (64 / seg) + lane / seg;
         int e = -1, n = 0, r = 0;
@@ -325,7 +323,7 @@ __global__ void __launch_bounds__(256, 3) ragged_solve(const int32_t* __restrict
             ragged_seg<32, 24>(A, B, offA, offB, e, n, r, info, chunk[w], lane);
         return;
     }
-    if (!BIG && scopes.s[k] == GLASS_SCOPE_THREAD) {
+    if (!big && scopes.s[k] == GLASS_SCOPE_THREAD) {
         const int q = rel * 64 + lane;
         if (q < meta[k]) {
             const int e = perm[cbase + q];
@@ -348,7 +346,7 @@ __global__ void __launch_bounds__(256, 3) ragged_solve(const int32_t* __restrict
     float* Ag = A + uniform_i64(offA[e]);
     float* Bg = B + uniform_i64(offB[e]);
     float* buf = chunk[w];
-    if (BIG) {  // problem offsets are arbitrary: 4-byte stores
+    if (big) {  // problem offsets are arbitrary: 4-byte stores
         const int inf = k == 3   ? blk_one<2, 1, false>(Ag, Bg, n, r, 0, false, buf, lane)
                         : k <= 5 ? blk_one<3, 1, false>(Ag, Bg, n, r, 0, false, buf, lane)
                                  : blk_one<4, 1, false>(Ag, Bg, n, r, 0, false, buf, lane);
@@ -423,10 +421,8 @@ int launch_posv_ragged(int count, const int32_t* n, const int32_t* nrhs, const i
     hipLaunchKernelGGL(ragged_scan, dim3(1), dim3(kScanThreads), 0, st, nchunks, hist, meta, scopes);
     hipLaunchKernelGGL(ragged_scatter, dim3(nchunks), dim3(256), 0, st, count, n, hist, perm);
     // work items never outnumber problems: ceil(count / 4) four-wave blocks cover the list
-    hipLaunchKernelGGL(ragged_solve<true>, dim3((count + 3) / 4), dim3(256), 0, st, n, nrhs, offA, offB, A, B, info,
-                       perm, meta, scopes);
-    hipLaunchKernelGGL(ragged_solve<false>, dim3((count + 3) / 4), dim3(256), 0, st, n, nrhs, offA, offB, A, B, info,
-                       perm, meta, scopes);
+    hipLaunchKernelGGL(ragged_solve, dim3((count + 3) / 4), dim3(256), 0, st, n, nrhs, offA, offB, A, B, info, perm,
+                       meta, scopes);
     return (int)hipGetLastError();
 }
 
