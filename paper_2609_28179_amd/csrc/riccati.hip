@@ -2,8 +2,9 @@
 // (Sec. III-B names it as a fused composition of GEMM and solve primitives;
 // Sec. IV-E measures fused against a chain of separate launches).
 //
-// One wavefront per problem (wave scope, P problems per workgroup), every
-// intermediate on chip, in one of two forms.
+// Every intermediate stays on chip.  At wave scope (one wavefront per
+// problem, P problems per workgroup) in one of two forms, riccati_wave and
+// riccati_mfma; at sub-wave scope riccati_seg; at thread scope riccati_thread.
 //
 // riccati_wave (LDS-staged, nx < kRiccatiMfmaMinNx):
 //   1. P (nx x nx) and B (nx x nu) are staged into LDS with coalesced loads,
@@ -44,8 +45,10 @@
 //   T_j  = sum_i PB_i^T A_ij              PB_i's registers are the T layout of PB_i^T
 //                                         (B^T P = (P B)^T: P is symmetric)
 //   K_j  = L^{-T} L^{-1} T_j              S = L L^T factored as a diagonal block
-// S's padded diagonal (orders nu..15) is the identity, so the factorization
-// and the solve run on a full 16 x 16 block.
+// S's padded diagonal (orders nu..15) is the identity, so the solve runs on a
+// full 16 x 16 block while the factorization and the inverse stop after nu
+// rounded up to 4, 8 or 16 pivots (the rest would find unit pivots and zero
+// coefficients).
 #include <type_traits>
 
 #include "device_common.hpp"
