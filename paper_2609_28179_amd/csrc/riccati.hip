@@ -357,14 +357,18 @@ __global__ void __launch_bounds__(512) riccati_seg(int nx, int nu, int batch, co
         brow[j] = okb ? bv : 0.f;
         rrow[j] = okr ? rv : 0.f;
     }
-    // row i of P B
+    // row i of P B; the broadcasts are folded into the FMAs (one DPP op each,
+    // so no broadcast value is held), after the wait states their sources need
     float pb[NUB];
 #pragma unroll
-    for (int j = 0; j < NUB; ++j) pb[j] = 0.f;
+    for (int j = 0; j < NUB; ++j) {
+        pb[j] = 0.f;
+        asm volatile("s_nop 1" : "+v"(brow[j]));
+    }
     static_for<0, 16>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
 #pragma unroll
-        for (int j = 0; j < NUB; ++j) pb[j] = fmaf(prow[k], row_bcast<k>(brow[j]), pb[j]);
+        for (int j = 0; j < NUB; ++j) fmac_bcast<k>(pb[j], brow[j], prow[k]);
     });
     // S = R + B^T P B: lane i contributes B_i PB_i^T; row i of S to lane i
     // (identity rows from nu to NUB, zero rows past NUB)
@@ -387,11 +391,14 @@ __global__ void __launch_bounds__(512) riccati_seg(int nx, int nu, int batch, co
     // column i of T = (P B)^T A
     float t[NUB];
 #pragma unroll
-    for (int a = 0; a < NUB; ++a) t[a] = 0.f;
+    for (int a = 0; a < NUB; ++a) {
+        t[a] = 0.f;
+        asm volatile("s_nop 1" : "+v"(pb[a]));
+    }
     static_for<0, 16>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
 #pragma unroll
-        for (int a = 0; a < NUB; ++a) t[a] = fmaf(row_bcast<k>(pb[a]), acol[k], t[a]);
+        for (int a = 0; a < NUB; ++a) fmac_bcast<k>(t[a], pb[a], acol[k]);
     });
     // L's strictly lower entries and 1 / L_aa as broadcasts, then L L^T k = t
     float lo[NUB][NUB], inv[NUB];
