@@ -198,9 +198,9 @@ glass_status_t glass_posv_adjoint_batched(int n, int nrhs, int batch, const floa
 /* Factor-and-solve of a ragged batch: `count` SPD systems of mixed order and
  * right-hand-side count in one launch sequence (problem packing of Sec. IV-C
  * extended to mixed sizes; no host synchronisation, so the call can be
- * captured in a HIP graph): three small planning kernels and two solve
- * launches with a wavefront per work item (the classes of orders above 24
- * first, then the rest).  All arrays are DEVICE arrays:
+ * captured in a HIP graph): three small planning kernels and one solve
+ * launch with a wavefront per work item (the classes of orders above 24
+ * first in the item list).  All arrays are DEVICE arrays:
  *   n[count], nrhs[count]  int32, each in 1..64 (a problem outside that range
  *                          gets info = -1 and is not touched);
  *   offA[count], offB[count] int64 element offsets of problem i's A (n x n,
