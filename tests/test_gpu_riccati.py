@@ -258,3 +258,31 @@ def test_graph_replays_of_both_forms(env):
         gu.replay()
         torch.cuda.synchronize()
         assert torch.equal(K_f, ef) and torch.equal(K_u, eu), rep
+
+
+@pytest.mark.parametrize("scope,nx,nu", [("thread", 4, 2), ("subwave", 12, 4), ("subwave", 14, 7)])
+def test_graph_replays_of_thread_and_subwave_forms(env, scope, nx, nu):
+    """The thread and sub-wave forms captured in a graph: every replay, with
+    the output wiped between them, equals the eager call bit for bit."""
+    glass, torch = env
+    from paper_2609_28179_amd import riccati
+    batch = 501
+    c = {k: dev(torch, v) for k, v in inputs.make_riccati(batch, nx, nu, seed=19).items()}
+    K = torch.empty((batch, nu, nx), device="cuda:0")
+    info = torch.empty((batch,), dtype=torch.int32, device="cuda:0")
+    print(f"riccati graph {scope} nx={nx} nu={nu} batch={batch}", flush=True)
+    riccati.fused(glass, c["A"], c["B"], c["P"], c["R"], K, info, pack=2, scope=scope)
+    torch.cuda.synchronize()
+    eK, ei = K.clone(), info.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        riccati.fused(glass, c["A"], c["B"], c["P"], c["R"], K, info, pack=2, scope=scope)
+    for rep in range(3):
+        K.fill_(float("nan"))
+        info.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(K, eK) and torch.equal(info, ei), rep
+    K_ref, _ = oracle.riccati_gain(*(c[k].cpu().numpy() for k in ("A", "B", "P", "R")))
+    assert normwise(eK.cpu().numpy(), K_ref).max() <= TOL
