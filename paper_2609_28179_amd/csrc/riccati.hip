@@ -344,7 +344,7 @@ __global__ void __launch_bounds__(512) riccati_seg(int nx, int nu, int batch, co
 #pragma unroll
     for (int k = 0; k < 16; ++k) {  // unconditional loads (entry 0 for the rest), so that all issue at once
         const bool ok = act && row && k < nx;
-        const float pv = Pp[ok ? i * nx + k : 0];
+        const float pv = Pp[ok ? k * nx + i : 0];  // P symmetric: row i read as column i (coalesced)
         const float av = Ap[ok ? k * nx + i : 0];
         prow[k] = ok ? pv : 0.f;
         acol[k] = ok ? av : 0.f;
