@@ -76,19 +76,30 @@ def disassemble(co_path: str) -> str:
     return r.stdout
 
 
-def kernel_vgprs(co_path: str) -> dict[str, int]:
-    """Kernel symbol -> .vgpr_count from the code object's metadata note."""
+def kernel_meta(co_path: str) -> dict[str, dict[str, int]]:
+    """Kernel symbol -> its integer metadata fields (.vgpr_count,
+    .private_segment_fixed_size, .vgpr_spill_count, ...) from the code
+    object's metadata note."""
     r = subprocess.run([os.path.join(LLVM, "llvm-readelf"), "--notes", co_path],
                        check=True, capture_output=True, text=True)
-    out, name = {}, None
+    blocks, cur = [], {}
     for line in r.stdout.splitlines():
-        m = re.match(r"\s+\.name:\s+(\S+)", line)
+        if re.match(r"\s+- \.", line):  # a new kernel's entry
+            cur = {}
+            blocks.append(cur)
+        m = re.match(r"\s+-?\s*\.([a-z_]+):\s+(\S+)", line)
         if m:
-            name = m.group(1)
-        m = re.match(r"\s+\.vgpr_count:\s+(\d+)", line)
-        if m and name:
-            out[name] = int(m.group(1))
+            cur[m.group(1)] = m.group(2)
+    out = {}
+    for b in blocks:
+        if "name" in b and "vgpr_count" in b:
+            out[b["name"]] = {k: int(v) for k, v in b.items() if v.lstrip("-").isdigit()}
     return out
+
+
+def kernel_vgprs(co_path: str) -> dict[str, int]:
+    """Kernel symbol -> .vgpr_count."""
+    return {k: v["vgpr_count"] for k, v in kernel_meta(co_path).items()}
 
 
 def parse(text: str) -> list[dict]:
@@ -250,11 +261,11 @@ def check(funcs: list[dict], mfma_dpp_need: int | None = None, mfma_search: int 
     return {"violations": viol, "counts": counts, "mfma_valu_min": mfma_min}
 
 
-def scan_library(so_path: str) -> tuple[list[dict], dict[str, int]]:
-    """Parsed functions and kernel VGPR counts of every gfx950 code object."""
-    funcs, vgprs = [], {}
+def scan_library(so_path: str) -> tuple[list[dict], dict[str, dict[str, int]]]:
+    """Parsed functions and kernel metadata of every gfx950 code object."""
+    funcs, meta = [], {}
     with tempfile.TemporaryDirectory() as tmp:
         for co in code_objects(so_path, tmp):
             funcs += parse(disassemble(co))
-            vgprs.update(kernel_vgprs(co))
-    return funcs, vgprs
+            meta.update(kernel_meta(co))
+    return funcs, meta

@@ -21,8 +21,8 @@ def scanned():
     if not os.path.exists(os.path.join(hz.LLVM, "llvm-objdump")):
         pytest.skip("ROCm LLVM tools not installed")
     assert os.path.exists(LIB), "libglass.so is not built"
-    funcs, vgprs = hz.scan_library(LIB)
-    return funcs, vgprs, hz.check(funcs)
+    funcs, meta = hz.scan_library(LIB)
+    return funcs, meta, hz.check(funcs)
 
 
 def _listing(body: str, name: str = "k") -> list[dict]:
@@ -162,8 +162,19 @@ def test_no_wait_state_hazards(scanned):
 def test_blocked_potrf_occupancy_cap(scanned):
     # the whole-tile POTRF kernels at three and four tiles per side reserve
     # VGPRs up to v103: four waves per SIMD (512 VGPRs / 104 rounded to 8)
-    _, vgprs, _ = scanned
-    caps = {k: v for k, v in vgprs.items() if "8chol_blkILi3ELi0ELb1E" in k or "8chol_blkILi4ELi0ELb1E" in k}
-    assert len(caps) == 2, sorted(vgprs)[:5]
+    _, meta, _ = scanned
+    caps = {k: m["vgpr_count"] for k, m in meta.items()
+            if "8chol_blkILi3ELi0ELb1E" in k or "8chol_blkILi4ELi0ELb1E" in k}
+    assert len(caps) == 2, sorted(meta)[:5]
     for k, v in caps.items():
         assert 512 // (-(-v // 8) * 8) == 4, (k, v)
+
+
+def test_no_kernel_spills_to_scratch(scanned):
+    # a VGPR spill or a private segment is per-lane scratch in HBM on every
+    # access of the spilled value: none of the kernels needs one
+    _, meta, _ = scanned
+    assert len(meta) > 400
+    spill = {k: (m.get("private_segment_fixed_size", 0), m.get("vgpr_spill_count", 0))
+             for k, m in meta.items() if m.get("private_segment_fixed_size", 0) or m.get("vgpr_spill_count", 0)}
+    assert spill == {}, sorted(spill.items())[:5]
