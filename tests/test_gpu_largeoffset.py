@@ -189,3 +189,39 @@ def test_ragged_past_2g_elements():
         assert (L[iu] == 0).all() and not np.signbit(L[iu]).any(), (i, n)
     del A, B
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("scope,nx,nu", [("thread", 4, 2), ("subwave", 16, 4), ("wave", 32, 8)])
+def test_riccati_past_2g_elements(scope, nx, nu):
+    """The fused LQR gain with P and A holding 2^31 + 3 problems' worth of
+    floats, in each of its scopes (thread, sub-wave, and the matrix-core
+    wavefront form): P = 2 I (exactly symmetric), R = I, A and B uniform, so
+    S = I + 2 B^T B is positive definite; sampled problems against the oracle."""
+    import torch
+    from paper_2609_28179_amd import glass
+    dev = torch.device("cuda:0")
+    batch = big_batch(nx)
+    print(f"riccati {scope} nx={nx} nu={nu} batch={batch}", flush=True)
+    g = inputs.torch_generator(dev, 70_200 + nx)
+    A = inputs.uniform_torch(g, (batch, nx, nx), dev)
+    B = inputs.uniform_torch(g, (batch, nx, nu), dev) * 0.5
+    P = torch.zeros((batch, nx, nx), dtype=torch.float32, device=dev)
+    P.diagonal(dim1=1, dim2=2).fill_(2.0)
+    R = torch.zeros((batch, nu, nu), dtype=torch.float32, device=dev)
+    R.diagonal(dim1=1, dim2=2).fill_(1.0)
+    K = torch.full((batch, nu, nx), float("nan"), dtype=torch.float32, device=dev)
+    info = torch.full((batch,), -7, dtype=torch.int32, device=dev)
+    assert glass.glass_riccati_gain_batched(nx, nu, batch, A, B, P, R, K, info, (scope, 1)) == 0
+    torch.cuda.synchronize()
+    info_h = info.cpu().numpy()
+    badi = np.nonzero(info_h != 0)[0]
+    assert badi.size == 0, (badi[:8], info_h[badi[:8]])
+    idx = sample_index(batch, nx)
+    ti = torch.from_numpy(idx).to(dev)
+    h = lambda t: t.index_select(0, ti).cpu().numpy()
+    K_ref, info_ref = oracle.riccati_gain(h(A), h(B), h(P), h(R))
+    assert (info_ref == 0).all()
+    err = normwise(h(K), K_ref)
+    del A, B, P, R, K, info
+    torch.cuda.empty_cache()
+    assert err.max() <= TOL, f"max normwise error {err.max():.3e} at problems {idx[err > TOL]}"
