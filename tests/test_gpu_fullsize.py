@@ -55,7 +55,7 @@ def test_fullsize_table_placement(op, n, batch):
             L_ref, X_ref, info_ref = oracle.posv(A0, h(before["B"]))
             err = np.maximum(normwise(np.tril(L), L_ref), normwise(h(bufs["B"]), X_ref))
         assert (info_ref == 0).all()
-        assert int(bufs["info"].abs().max()) == 0, "info must be 0 for every problem"
+        assert (bufs["info"].cpu().numpy() == 0).all(), "info must be 0 for every problem"
         up = torch.triu(bufs["A"], 1)
         assert int(torch.count_nonzero(up)) == 0 and not bool(torch.signbit(up).any()), "strict upper must be +0"
     elif op == "potrs":

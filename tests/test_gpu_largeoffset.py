@@ -90,7 +90,7 @@ def test_past_2g_elements(op, n):
             err = np.maximum(normwise(np.tril(h(A)), L_ref), normwise(h(B), X_ref))
             del B
         assert (info_ref == 0).all()
-        assert int(info.abs().max()) == 0, "info must be 0 for every problem"
+        assert (info.cpu().numpy() == 0).all(), "info must be 0 for every problem"
         up = torch.triu(A.index_select(0, ti), 1)
         assert int(torch.count_nonzero(up)) == 0 and not bool(torch.signbit(up).any()), "strict upper must be +0"
         del A, info
