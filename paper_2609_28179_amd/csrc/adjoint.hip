@@ -38,18 +38,43 @@ GLASS_DEV float sym_pair(float acc, float p, float q, float r, float s) {
     return acc + t;
 }
 
-// One right-hand side, N % 4 == 0, every operand 16-byte aligned: the same
-// arithmetic as adjoint_thread with no LDS.  Each lane loads the 16-byte
-// pieces of its own problem's rows at or left of the diagonal, x and g, all
-// issued before any is used, and stores dB and the rows of dA straight to
-// memory.  (dB may be G: a lane reads its g before it writes its dB.)  Entry
-// (i, j) of dA is formed here as b_i x_j + x_i b_j for every j, which is the
-// staged kernel's value of the (j, i) pair with the sum's terms swapped, so
-// the result is the same bit for bit.
+// One right-hand side, every operand 16-byte aligned: the same arithmetic as
+// adjoint_thread with no LDS.  Each lane loads its own problem's rows at or
+// left of the diagonal, x and g, all issued before any is used, and stores
+// dB and the rows of dA straight to memory, in pieces of AL floats: 4, 2 or 1
+// as N allows (every row of every problem starts at a multiple of AL floats
+// from the aligned base).  (dB may be G: a lane reads its g before it writes
+// its dB.)  Entry (i, j) of dA is formed here as b_i x_j + x_i b_j for every
+// j, which is the staged kernel's value of the (j, i) pair with the sum's
+// terms swapped, so the result is the same bit for bit.
+template <int AL>
+GLASS_DEV void piece_get(float* v, const float* p) {
+    if constexpr (AL == 4) {
+        const f4_t x = *reinterpret_cast<const f4_t*>(p);
+        v[0] = x[0], v[1] = x[1], v[2] = x[2], v[3] = x[3];
+    } else if constexpr (AL == 2) {
+        const float2 x = *reinterpret_cast<const float2*>(p);
+        v[0] = x.x, v[1] = x.y;
+    } else {
+        v[0] = *p;
+    }
+}
+
+template <int AL>
+GLASS_DEV void piece_put(float* p, const float* v) {
+    if constexpr (AL == 4)
+        *reinterpret_cast<f4_t*>(p) = f4_t{v[0], v[1], v[2], v[3]};
+    else if constexpr (AL == 2)
+        *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
+    else
+        *p = v[0];
+}
+
 template <int N>
 __global__ void __launch_bounds__(512) adjoint_thread1(int batch, const float* __restrict__ L,
                                                        const float* __restrict__ X, const float* G, float* dB,
                                                        float* __restrict__ dA) {
+    constexpr int AL = N % 4 == 0 ? 4 : N % 2 == 0 ? 2 : 1;
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= batch) return;
     const float* Lp = L + p * (N * N);
@@ -57,22 +82,18 @@ __global__ void __launch_bounds__(512) adjoint_thread1(int batch, const float* _
 #pragma unroll
     for (int i = 0; i < N; ++i)
 #pragma unroll
-        for (int t = 0; t <= i / 4; ++t) {
-            const f4_t v = *reinterpret_cast<const f4_t*>(Lp + i * N + 4 * t);
+        for (int t = 0; t <= i / AL; ++t) {
+            float v[AL];
+            piece_get<AL>(v, Lp + i * N + AL * t);
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (4 * t + e <= i) a[TI(i, 4 * t + e)] = v[e];
+            for (int e = 0; e < AL; ++e)
+                if (AL * t + e <= i) a[TI(i, AL * t + e)] = v[e];
         }
     float x[N], y[N];
 #pragma unroll
-    for (int t = 0; t < N / 4; ++t) {
-        const f4_t xv = *reinterpret_cast<const f4_t*>(X + p * N + 4 * t);
-        const f4_t gv = *reinterpret_cast<const f4_t*>(G + p * N + 4 * t);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            x[4 * t + e] = xv[e];
-            y[4 * t + e] = gv[e];
-        }
+    for (int t = 0; t < N / AL; ++t) {
+        piece_get<AL>(x + AL * t, X + p * N + AL * t);
+        piece_get<AL>(y + AL * t, G + p * N + AL * t);
     }
     float dinv[N];
 #pragma unroll
@@ -80,17 +101,16 @@ __global__ void __launch_bounds__(512) adjoint_thread1(int batch, const float* _
     tri_fwd<N>(a, dinv, y);
     tri_bwd<N>(a, dinv, y);
 #pragma unroll
-    for (int t = 0; t < N / 4; ++t)
-        *reinterpret_cast<f4_t*>(dB + p * N + 4 * t) = f4_t{y[4 * t], y[4 * t + 1], y[4 * t + 2], y[4 * t + 3]};
+    for (int t = 0; t < N / AL; ++t) piece_put<AL>(dB + p * N + AL * t, y + AL * t);
     float* Ap = dA + p * (N * N);
 #pragma unroll
     for (int i = 0; i < N; ++i)
 #pragma unroll
-        for (int t = 0; t < N / 4; ++t) {
-            f4_t o;
+        for (int t = 0; t < N / AL; ++t) {
+            float o[AL];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) o[e] = -0.5f * sym_pair(0.f, y[i], x[4 * t + e], x[i], y[4 * t + e]);
-            *reinterpret_cast<f4_t*>(Ap + i * N + 4 * t) = o;
+            for (int e = 0; e < AL; ++e) o[e] = -0.5f * sym_pair(0.f, y[i], x[AL * t + e], x[i], y[AL * t + e]);
+            piece_put<AL>(Ap + i * N + AL * t, o);
         }
 }
 
@@ -275,11 +295,12 @@ int launch_posv_adjoint(const Shape& sh, const Geometry& g, int batch, const flo
     dim3 grid((unsigned)g.grid), block(g.threads);
     if (g.scope == GLASS_SCOPE_THREAD) {
         auto al16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
-        if (r == 1 && (n & 3) == 0 && al16(L) && al16(X) && al16(G) && al16(dB) && al16(dA)) {
+        if (r == 1 && al16(L) && al16(X) && al16(G) && al16(dB) && al16(dA)) {
             switch (n) {
 #define CASE1(N) \
     case N: hipLaunchKernelGGL(adjoint_thread1<N>, grid, block, 0, st, batch, L, X, G, dB, dA); return (int)hipGetLastError();
-                CASE1(4) CASE1(8) CASE1(12) CASE1(16)
+                CASE1(1) CASE1(2) CASE1(3) CASE1(4) CASE1(5) CASE1(6) CASE1(7) CASE1(8) CASE1(9) CASE1(10) CASE1(11)
+                CASE1(12) CASE1(13) CASE1(14) CASE1(15) CASE1(16)
 #undef CASE1
             }
         }

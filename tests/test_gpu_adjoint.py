@@ -87,7 +87,7 @@ def test_adjoint_config3_and_finite_differences(env):
             assert abs(fd - an) <= 1e-2 * max(1.0, abs(an)), (q, i, j, fd, an)
 
 
-@pytest.mark.parametrize("n", [4, 8, 12, 16])
+@pytest.mark.parametrize("n", [1, 3, 4, 5, 6, 7, 8, 12, 15, 16])
 def test_adjoint_thread_direct_form_bit_identical(env, n):
     """One right-hand side at thread scope: aligned operands take the direct
     form (no LDS), operands one float off alignment the staged form; both
